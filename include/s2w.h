@@ -1,0 +1,144 @@
+/*
+ * s2w — directional scale-discretised wavelet transform on the sphere S^2
+ * (and, through radial shells, the ball B^3) on McEwen-Wiaux sampling,
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Price, Polanska, Whitney & McEwen, "Differentiable and accelerated
+ * directional wavelet transforms on the sphere and ball".
+ *   analysis   W^{Psi^j} = D_j^{-1} N Psi^j Y f          (Section 4.1, eq:analysis_s2)
+ *              W^Phi = Y^{-1} Phi Y f                    (Section 4.1)
+ *   synthesis  f = Y^{-1}(Phi Y W^Phi + sum_j Psi^{j dagger} D_j W^{Psi^j})   (eq:synthesis_s2)
+ *   filters    Appendix A (kappa, eta, zeta, Psi, Phi); multiresolution band
+ *              limits per scale (Section 3.3).
+ *
+ * Conventions (all arrays row-major, FP64 unless stated):
+ *   map f              [B][L][2L-1]     theta_b = pi(2b+1)/(2L-1), phi_a = 2 pi a/(2L-1)
+ *   harmonic flm       [B][L][2L-1]     complex interleaved (re, im), index m+L-1 ("lm" layout
+ *                                       of Algorithm 1), zero where |m| > l
+ *   wavelet coeffs     scales j = J0..J packed one after another; scale k = j-J0 occupies
+ *                      [B][2N_k-1][L_k][2L_k-1] (gamma, beta, alpha) starting at element
+ *                      wav_offset[k]; FP64 for S2W_FP64 plans, FP32 for S2W_MIXED plans
+ *   scaling coeffs     [B][L_phi][2L_phi-1]
+ *   per-scale limits   L_k = min(ceil(lambda^(j+1)), L), N_k = min(N, L_k), L_phi = ceil(lambda^J0),
+ *                      J = smallest integer with lambda^J >= L
+ *
+ * Ownership and asynchrony: the caller owns every input/output device buffer.
+ * The plan owns its tables and workspace, all allocated in s2w_plan_create; the
+ * transform entry points allocate nothing, never synchronise, and enqueue their
+ * work on `stream` (a hipStream_t, or NULL for the default stream).  Argument
+ * errors are reported synchronously; device faults surface as S2W_EHIP at a later
+ * call.  Calls never abort: failures return a negative status and set a
+ * thread-local message readable with s2w_last_error().  A plan may be used by one
+ * stream at a time (its workspace is shared by all calls on the plan).
+ */
+#ifndef S2W_H
+#define S2W_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    S2W_OK = 0,
+    S2W_EINVAL = -1,        /* invalid argument (sizes, null pointers, plan) */
+    S2W_ENOMEM = -2,        /* device or host allocation failed at plan creation */
+    S2W_EHIP = -3,          /* HIP runtime error */
+    S2W_EUNSUPPORTED = -4,  /* valid but unsupported configuration */
+    S2W_ESTATE = -5         /* plan destroyed or used inconsistently */
+} s2w_status;
+
+typedef enum {
+    S2W_FP64 = 0,           /* FP64 end to end */
+    S2W_MIXED = 1           /* FP64 Wigner-d recursion and scale sums; FP32 coefficients */
+} s2w_precision;
+
+typedef struct s2w_plan_s *s2w_plan;
+
+/* Create a plan for band limit L >= 2, azimuthal band limit 1 <= N <= L, dilation
+ * lambda > 1, lowest wavelet scale 0 <= J0 <= J, batch >= 1 maps per call, on HIP
+ * device `device`.  flags must be 0.  Computes filters (Appendix A), the exact MW
+ * theta-quadrature matrices, recursion tables and allocates all workspace. */
+s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, int batch,
+                           s2w_precision precision, int device, unsigned flags);
+
+/* Release a plan (NULL is accepted). */
+s2w_status s2w_plan_destroy(s2w_plan plan);
+
+/* Query the packed layout.  Any pointer may be NULL.  Arrays Lk, Nk have
+ * nscales = J - J0 + 1 entries, wav_offset has nscales + 1 (the last is the total
+ * element count per call, all maps included). */
+s2w_status s2w_plan_layout(s2w_plan plan, int *nscales, int *J0, int *Lk, int *Nk,
+                           int64_t *wav_offset, int *L_phi);
+
+/* Wavelet analysis (Algorithm 1, analysis): real maps f -> wavelet and scaling
+ * coefficients.  f: device [B][L][2L-1]; wav: device, packed (see above);
+ * scal: device [B][L_phi][2L_phi-1]. */
+s2w_status s2w_analysis(s2w_plan plan, const double *f, void *wav, double *scal, void *stream);
+
+/* Wavelet synthesis (Algorithm 1, synthesis): coefficients -> real maps. */
+s2w_status s2w_synthesis(s2w_plan plan, const void *wav, const double *scal, double *f, void *stream);
+
+/* Transpose of the analysis map under the real inner product of the sample arrays
+ * (the gradient of a loss with respect to f, given its gradient with respect to the
+ * coefficients).  It is not the synthesis: MW sampling oversamples, so A^T A != I. */
+s2w_status s2w_analysis_adjoint(s2w_plan plan, const void *gwav, const double *gscal, double *gf,
+                                void *stream);
+
+/* Transpose of the synthesis map (the gradient through a synthesis). */
+s2w_status s2w_synthesis_adjoint(s2w_plan plan, const double *gf, void *gwav, double *gscal,
+                                 void *stream);
+
+/* Spin-0 spherical-harmonic transforms on the plan's grid (Section 2.1,
+ * eq:fswsh / eq:iswsh; the S^2 case of the Wigner transforms).  flm is complex
+ * interleaved [B][L][2L-1].  Inputs to s2w_sht_inverse must describe real maps
+ * (f_{l,-m} = (-1)^m conj(f_lm)); only m >= 0 entries are read. */
+s2w_status s2w_sht_forward(s2w_plan plan, const double *f, double *flm, void *stream);
+s2w_status s2w_sht_inverse(s2w_plan plan, const double *flm, double *f, void *stream);
+
+/* Kernel timing (for measurement).  s2w_plan_profile(plan, capacity) with capacity > 0
+ * creates `capacity` pairs of HIP events and from then on records one pair around
+ * every kernel launch of the transform entry points, on the stream of the call, together
+ * with the launch's algorithmic floating-point operation count (the per-unit figures
+ * are: 6 flop per Wigner-d recursion step and 4 per complex-by-real multiply-add of a
+ * contraction; 5 n log2 n per length-n complex DFT; 2 per multiply-add of a dense product);
+ * capacity 0 stops recording and releases the events.  Not to be used under graph capture.
+ * s2w_plan_profile_read synchronises the device, then reports per kernel name (up to `max`
+ * names, each at most 31 characters, written to names + 32*i): total milliseconds, launch
+ * count and total algorithmic flop since profiling started, and clears the record.
+ * Launches beyond the capacity are not recorded (dropped reports their number). */
+s2w_status s2w_plan_profile(s2w_plan plan, int capacity);
+s2w_status s2w_plan_profile_read(s2w_plan plan, int max, char *names, double *total_ms,
+                                 int64_t *launches, double *flop, int *count, int64_t *dropped);
+
+/* Message for the last failure on the calling thread. */
+const char *s2w_last_error(void);
+
+/* ---- host-only helpers (no device work; used to test the plan arithmetic) ---- */
+
+/* Per-scale band limits for (L, N, lambda, J0).  Lk, Nk need room for J - J0 + 1 entries
+ * (J <= 64). */
+s2w_status s2w_host_scales(int L, int N, double lambda, int J0, int *nscales, int *Lk, int *Nk,
+                           int *L_phi);
+
+/* Wavelet filters Psi^j_ln (complex interleaved, [nscales][L][2N-1], index n+N-1) and
+ * scaling filter Phi_l0 ([L]) from Appendix A. */
+s2w_status s2w_host_filters(int L, int N, double lambda, int J0, double *psi, double *phi);
+
+/* Exact MW theta-quadrature matrix T_sigma ([L][L], row-major): for F of band limit L
+ * with parity F(2pi - t) = sigma F(t) and any d of band limit L with the same parity,
+ * int_0^pi F d sin t dt = sum_b d(theta_b) (T_sigma F)(theta_b). sigma = +1 or -1. */
+s2w_status s2w_host_theta_matrix(int L, int sigma, double *T);
+
+/* Wigner d^l_mn(theta_b) for l = 0..L-1 on the MW grid of band limit L, computed on the
+ * host by the same scaled, log-rescaled three-term recursion the device uses
+ * (out: [L][L] as out[l*L + b]; zero for l < max(|m|,|n|)).  For tests of the
+ * recursion tables. */
+s2w_status s2w_host_wigner_d(int L, int m, int n, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* S2W_H */

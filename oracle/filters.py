@@ -5,6 +5,7 @@ Paper Appendix A:
   s_lam(t) = s(2 lam/(lam-1) (t - 1/lam) - 1)           (A.1, support [1/lam, 1])
   k_lam(t) = int_t^1 s_lam^2(t')/t' dt' / int_{1/lam}^1 s_lam^2(t')/t' dt'   (A.1)
   kappa_lam(t) = sqrt(k_lam(t/lam) - k_lam(t)),  eta_lam(t) = sqrt(k_lam(t))  (A.1)
+      (the difference is evaluated as one integral over [t/lam, t]; see kappa2_lam)
   zeta_ln = xi mu sqrt(2^{-q} C(q, (q-n)/2)), xi = 1 (N-1 even) else i,
             mu = [1 - (-1)^{N+n}]/2, q = min(N-1, l - [1 + (-1)^{N+l}]/2)   (A.2)
   Psi^j_ln = sqrt((2l+1)/(8 pi^2)) kappa^j(l) zeta_ln                      (A.4)
@@ -54,9 +55,22 @@ def k_lam(t: float, lam: float) -> float:
     return num / _k_den(lam)
 
 
+@lru_cache(maxsize=None)
+def kappa2_lam(t: float, lam: float) -> float:
+    """kappa_lam(t)^2 = k_lam(t/lam) - k_lam(t).  Both terms are integrals of the
+    same integrand s_lam^2/t' from their argument to 1, so the difference is the
+    integral over [t/lam, t] (clipped to the support [1/lam, 1]); evaluating it
+    that way avoids the cancellation of two numbers close to 1."""
+    a, b = max(t / lam, 1.0 / lam), min(t, 1.0)
+    if b <= a:
+        return 0.0
+    num = quad(lambda x: s_lam(x, lam) ** 2 / x, a, b, epsabs=0.0, epsrel=2e-14, limit=400)[0]
+    return num / _k_den(lam)
+
+
 def kappa(j: int, l: int, lam: float) -> float:
     t = l / lam ** j
-    return math.sqrt(max(k_lam(t / lam, lam) - k_lam(t, lam), 0.0))
+    return math.sqrt(kappa2_lam(t, lam))
 
 
 def eta(l: int, lam: float, J0: int) -> float:

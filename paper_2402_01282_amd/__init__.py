@@ -1,0 +1,281 @@
+"""Directional scale-discretised wavelet transform on the sphere for MI355X.
+
+Thin Python binding over the C-ABI library libs2w.so (declared in
+include/s2w.h).  Every step of the transform runs in the library's HIP
+kernels; this module only marshals pointers, sizes and streams.  PyTorch
+provides device memory and the current stream.
+
+The library must be built (``python -m paper_2402_01282_amd._build`` or
+``__graft_entry__.build()``); importing the binding without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libs2w.so")
+
+S2W_FP64 = 0
+S2W_MIXED = 1
+
+_STATUS = {0: "S2W_OK", -1: "S2W_EINVAL", -2: "S2W_ENOMEM", -3: "S2W_EHIP",
+           -4: "S2W_EUNSUPPORTED", -5: "S2W_ESTATE"}
+
+
+class S2WError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                          "(python -m paper_2402_01282_amd._build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    sigs = {
+        "s2w_plan_create": [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint],
+        "s2w_plan_destroy": [vp],
+        "s2w_plan_layout": [vp, ip, ip, ip, ip, i64p, ip],
+        "s2w_analysis": [vp, vp, vp, vp, vp],
+        "s2w_synthesis": [vp, vp, vp, vp, vp],
+        "s2w_analysis_adjoint": [vp, vp, vp, vp, vp],
+        "s2w_synthesis_adjoint": [vp, vp, vp, vp, vp],
+        "s2w_sht_forward": [vp, vp, vp, vp],
+        "s2w_sht_inverse": [vp, vp, vp, vp],
+        "s2w_plan_profile": [vp, ctypes.c_int],
+        "s2w_plan_profile_read": [vp, ctypes.c_int, ctypes.c_char_p, dp, i64p, dp, ip, i64p],
+        "s2w_host_scales": [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ip, ip, ip, ip],
+        "s2w_host_filters": [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp],
+        "s2w_host_theta_matrix": [ctypes.c_int, ctypes.c_int, dp],
+        "s2w_host_wigner_d": [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.s2w_last_error.argtypes = []
+    lib.s2w_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+# every symbol the header declares (checked by the tests)
+EXPORTS = ["s2w_plan_create", "s2w_plan_destroy", "s2w_plan_layout", "s2w_analysis", "s2w_synthesis",
+           "s2w_analysis_adjoint", "s2w_synthesis_adjoint", "s2w_sht_forward", "s2w_sht_inverse",
+           "s2w_plan_profile", "s2w_plan_profile_read",
+           "s2w_last_error", "s2w_host_scales", "s2w_host_filters", "s2w_host_theta_matrix",
+           "s2w_host_wigner_d"]
+
+
+def lib():
+    return _lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise S2WError(st, _lib.s2w_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ------------------------------------------------------------- host helpers
+
+def host_scales(L, N, lam=2.0, J0=0):
+    ns = ctypes.c_int()
+    Lk = (ctypes.c_int * 70)()
+    Nk = (ctypes.c_int * 70)()
+    Lp = ctypes.c_int()
+    _check(_lib.s2w_host_scales(L, N, lam, J0, ctypes.byref(ns), Lk, Nk, ctypes.byref(Lp)))
+    return list(Lk[:ns.value]), list(Nk[:ns.value]), Lp.value
+
+
+def host_filters(L, N, lam=2.0, J0=0):
+    Lk, _, _ = host_scales(L, N, lam, J0)
+    psi = np.zeros(len(Lk) * L * (2 * N - 1) * 2)
+    phi = np.zeros(L)
+    _check(_lib.s2w_host_filters(L, N, lam, J0, _dptr(psi), _dptr(phi)))
+    return psi.view(np.complex128).reshape(len(Lk), L, 2 * N - 1), phi
+
+
+def host_theta_matrix(L, sigma):
+    T = np.zeros(L * L)
+    _check(_lib.s2w_host_theta_matrix(L, sigma, _dptr(T)))
+    return T.reshape(L, L)
+
+
+def host_wigner_d(L, m, n):
+    out = np.zeros(L * L)
+    _check(_lib.s2w_host_wigner_d(L, m, n, _dptr(out)))
+    return out.reshape(L, L)
+
+
+# --------------------------------------------------------------- GPU plans
+
+def _stream_ptr(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """A transform plan (filters, tables, workspace) for (L, N, lambda, J0, batch).
+
+    Maps are torch float64 tensors [B, L, 2L-1] on the plan's device; wavelet
+    coefficients are returned as one packed tensor plus per-scale views.
+    """
+
+    def __init__(self, L, N, lam=2.0, J0=0, batch=1, precision=S2W_FP64, device=0):
+        import torch
+        self._torch = torch
+        self.L, self.N, self.lam, self.J0, self.batch = L, N, float(lam), J0, batch
+        self.precision = precision
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(_lib.s2w_plan_create(ctypes.byref(h), L, N, float(lam), J0, batch, precision, device, 0))
+        self._h = h
+        ns, j0 = ctypes.c_int(), ctypes.c_int()
+        Lk = (ctypes.c_int * 70)()
+        Nk = (ctypes.c_int * 70)()
+        off = (ctypes.c_int64 * 71)()
+        Lp = ctypes.c_int()
+        _check(_lib.s2w_plan_layout(h, ctypes.byref(ns), ctypes.byref(j0), Lk, Nk, off, ctypes.byref(Lp)))
+        self.nscales = ns.value
+        self.Lk = list(Lk[:ns.value])
+        self.Nk = list(Nk[:ns.value])
+        self.wav_offset = list(off[:ns.value + 1])
+        self.Lphi = Lp.value
+        self.wav_dtype = torch.float64 if precision == S2W_FP64 else torch.float32
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.s2w_plan_destroy(h)
+            self._h = None
+
+    # shapes ------------------------------------------------------------
+    @property
+    def map_shape(self):
+        return (self.batch, self.L, 2 * self.L - 1)
+
+    @property
+    def scal_shape(self):
+        return (self.batch, self.Lphi, 2 * self.Lphi - 1)
+
+    def scale_shape(self, k):
+        return (self.batch, 2 * self.Nk[k] - 1, self.Lk[k], 2 * self.Lk[k] - 1)
+
+    def wav_views(self, packed):
+        return [packed[self.wav_offset[k]:self.wav_offset[k + 1]].view(self.scale_shape(k))
+                for k in range(self.nscales)]
+
+    def _dev(self):
+        return self._torch.device("cuda", self.device)
+
+    def empty_wav(self):
+        return self._torch.empty(self.wav_offset[-1], dtype=self.wav_dtype, device=self._dev())
+
+    def _check_map(self, t):
+        torch = self._torch
+        if t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != self.map_shape or not t.is_contiguous():
+            raise ValueError(f"expected a contiguous float64 CUDA tensor of shape {self.map_shape}")
+
+    def _p(self, t):
+        return ctypes.c_void_p(t.data_ptr())
+
+    # transforms --------------------------------------------------------
+    def analysis(self, f, wav=None, scal=None):
+        torch = self._torch
+        self._check_map(f)
+        wav = self.empty_wav() if wav is None else wav
+        scal = torch.empty(self.scal_shape, dtype=torch.float64, device=self._dev()) if scal is None else scal
+        _check(_lib.s2w_analysis(self._h, self._p(f), self._p(wav), self._p(scal),
+                                 _stream_ptr(torch, self.device)))
+        return wav, scal
+
+    def synthesis(self, wav, scal, f=None):
+        torch = self._torch
+        f = torch.empty(self.map_shape, dtype=torch.float64, device=self._dev()) if f is None else f
+        _check(_lib.s2w_synthesis(self._h, self._p(wav), self._p(scal), self._p(f),
+                                  _stream_ptr(torch, self.device)))
+        return f
+
+    def analysis_adjoint(self, gwav, gscal, gf=None):
+        torch = self._torch
+        gf = torch.empty(self.map_shape, dtype=torch.float64, device=self._dev()) if gf is None else gf
+        _check(_lib.s2w_analysis_adjoint(self._h, self._p(gwav), self._p(gscal), self._p(gf),
+                                         _stream_ptr(torch, self.device)))
+        return gf
+
+    # kernel timing ------------------------------------------------------
+    def profile(self, capacity):
+        """Record HIP events around every kernel launch (capacity pairs); 0 stops."""
+        _check(_lib.s2w_plan_profile(self._h, int(capacity)))
+
+    def profile_read(self):
+        """{kernel name: (total ms, launches, algorithmic flop)} since profiling started."""
+        mx = 64
+        names = ctypes.create_string_buffer(32 * mx)
+        ms = (ctypes.c_double * mx)()
+        cnt = (ctypes.c_int64 * mx)()
+        fl = (ctypes.c_double * mx)()
+        k = ctypes.c_int()
+        dropped = ctypes.c_int64()
+        _check(_lib.s2w_plan_profile_read(self._h, mx, names, ms, cnt, fl, ctypes.byref(k),
+                                          ctypes.byref(dropped)))
+        out = {}
+        for i in range(k.value):
+            name = names.raw[32 * i:32 * (i + 1)].split(b"\0", 1)[0].decode()
+            out[name] = (ms[i], cnt[i], fl[i])
+        return out, dropped.value
+
+    def sht_forward(self, f):
+        torch = self._torch
+        self._check_map(f)
+        flm = torch.empty((self.batch, self.L, 2 * self.L - 1, 2), dtype=torch.float64, device=self._dev())
+        _check(_lib.s2w_sht_forward(self._h, self._p(f), self._p(flm), _stream_ptr(torch, self.device)))
+        return torch.view_as_complex(flm)
+
+    def sht_inverse(self, flm):
+        torch = self._torch
+        flm = torch.view_as_real(flm.to(torch.complex128)).contiguous()
+        f = torch.empty(self.map_shape, dtype=torch.float64, device=self._dev())
+        _check(_lib.s2w_sht_inverse(self._h, self._p(flm), self._p(f), _stream_ptr(torch, self.device)))
+        return f
+
+
+def _autograd():
+    import torch
+
+    class WaveletAnalysis(torch.autograd.Function):
+        """W = A f with the hand-written adjoint A^T in backward (Wigner d recomputed)."""
+
+        @staticmethod
+        def forward(ctx, f, plan):
+            wav, scal = plan.analysis(f.contiguous())
+            ctx.plan = plan
+            return wav, scal
+
+        @staticmethod
+        def backward(ctx, gwav, gscal):
+            plan = ctx.plan
+            if gwav is None:
+                gwav = torch.zeros(plan.wav_offset[-1], dtype=plan.wav_dtype, device=plan._dev())
+            if gscal is None:
+                gscal = torch.zeros(plan.scal_shape, dtype=torch.float64, device=plan._dev())
+            gf = plan.analysis_adjoint(gwav.contiguous(), gscal.contiguous())
+            return gf, None
+
+    return WaveletAnalysis
+
+
+def analysis(f, plan):
+    """Differentiable wavelet analysis: returns (packed wavelet coefficients, scaling coefficients)."""
+    return _autograd().apply(f, plan)

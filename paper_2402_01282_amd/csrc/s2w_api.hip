@@ -1,0 +1,930 @@
+// C-ABI of the s2w library: plans and transform entry points (see include/s2w.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/s2w.h"
+#include "s2w_host.h"
+#include "s2w_kern.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+s2w_status fail(s2w_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+struct DevDft {
+    int n = 0, n1 = 0, n2 = 0;
+    int *pin = nullptr, *pout = nullptr, *pinv = nullptr;
+    double *w1 = nullptr, *w2 = nullptr;
+};
+
+struct DevGrid {
+    int L = 0;
+    double *cth = nullptr, *ch = nullptr, *sh = nullptr, *ceps = nullptr, *seps = nullptr;
+    double *T[2] = {nullptr, nullptr};
+    DevDft dft;
+};
+
+struct Group {
+    std::vector<int> scales;   // plan scale indices sharing one grid
+    int L = 0;
+};
+
+}  // namespace
+
+struct s2w_plan_s {
+    int L = 0, N = 0, J0 = 0, J = 0, B = 1, device = 0;
+    double lambda = 2.0;
+    s2w_precision prec = S2W_FP64;
+    s2w::Scales S;
+    s2w::Filters F;
+    int Lphi = 1;
+    std::vector<int64_t> wav_off;
+    std::map<int, DevGrid> grids;
+    std::map<int, double *> gamma_tw;       // per ng = 2N_k-1
+    std::vector<int> nglob;                  // global n values of the recursion tables
+    double *A = nullptr, *Bt = nullptr, *S_ = nullptr, *smant = nullptr;
+    int *sexp = nullptr;
+    std::vector<double *> wpsi;              // per scale [nn][L_k]
+    double *wphi = nullptr, *wsht = nullptr;
+    double *flm = nullptr, *fhat = nullptr;
+    double *bufA = nullptr, *bufB = nullptr, *bufC = nullptr;
+    size_t szA = 0, szB = 0, szC = 0;
+    std::vector<double *> P;                 // per scale [B][L_k][nn][L_k] complex
+    double *Pphi = nullptr;
+    std::vector<Group> groups;
+    std::vector<void *> allocs;
+    bool alive = true;
+    // kernel timing
+    std::vector<hipEvent_t> ev0, ev1;
+    std::vector<int> rec_name;
+    std::vector<double> rec_flop;
+    std::vector<std::string> prof_names;
+    int64_t prof_dropped = 0;
+    int prof_cap = 0;
+};
+
+namespace {
+
+using s2w::CombineArgs;
+using s2w::DftArgs;
+using s2w::GammaArgs;
+using s2w::LsumArgs;
+using s2w::TsumArgs;
+
+// One HIP event pair around a kernel launch when profiling is on.
+struct Prof {
+    s2w_plan p;
+    hipStream_t st;
+    int idx = -1;
+    Prof(s2w_plan p_, const char *name, double flop, hipStream_t st_) : p(p_), st(st_)
+    {
+        if (p->prof_cap == 0) return;
+        if ((int)p->rec_name.size() >= p->prof_cap) { ++p->prof_dropped; return; }
+        int id = -1;
+        for (size_t i = 0; i < p->prof_names.size(); ++i)
+            if (p->prof_names[i] == name) id = (int)i;
+        if (id < 0) { p->prof_names.push_back(name); id = (int)p->prof_names.size() - 1; }
+        idx = (int)p->rec_name.size();
+        p->rec_name.push_back(id);
+        p->rec_flop.push_back(flop);
+        (void)hipEventRecord(p->ev0[idx], st);
+    }
+    ~Prof()
+    {
+        if (idx >= 0) (void)hipEventRecord(p->ev1[idx], st);
+    }
+};
+
+// algorithmic flop of a recursion + contraction pass: sum over (m, n) of
+// (L - l0) steps x L theta samples x (6 + 4 NS)
+double rec_flop(int L, int mcount, const std::vector<int> &ns, int NS, int B)
+{
+    double steps = 0.0;
+    for (int n : ns)
+        for (int m = 0; m < mcount; ++m) {
+            const int l0 = std::max(m, std::abs(n));
+            if (l0 < L) steps += (double)(L - l0);
+        }
+    return steps * L * (6.0 + 4.0 * NS) * B;
+}
+
+double dft_flop(int n, long rows) { return n > 1 ? 2.5 * n * std::log2((double)n) * (double)rows : 0.0; }
+
+template <class Tp>
+bool dalloc(s2w_plan p, Tp *&ptr, size_t count)
+{
+    void *v = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&v, count * sizeof(Tp)) != hipSuccess) return false;
+    p->allocs.push_back(v);
+    ptr = (Tp *)v;
+    return true;
+}
+
+template <class Tp>
+bool upload(s2w_plan p, Tp *&ptr, const std::vector<Tp> &h)
+{
+    if (!dalloc(p, ptr, h.size())) return false;
+    return hipMemcpy(ptr, h.data(), h.size() * sizeof(Tp), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+void free_plan(s2w_plan p)
+{
+    for (void *v : p->allocs) (void)hipFree(v);
+    p->allocs.clear();
+}
+
+int nglob_index(s2w_plan p, int n)
+{
+    for (size_t i = 0; i < p->nglob.size(); ++i)
+        if (p->nglob[i] == n) return (int)i;
+    return -1;
+}
+
+bool make_grid(s2w_plan p, int L)
+{
+    if (p->grids.count(L)) return true;
+    DevGrid g;
+    g.L = L;
+    s2w::ThetaTables tt;
+    s2w::theta_tables(L, tt);
+    if (!upload(p, g.cth, tt.cth) || !upload(p, g.ch, tt.ch) || !upload(p, g.sh, tt.sh) ||
+        !upload(p, g.ceps, tt.ch_eps) || !upload(p, g.seps, tt.sh_eps))
+        return false;
+    for (int si = 0; si < 2; ++si) {
+        std::vector<double> T;
+        s2w::theta_matrix(L, si == 0 ? 1 : -1, T);
+        if (!upload(p, g.T[si], T)) return false;
+    }
+    const int n = 2 * L - 1;
+    s2w::PfaPlan pp;
+    s2w::pfa_plan(n, pp);
+    std::vector<int> pin(n), pout(n), pinv(n);
+    for (int m1 = 0; m1 < pp.n1; ++m1)
+        for (int m2 = 0; m2 < pp.n2; ++m2) {
+            const int pos = m1 * pp.n2 + m2;
+            pin[pos] = (int)(((long long)m1 * pp.n2 + (long long)m2 * pp.n1) % n);
+            pout[pos] = (int)(((long long)m1 * pp.e1 + (long long)m2 * pp.e2) % n);
+        }
+    for (int pos = 0; pos < n; ++pos) pinv[pout[pos]] = pos;
+    g.dft.n = n;
+    g.dft.n1 = pp.n1;
+    g.dft.n2 = pp.n2;
+    if (!upload(p, g.dft.pin, pin) || !upload(p, g.dft.pout, pout) || !upload(p, g.dft.pinv, pinv) ||
+        !upload(p, g.dft.w1, pp.w1) || !upload(p, g.dft.w2, pp.w2))
+        return false;
+    p->grids[L] = g;
+    return true;
+}
+
+bool make_gamma_tw(s2w_plan p, int ng)
+{
+    if (p->gamma_tw.count(ng)) return true;
+    std::vector<double> tw(2 * ng);
+    for (int k = 0; k < ng; ++k) {
+        long double a = 2.0L * 3.141592653589793238462643383279502884L * k / ng;
+        tw[2 * k] = (double)cosl(a);
+        tw[2 * k + 1] = (double)sinl(a);
+    }
+    double *d = nullptr;
+    if (!upload(p, d, tw)) return false;
+    p->gamma_tw[ng] = d;
+    return true;
+}
+
+DftArgs dft_args(const DevGrid &g, const double *in, long istride, double *out, long ostride, int nrows,
+                 double scale)
+{
+    DftArgs a{};
+    a.in = in;
+    a.out = out;
+    a.istride = istride;
+    a.ostride = ostride;
+    a.nrows = nrows;
+    a.n = g.dft.n;
+    a.n1 = g.dft.n1;
+    a.n2 = g.dft.n2;
+    a.pin = g.dft.pin;
+    a.pout = g.dft.pout;
+    a.pinv = g.dft.pinv;
+    a.w1 = g.dft.w1;
+    a.w2 = g.dft.w2;
+    a.scale = scale;
+    return a;
+}
+
+void sig_counts(int M, int npar, int &M0, int &M1)
+{
+    M0 = M1 = 0;
+    for (int m = 0; m < M; ++m) ((m + npar) & 1) ? ++M1 : ++M0;
+}
+
+LsumArgs lsum_args(s2w_plan p, const DevGrid &g, int mcount, const std::vector<int> &ns)
+{
+    LsumArgs a{};
+    a.L = g.L;
+    a.mcount = mcount;
+    a.nn = (int)ns.size();
+    a.Lrec = p->L;
+    for (int i = 0; i < a.nn; ++i) {
+        a.nval[i] = ns[i];
+        a.nglob[i] = nglob_index(p, ns[i]);
+    }
+    a.A = p->A;
+    a.B = p->Bt;
+    a.S = p->S_;
+    a.smant = p->smant;
+    a.sexp = p->sexp;
+    a.cth = g.cth;
+    a.ch = g.ch;
+    a.sh = g.sh;
+    a.ceps = g.ceps;
+    a.seps = g.seps;
+    return a;
+}
+
+TsumArgs tsum_args(s2w_plan p, const DevGrid &g, int mcount, const std::vector<int> &ns, int npar)
+{
+    TsumArgs a{};
+    a.L = g.L;
+    a.mcount = mcount;
+    a.nn = (int)ns.size();
+    a.Lrec = p->L;
+    a.B = p->B;
+    for (int i = 0; i < a.nn; ++i) {
+        a.nval[i] = ns[i];
+        a.nglob[i] = nglob_index(p, ns[i]);
+    }
+    a.A = p->A;
+    a.B_ = p->Bt;
+    a.S = p->S_;
+    a.smant = p->smant;
+    a.sexp = p->sexp;
+    a.cth = g.cth;
+    a.ch = g.ch;
+    a.sh = g.sh;
+    a.ceps = g.ceps;
+    a.seps = g.seps;
+    a.npar = npar;
+    sig_counts(mcount, npar, a.M0, a.M1);
+    return a;
+}
+
+GammaArgs gamma_args(s2w_plan p, int M, int L, int Min, int Mout, const std::vector<int> &ns, int ng)
+{
+    GammaArgs a{};
+    a.B = p->B;
+    a.M = M;
+    a.L = L;
+    a.Min = Min;
+    a.Mout = Mout;
+    a.nn = (int)ns.size();
+    a.ng = ng;
+    for (int i = 0; i < a.nn; ++i) a.nval[i] = ns[i];
+    a.tw = p->gamma_tw[ng];
+    a.sgn = 1.0;
+    a.phr = 1.0;
+    a.phi = 0.0;
+    a.wscale = 1.0;
+    a.fm0 = 1.0;
+    a.fm1 = 1.0;
+    a.npar = 0;
+    a.M0 = a.M1 = 0;
+    return a;
+}
+
+// h = T_sigma F on sigma-grouped rows; nn n values per m, npar their parity
+void theta_quadrature(s2w_plan p, const DevGrid &g, const double *F, double *H, int M, int nn, int npar,
+                      hipStream_t st)
+{
+    int M0, M1;
+    sig_counts(M, npar, M0, M1);
+    const size_t r0 = (size_t)p->B * M0 * nn * 2, r1 = (size_t)p->B * M1 * nn * 2;
+    {
+        Prof pr_(p, "gemm_theta", 2.0 * (double)r0 * g.L * g.L, st);
+        s2w::launch_gemm(F, g.T[0], H, (int)r0, g.L, g.L, st);
+    }
+    {
+        Prof pr_(p, "gemm_theta", 2.0 * (double)r1 * g.L * g.L, st);
+        s2w::launch_gemm(F + r0 * g.L, g.T[1], H + r0 * g.L, (int)r1, g.L, g.L, st);
+    }
+}
+
+// f (maps) -> flm internal [B][L][L] (m-major), forward SHT (eq:fswsh on MW samples)
+void sht_forward_internal(s2w_plan p, const double *f, double *flm_out, hipStream_t st)
+{
+    const DevGrid &g = p->grids[p->L];
+    const int L = p->L, na = 2 * L - 1;
+    { const DftArgs da_ = dft_args(g, f, na, p->bufA, L, p->B * L, 2.0 * M_PI / na); Prof pr_(p, "dft_r2c", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_r2c(da_, st); }
+    std::vector<int> n0{0};
+    GammaArgs ga = gamma_args(p, L, L, L, L, n0, 1);
+    ga.src = p->bufA;
+    ga.dst = p->bufB;
+    ga.sgn = -1.0;
+    sig_counts(L, 0, ga.M0, ga.M1);
+    { Prof pr_(p, "gamma_r2c", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_r2c(ga, st); }
+    theta_quadrature(p, g, p->bufB, p->bufC, L, 1, 0, st);
+    TsumArgs ta = tsum_args(p, g, L, n0, 0);
+    ta.h[0] = p->bufC;
+    ta.w[0] = p->wsht;
+    ta.wstride = 0;
+    ta.out[0] = flm_out;
+    {
+        std::vector<int> ns_(ta.nval, ta.nval + ta.nn);
+        Prof pr_(p, "tsum", rec_flop(ta.L, ta.mcount, ns_, 1, p->B), st);
+        s2w::launch_tsum(ta, 1, p->B, st);
+    }
+}
+
+// flm internal -> maps, inverse SHT (eq:iswsh)
+void sht_inverse_internal(s2w_plan p, const double *flm_in, double *f, hipStream_t st)
+{
+    const DevGrid &g = p->grids[p->L];
+    const int L = p->L, na = 2 * L - 1;
+    std::vector<int> n0{0};
+    LsumArgs la = lsum_args(p, g, L, n0);
+    la.flm = flm_in;
+    la.flm_m = L;
+    la.flm_l = L;
+    la.w[0] = p->wsht;
+    la.wstride = 0;
+    la.out[0] = p->bufA;
+    {
+        std::vector<int> ns_(la.nval, la.nval + la.nn);
+        Prof pr_(p, "lsum", rec_flop(la.L, la.mcount, ns_, 1, p->B), st);
+        s2w::launch_lsum(la, 1, p->B, st);
+    }
+    GammaArgs ga = gamma_args(p, L, L, L, L, n0, 1);
+    ga.src = p->bufA;
+    ga.dst = p->bufB;
+    { Prof pr_(p, "gamma_c2r", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_c2r(ga, st); }
+    { const DftArgs da_ = dft_args(g, p->bufB, L, f, na, p->B * L, 1.0); Prof pr_(p, "dft_c2r", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_c2r(da_, st); }
+}
+
+s2w_status check_plan(s2w_plan p)
+{
+    if (!p) return fail(S2W_EINVAL, "null plan");
+    if (!p->alive) return fail(S2W_ESTATE, "plan used after destroy");
+    return S2W_OK;
+}
+
+s2w_status post_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(S2W_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return S2W_OK;
+}
+
+}  // namespace
+
+// ======================================================================== API
+
+extern "C" {
+
+const char *s2w_last_error(void) { return g_err.c_str(); }
+
+s2w_status s2w_host_scales(int L, int N, double lambda, int J0, int *nscales, int *Lk, int *Nk, int *L_phi)
+{
+    s2w::Scales S;
+    std::string err;
+    if (!s2w::make_scales(L, N, lambda, J0, S, err)) return fail(S2W_EINVAL, err);
+    if (nscales) *nscales = (int)S.s.size();
+    for (size_t k = 0; k < S.s.size(); ++k) {
+        if (Lk) Lk[k] = S.s[k].L;
+        if (Nk) Nk[k] = S.s[k].N;
+    }
+    if (L_phi) *L_phi = S.Lphi;
+    return S2W_OK;
+}
+
+s2w_status s2w_host_filters(int L, int N, double lambda, int J0, double *psi, double *phi)
+{
+    s2w::Scales S;
+    std::string err;
+    if (!s2w::make_scales(L, N, lambda, J0, S, err)) return fail(S2W_EINVAL, err);
+    s2w::Filters F;
+    s2w::make_filters(S, F);
+    if (phi)
+        for (int l = 0; l < L; ++l) phi[l] = F.phi[l];
+    if (psi) {
+        const size_t per = (size_t)L * (2 * N - 1) * 2;
+        std::memset(psi, 0, sizeof(double) * per * S.s.size());
+        for (size_t k = 0; k < S.s.size(); ++k) {
+            const auto &si = S.s[k];
+            const int nn = (int)si.n.size();
+            for (int l = 0; l < si.L; ++l)
+                for (int i = 0; i < nn; ++i) {
+                    const double v = F.psi_mag[k][(size_t)l * nn + i];
+                    double *o = psi + k * per + ((size_t)l * (2 * N - 1) + (si.n[i] + N - 1)) * 2;
+                    if (F.xi_imag) o[1] = v;
+                    else o[0] = v;
+                }
+        }
+    }
+    return S2W_OK;
+}
+
+s2w_status s2w_host_theta_matrix(int L, int sigma, double *T)
+{
+    if (L < 1 || !T || (sigma != 1 && sigma != -1)) return fail(S2W_EINVAL, "bad arguments");
+    std::vector<double> t;
+    s2w::theta_matrix(L, sigma, t);
+    std::memcpy(T, t.data(), sizeof(double) * t.size());
+    return S2W_OK;
+}
+
+s2w_status s2w_host_wigner_d(int L, int m, int n, double *out)
+{
+    if (L < 1 || !out || std::abs(m) >= L || std::abs(n) >= L) return fail(S2W_EINVAL, "bad arguments");
+    std::vector<double> d;
+    s2w::host_wigner_d(L, m, n, d);
+    std::memcpy(out, d.data(), sizeof(double) * d.size());
+    return S2W_OK;
+}
+
+s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, int batch,
+                           s2w_precision precision, int device, unsigned flags)
+{
+    if (!out) return fail(S2W_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (batch < 1) return fail(S2W_EINVAL, "batch must be >= 1");
+    if (flags != 0) return fail(S2W_EINVAL, "flags must be 0");
+    if (precision != S2W_FP64) return fail(S2W_EUNSUPPORTED, "only S2W_FP64 plans are available");
+    s2w::Scales S;
+    std::string err;
+    if (!s2w::make_scales(L, N, lambda, J0, S, err)) return fail(S2W_EINVAL, err);
+    if (N > s2w::MAX_NN) return fail(S2W_EUNSUPPORTED, "N too large (max 8)");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(S2W_EHIP, "no HIP device");
+    if (device < 0 || device >= ndev) return fail(S2W_EINVAL, "bad device index");
+    if (hipSetDevice(device) != hipSuccess) return fail(S2W_EHIP, "hipSetDevice failed");
+
+    s2w_plan p = new (std::nothrow) s2w_plan_s;
+    if (!p) return fail(S2W_ENOMEM, "host allocation failed");
+    p->L = L; p->N = N; p->J0 = J0; p->J = S.J; p->B = batch; p->device = device;
+    p->lambda = lambda; p->prec = precision;
+    p->S = S;
+    p->Lphi = S.Lphi;
+    s2w::make_filters(p->S, p->F);
+
+    auto oom = [&](const char *what) {
+        free_plan(p);
+        delete p;
+        return fail(S2W_ENOMEM, std::string("device allocation failed: ") + what);
+    };
+
+    // layout
+    const int K = (int)S.s.size();
+    p->wav_off.assign(K + 1, 0);
+    for (int k = 0; k < K; ++k)
+        p->wav_off[k + 1] = p->wav_off[k] + (int64_t)batch * (2 * S.s[k].N - 1) * S.s[k].L * (2 * S.s[k].L - 1);
+
+    // grids
+    if (!make_grid(p, L) || !make_grid(p, p->Lphi)) return oom("grid tables");
+    for (int k = 0; k < K; ++k) {
+        if (!make_grid(p, S.s[k].L)) return oom("grid tables");
+        if (!make_gamma_tw(p, 2 * S.s[k].N - 1)) return oom("gamma twiddles");
+    }
+    if (!make_gamma_tw(p, 1)) return oom("gamma twiddles");
+
+    // global n list: top scale's n values plus n = 0
+    p->nglob = S.s.back().n;
+    if (std::find(p->nglob.begin(), p->nglob.end(), 0) == p->nglob.end()) p->nglob.push_back(0);
+    {
+        s2w::RecTables R;
+        s2w::rec_tables(L, p->nglob, R);
+        if (!upload(p, p->A, R.A) || !upload(p, p->Bt, R.B) || !upload(p, p->S_, R.S) ||
+            !upload(p, p->smant, R.start_mant) || !upload(p, p->sexp, R.start_exp))
+            return oom("recursion tables");
+    }
+    // weights
+    {
+        std::vector<double> ws(L), wp(p->Lphi);
+        for (int l = 0; l < L; ++l) ws[l] = sqrt((2.0 * l + 1.0) / (4.0 * M_PI));
+        for (int l = 0; l < p->Lphi; ++l) wp[l] = p->F.phi[l];
+        if (!upload(p, p->wsht, ws) || !upload(p, p->wphi, wp)) return oom("weights");
+        p->wpsi.assign(K, nullptr);
+        for (int k = 0; k < K; ++k) {
+            const int Lk = S.s[k].L, nn = (int)S.s[k].n.size();
+            std::vector<double> w((size_t)nn * Lk);
+            for (int i = 0; i < nn; ++i)
+                for (int l = 0; l < Lk; ++l) w[(size_t)i * Lk + l] = p->F.psi_mag[k][(size_t)l * nn + i];
+            if (!upload(p, p->wpsi[k], w)) return oom("weights");
+        }
+    }
+    // scale groups (same grid)
+    for (int k = 0; k < K; ++k) {
+        if (!p->groups.empty() && p->groups.back().L == S.s[k].L && p->groups.back().scales.size() < 2)
+            p->groups.back().scales.push_back(k);
+        else {
+            Group g;
+            g.L = S.s[k].L;
+            g.scales.push_back(k);
+            p->groups.push_back(g);
+        }
+    }
+    // workspace
+    {
+        size_t a = (size_t)batch * L * L * 2 * 2;   // SHT stages
+        size_t bsz = a, c = a;
+        for (auto &g : p->groups) {
+            const int Lk = g.L, NS = (int)g.scales.size();
+            const int nn = (int)S.s[g.scales[0]].n.size(), ng = 2 * S.s[g.scales[0]].N - 1;
+            const size_t cbuf = (size_t)NS * batch * nn * Lk * Lk * 2;   // lsum out / sigma rows
+            const size_t ebuf = (size_t)batch * ng * Lk * Lk * 2;        // rows over m
+            a = std::max(a, std::max(cbuf, ebuf));
+            bsz = std::max(bsz, std::max(cbuf, ebuf));
+            c = std::max(c, cbuf);
+        }
+        p->szA = a; p->szB = bsz; p->szC = c;
+        if (!dalloc(p, p->bufA, a) || !dalloc(p, p->bufB, bsz) || !dalloc(p, p->bufC, c)) return oom("workspace");
+        if (!dalloc(p, p->flm, (size_t)batch * L * L * 2) || !dalloc(p, p->fhat, (size_t)batch * L * L * 2))
+            return oom("workspace");
+        p->P.assign(K, nullptr);
+        for (int k = 0; k < K; ++k) {
+            const int Lk = S.s[k].L, nn = (int)S.s[k].n.size();
+            if (!dalloc(p, p->P[k], (size_t)batch * Lk * nn * Lk * 2)) return oom("workspace");
+        }
+        if (!dalloc(p, p->Pphi, (size_t)batch * p->Lphi * p->Lphi * 2)) return oom("workspace");
+    }
+    if (hipDeviceSynchronize() != hipSuccess) {
+        free_plan(p);
+        delete p;
+        return fail(S2W_EHIP, "device synchronisation failed during plan creation");
+    }
+    *out = p;
+    return S2W_OK;
+}
+
+s2w_status s2w_plan_destroy(s2w_plan p)
+{
+    if (!p) return S2W_OK;
+    if (!p->alive) return fail(S2W_ESTATE, "plan destroyed twice");
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    for (auto e : p->ev0) (void)hipEventDestroy(e);
+    for (auto e : p->ev1) (void)hipEventDestroy(e);
+    free_plan(p);
+    p->alive = false;
+    delete p;
+    return S2W_OK;
+}
+
+s2w_status s2w_plan_layout(s2w_plan p, int *nscales, int *J0, int *Lk, int *Nk, int64_t *wav_offset, int *L_phi)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    const int K = (int)p->S.s.size();
+    if (nscales) *nscales = K;
+    if (J0) *J0 = p->J0;
+    for (int k = 0; k < K; ++k) {
+        if (Lk) Lk[k] = p->S.s[k].L;
+        if (Nk) Nk[k] = p->S.s[k].N;
+    }
+    if (wav_offset)
+        for (int k = 0; k <= K; ++k) wav_offset[k] = p->wav_off[k];
+    if (L_phi) *L_phi = p->Lphi;
+    return S2W_OK;
+}
+
+s2w_status s2w_sht_forward(s2w_plan p, const double *f, double *flm, void *stream)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (!f || !flm) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    sht_forward_internal(p, f, p->flm, st);
+    s2w::launch_flm_to_ext(p->flm, flm, p->L, p->B, st);
+    return post_launch("s2w_sht_forward");
+}
+
+s2w_status s2w_sht_inverse(s2w_plan p, const double *flm, double *f, void *stream)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (!f || !flm) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    s2w::launch_flm_from_ext(flm, p->flm, p->L, p->B, st);
+    sht_inverse_internal(p, p->flm, f, st);
+    return post_launch("s2w_sht_inverse");
+}
+
+s2w_status s2w_analysis(s2w_plan p, const double *f, void *wav_, double *scal, void *stream)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (!f || !wav_ || !scal) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    double *wav = (double *)wav_;
+    const int B = p->B;
+    sht_forward_internal(p, f, p->flm, st);
+    // scaling coefficients: W^Phi = Y^{-1}_{L_phi}(Phi f)
+    {
+        const DevGrid &g = p->grids[p->Lphi];
+        const int Lp = p->Lphi;
+        std::vector<int> n0{0};
+        LsumArgs la = lsum_args(p, g, Lp, n0);
+        la.flm = p->flm;
+        la.flm_m = p->L;
+        la.flm_l = p->L;
+        la.w[0] = p->wphi;
+        la.wstride = 0;
+        la.out[0] = p->bufA;
+        { std::vector<int> ns_(la.nval, la.nval + la.nn); Prof pr_(p, "lsum", rec_flop(la.L, la.mcount, ns_, 1, B), st); s2w::launch_lsum(la, 1, B, st); }
+        GammaArgs ga = gamma_args(p, Lp, Lp, Lp, Lp, n0, 1);
+        ga.src = p->bufA;
+        ga.dst = p->bufB;
+        { Prof pr_(p, "gamma_c2r", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_c2r(ga, st); }
+        { const DftArgs da_ = dft_args(g, p->bufB, Lp, scal, 2 * Lp - 1, B * Lp, 1.0); Prof pr_(p, "dft_c2r", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_c2r(da_, st); }
+    }
+    // wavelet scales
+    for (auto &grp : p->groups) {
+        const DevGrid &g = p->grids[grp.L];
+        const int Lk = grp.L, NS = (int)grp.scales.size();
+        const auto &si = p->S.s[grp.scales[0]];
+        const int nn = (int)si.n.size(), ng = 2 * si.N - 1;
+        LsumArgs la = lsum_args(p, g, Lk, si.n);
+        la.flm = p->flm;
+        la.flm_m = p->L;
+        la.flm_l = p->L;
+        la.wstride = Lk;
+        const size_t cstride = (size_t)B * nn * Lk * Lk * 2;
+        for (int s = 0; s < NS; ++s) {
+            la.w[s] = p->wpsi[grp.scales[s]];
+            la.out[s] = p->bufA + s * cstride;
+        }
+        { std::vector<int> ns_(la.nval, la.nval + la.nn); Prof pr_(p, "lsum", rec_flop(la.L, la.mcount, ns_, NS, B), st); s2w::launch_lsum(la, NS, B, st); }
+        for (int s = 0; s < NS; ++s) {
+            const int k = grp.scales[s];
+            GammaArgs ga = gamma_args(p, Lk, Lk, Lk, Lk, si.n, ng);
+            ga.src = p->bufA + s * cstride;
+            ga.dst = p->bufB;
+            if (p->F.xi_imag) { ga.phr = 0.0; ga.phi = -1.0; }   // conj(xi) = -i
+            { Prof pr_(p, "gamma_c2r", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_c2r(ga, st); }
+            { const DftArgs da_ = dft_args(g, p->bufB, Lk, wav + p->wav_off[k], 2 * Lk - 1, B * ng * Lk, 1.0); Prof pr_(p, "dft_c2r", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_c2r(da_, st); }
+        }
+    }
+    return post_launch("s2w_analysis");
+}
+
+s2w_status s2w_synthesis(s2w_plan p, const void *wav_, const double *scal, double *f, void *stream)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (!f || !wav_ || !scal) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    const double *wav = (const double *)wav_;
+    const int B = p->B;
+    const int npar = (p->N - 1) & 1;
+    for (auto &grp : p->groups) {
+        const DevGrid &g = p->grids[grp.L];
+        const int Lk = grp.L, NS = (int)grp.scales.size();
+        const auto &si = p->S.s[grp.scales[0]];
+        const int nn = (int)si.n.size(), ng = 2 * si.N - 1;
+        const size_t cstride = (size_t)B * nn * Lk * Lk * 2;
+        TsumArgs ta = tsum_args(p, g, Lk, si.n, npar);
+        ta.wstride = Lk;
+        for (int s = 0; s < NS; ++s) {
+            const int k = grp.scales[s];
+            { const DftArgs da_ = dft_args(g, wav + p->wav_off[k], 2 * Lk - 1, p->bufB, Lk, B * ng * Lk, 1.0); Prof pr_(p, "dft_r2c", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_r2c(da_, st); }
+            GammaArgs ga = gamma_args(p, Lk, Lk, Lk, Lk, si.n, ng);
+            ga.src = p->bufB;
+            ga.dst = p->bufA + s * cstride;
+            ga.sgn = -1.0;
+            ga.wscale = (2.0 * M_PI / (2 * Lk - 1)) * (2.0 * M_PI / ng);
+            ga.npar = npar;
+            sig_counts(Lk, npar, ga.M0, ga.M1);
+            { Prof pr_(p, "gamma_r2c", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_r2c(ga, st); }
+            theta_quadrature(p, g, p->bufA + s * cstride, p->bufC + s * cstride, Lk, nn, npar, st);
+            ta.h[s] = p->bufC + s * cstride;
+            ta.w[s] = p->wpsi[k];
+            ta.out[s] = p->P[k];
+        }
+        { std::vector<int> ns_(ta.nval, ta.nval + ta.nn); Prof pr_(p, "tsum", rec_flop(ta.L, ta.mcount, ns_, NS, B), st); s2w::launch_tsum(ta, NS, B, st); }
+    }
+    // scaling: Phi * Y(W^Phi)
+    {
+        const DevGrid &g = p->grids[p->Lphi];
+        const int Lp = p->Lphi;
+        std::vector<int> n0{0};
+        { const DftArgs da_ = dft_args(g, scal, 2 * Lp - 1, p->bufB, Lp, B * Lp, 2.0 * M_PI / (2 * Lp - 1)); Prof pr_(p, "dft_r2c", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_r2c(da_, st); }
+        GammaArgs ga = gamma_args(p, Lp, Lp, Lp, Lp, n0, 1);
+        ga.src = p->bufB;
+        ga.dst = p->bufA;
+        ga.sgn = -1.0;
+        sig_counts(Lp, 0, ga.M0, ga.M1);
+        { Prof pr_(p, "gamma_r2c", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_r2c(ga, st); }
+        theta_quadrature(p, g, p->bufA, p->bufC, Lp, 1, 0, st);
+        TsumArgs ta = tsum_args(p, g, Lp, n0, 0);
+        ta.h[0] = p->bufC;
+        ta.w[0] = p->wphi;
+        ta.wstride = 0;
+        ta.out[0] = p->Pphi;
+        { std::vector<int> ns_(ta.nval, ta.nval + ta.nn); Prof pr_(p, "tsum", rec_flop(ta.L, ta.mcount, ns_, 1, B), st); s2w::launch_tsum(ta, 1, B, st); }
+    }
+    CombineArgs ca{};
+    ca.out = p->fhat;
+    ca.L = p->L;
+    ca.nterms = 0;
+    for (size_t k = 0; k < p->S.s.size(); ++k) {
+        auto &t = ca.t[ca.nterms++];
+        t.P = p->P[k];
+        t.L = p->S.s[k].L;
+        t.nn = (int)p->S.s[k].n.size();
+        t.phr = p->F.xi_imag ? 0.0 : 1.0;
+        t.phi = p->F.xi_imag ? 1.0 : 0.0;
+    }
+    {
+        auto &t = ca.t[ca.nterms++];
+        t.P = p->Pphi;
+        t.L = p->Lphi;
+        t.nn = 1;
+        t.phr = 1.0;
+        t.phi = 0.0;
+    }
+    { Prof pr_(p, "combine", 0.0, st); s2w::launch_combine(ca, B, st); }
+    sht_inverse_internal(p, p->fhat, f, st);
+    return post_launch("s2w_synthesis");
+}
+
+s2w_status s2w_analysis_adjoint(s2w_plan p, const void *gwav_, const double *gscal, double *gf, void *stream)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (!gf || !gwav_ || !gscal) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    const double *gwav = (const double *)gwav_;
+    const int B = p->B;
+    const int npar = (p->N - 1) & 1;
+    // wavelet scales: transpose of (c2r, gamma, l-sum)
+    for (auto &grp : p->groups) {
+        const DevGrid &g = p->grids[grp.L];
+        const int Lk = grp.L, NS = (int)grp.scales.size();
+        const auto &si = p->S.s[grp.scales[0]];
+        const int nn = (int)si.n.size(), ng = 2 * si.N - 1;
+        const size_t cstride = (size_t)B * nn * Lk * Lk * 2;
+        TsumArgs ta = tsum_args(p, g, Lk, si.n, npar);
+        ta.wstride = Lk;
+        for (int s = 0; s < NS; ++s) {
+            const int k = grp.scales[s];
+            { const DftArgs da_ = dft_args(g, gwav + p->wav_off[k], 2 * Lk - 1, p->bufB, Lk, B * ng * Lk, 1.0); Prof pr_(p, "dft_r2c", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_r2c(da_, st); }
+            GammaArgs ga = gamma_args(p, Lk, Lk, Lk, Lk, si.n, ng);
+            ga.src = p->bufB;
+            ga.dst = p->bufA + s * cstride;
+            ga.sgn = -1.0;
+            ga.fm0 = 1.0;
+            ga.fm1 = 2.0;
+            if (p->F.xi_imag) { ga.phr = 0.0; ga.phi = 1.0; }   // xi = i
+            ga.npar = npar;
+            sig_counts(Lk, npar, ga.M0, ga.M1);
+            { Prof pr_(p, "gamma_r2c", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_r2c(ga, st); }
+            ta.h[s] = p->bufA + s * cstride;
+            ta.w[s] = p->wpsi[k];
+            ta.out[s] = p->P[k];
+        }
+        { std::vector<int> ns_(ta.nval, ta.nval + ta.nn); Prof pr_(p, "tsum", rec_flop(ta.L, ta.mcount, ns_, NS, B), st); s2w::launch_tsum(ta, NS, B, st); }
+    }
+    // scaling part
+    {
+        const DevGrid &g = p->grids[p->Lphi];
+        const int Lp = p->Lphi;
+        std::vector<int> n0{0};
+        { const DftArgs da_ = dft_args(g, gscal, 2 * Lp - 1, p->bufB, Lp, B * Lp, 1.0); Prof pr_(p, "dft_r2c", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_r2c(da_, st); }
+        GammaArgs ga = gamma_args(p, Lp, Lp, Lp, Lp, n0, 1);
+        ga.src = p->bufB;
+        ga.dst = p->bufA;
+        ga.sgn = -1.0;
+        ga.fm0 = 1.0;
+        ga.fm1 = 2.0;
+        sig_counts(Lp, 0, ga.M0, ga.M1);
+        { Prof pr_(p, "gamma_r2c", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_r2c(ga, st); }
+        TsumArgs ta = tsum_args(p, g, Lp, n0, 0);
+        ta.h[0] = p->bufA;
+        ta.w[0] = p->wphi;
+        ta.wstride = 0;
+        ta.out[0] = p->Pphi;
+        { std::vector<int> ns_(ta.nval, ta.nval + ta.nn); Prof pr_(p, "tsum", rec_flop(ta.L, ta.mcount, ns_, 1, B), st); s2w::launch_tsum(ta, 1, B, st); }
+    }
+    CombineArgs ca{};
+    ca.out = p->fhat;
+    ca.L = p->L;
+    for (size_t k = 0; k < p->S.s.size(); ++k) {
+        auto &t = ca.t[ca.nterms++];
+        t.P = p->P[k];
+        t.L = p->S.s[k].L;
+        t.nn = (int)p->S.s[k].n.size();
+        t.phr = 1.0;
+        t.phi = 0.0;
+    }
+    {
+        auto &t = ca.t[ca.nterms++];
+        t.P = p->Pphi;
+        t.L = p->Lphi;
+        t.nn = 1;
+        t.phr = 1.0;
+        t.phi = 0.0;
+    }
+    { Prof pr_(p, "combine", 0.0, st); s2w::launch_combine(ca, B, st); }
+    // transpose of the forward SHT: l-sum (n = 0), T_sigma, then the phi transpose
+    {
+        const DevGrid &g = p->grids[p->L];
+        const int L = p->L, na = 2 * L - 1;
+        std::vector<int> n0{0};
+        LsumArgs la = lsum_args(p, g, L, n0);
+        la.flm = p->fhat;
+        la.flm_m = L;
+        la.flm_l = L;
+        la.w[0] = p->wsht;
+        la.wstride = 0;
+        la.out[0] = p->bufA;
+        { std::vector<int> ns_(la.nval, la.nval + la.nn); Prof pr_(p, "lsum", rec_flop(la.L, la.mcount, ns_, 1, B), st); s2w::launch_lsum(la, 1, B, st); }
+        int M0, M1;
+        sig_counts(L, 0, M0, M1);
+        { Prof pr_(p, "pack_sigma", 0.0, st); s2w::launch_pack_sigma(p->bufA, p->bufB, B, 1, L, L, 0, M0, M1, 0, st); }
+        theta_quadrature(p, g, p->bufB, p->bufC, L, 1, 0, st);
+        { Prof pr_(p, "pack_sigma", 0.0, st); s2w::launch_pack_sigma(p->bufC, p->bufA, B, 1, L, L, 0, M0, M1, 1, st); }
+        GammaArgs ga = gamma_args(p, L, L, L, L, n0, 1);
+        ga.src = p->bufA;
+        ga.dst = p->bufB;
+        ga.fm0 = 1.0;
+        ga.fm1 = 0.5;
+        { Prof pr_(p, "gamma_c2r", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_c2r(ga, st); }
+        { const DftArgs da_ = dft_args(g, p->bufB, L, gf, na, B * L, 2.0 * M_PI / na); Prof pr_(p, "dft_c2r", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_c2r(da_, st); }
+    }
+    return post_launch("s2w_analysis_adjoint");
+}
+
+s2w_status s2w_plan_profile(s2w_plan p, int capacity)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (capacity < 0) return fail(S2W_EINVAL, "capacity must be >= 0");
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    for (auto e : p->ev0) (void)hipEventDestroy(e);
+    for (auto e : p->ev1) (void)hipEventDestroy(e);
+    p->ev0.clear();
+    p->ev1.clear();
+    p->rec_name.clear();
+    p->rec_flop.clear();
+    p->prof_names.clear();
+    p->prof_dropped = 0;
+    p->prof_cap = 0;
+    for (int i = 0; i < capacity; ++i) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+            return fail(S2W_EHIP, "hipEventCreate failed");
+        p->ev0.push_back(a);
+        p->ev1.push_back(b);
+    }
+    p->prof_cap = capacity;
+    return S2W_OK;
+}
+
+s2w_status s2w_plan_profile_read(s2w_plan p, int max, char *names, double *total_ms, int64_t *launches,
+                                 double *flop, int *count, int64_t *dropped)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (hipDeviceSynchronize() != hipSuccess) return fail(S2W_EHIP, "device synchronisation failed");
+    const int nn = (int)p->prof_names.size();
+    std::vector<double> ms(nn, 0.0), fl(nn, 0.0);
+    std::vector<int64_t> cnt(nn, 0);
+    for (size_t i = 0; i < p->rec_name.size(); ++i) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, p->ev0[i], p->ev1[i]) != hipSuccess) return fail(S2W_EHIP, "event timing failed");
+        ms[p->rec_name[i]] += t;
+        fl[p->rec_name[i]] += p->rec_flop[i];
+        cnt[p->rec_name[i]] += 1;
+    }
+    const int k = std::min(nn, max);
+    for (int i = 0; i < k; ++i) {
+        if (names) {
+            std::memset(names + 32 * i, 0, 32);
+            std::strncpy(names + 32 * i, p->prof_names[i].c_str(), 31);
+        }
+        if (total_ms) total_ms[i] = ms[i];
+        if (launches) launches[i] = cnt[i];
+        if (flop) flop[i] = fl[i];
+    }
+    if (count) *count = k;
+    if (dropped) *dropped = p->prof_dropped;
+    p->rec_name.clear();
+    p->rec_flop.clear();
+    p->prof_dropped = 0;
+    return S2W_OK;
+}
+
+s2w_status s2w_synthesis_adjoint(s2w_plan p, const double *gf, void *gwav, double *gscal, void *stream)
+{
+    (void)gf; (void)gwav; (void)gscal; (void)stream;
+    if (s2w_status st = check_plan(p)) return st;
+    return fail(S2W_EUNSUPPORTED, "s2w_synthesis_adjoint is not implemented yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Kernel argument blocks and launchers shared by the s2w entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace s2w {
+
+constexpr int MAX_NS = 2;        // scales sharing one recursion pass
+constexpr int MAX_NN = 8;        // azimuthal orders per launch
+constexpr int GAMMA_MAXN = 8;
+
+// sum over l (lanes own theta)
+struct LsumArgs {
+    int L;                       // grid band limit (theta samples, l < L)
+    int mcount;                  // m = 0..mcount-1
+    int nn;                      // number of n values
+    int Lrec;                    // leading size of the recursion tables
+    int nval[MAX_NN], nglob[MAX_NN];
+    const double *A, *B, *S;     // [NG][Lrec][Lrec]
+    const double *smant;         // [NG][Lrec]
+    const int *sexp;
+    const double *cth, *ch, *sh, *ceps, *seps;   // [L]
+    const double *flm;           // [B][flm_m][flm_l] complex
+    int flm_m, flm_l;
+    const double *w[MAX_NS];     // weights [nn][wstride] (wstride 0: shared by all n)
+    int wstride;
+    double *out[MAX_NS];         // [B][nn][mcount][L] complex
+};
+
+// sum over theta (reduction across lanes)
+struct TsumArgs {
+    int L, mcount, nn, Lrec, B;
+    int nval[MAX_NN], nglob[MAX_NN];
+    const double *A, *B_, *S;
+    const double *smant;
+    const int *sexp;
+    const double *cth, *ch, *sh, *ceps, *seps;
+    int npar;                    // parity of n in this launch: sigma index = (m + npar) & 1
+    int M0, M1;                  // number of m with sigma index 0 / 1
+    const double *h[MAX_NS];     // rows [sig][b][m'][ni][c][L]
+    const double *w[MAX_NS];
+    int wstride;
+    double *out[MAX_NS];         // [B][mcount][nn][L] complex
+};
+
+struct DftArgs {
+    const double *in;
+    double *out;
+    long istride, ostride;       // in elements of the row type (complex or real)
+    int nrows;
+    int n, n1, n2;
+    const int *pin, *pout, *pinv;
+    const double *w1, *w2;
+    double scale;
+};
+
+struct GammaArgs {
+    const double *src;
+    double *dst;
+    int B, M, L;                 // maps, m count, theta count
+    int Min, Mout;               // row lengths (m) of the rows over m
+    int nn, ng;                  // n values, gamma samples (2N-1)
+    int nval[GAMMA_MAXN];
+    const double *tw;            // cos/sin of 2 pi k / ng, k < ng
+    double sgn;                  // +1: e^{+i n g}, -1: e^{-i n g}
+    double phr, phi;             // complex phase factor
+    double wscale;               // real scale factor
+    double fm0, fm1;             // r2c side: factor for m = 0 and m >= 1
+    int npar, M0, M1;            // sigma grouping on the r2c side
+};
+
+struct CombineTerm {
+    const double *P;             // [B][L][nn][L] complex
+    int L, nn;
+    double phr, phi;
+};
+
+struct CombineArgs {
+    double *out;                 // [B][L][L] complex
+    int L;
+    int nterms;
+    CombineTerm t[24];
+};
+
+void launch_lsum(const LsumArgs &a, int NS, int B, hipStream_t st);
+void launch_tsum(const TsumArgs &a, int NS, int B, hipStream_t st);
+void launch_gemm(const double *A, const double *Bm, double *C, int M, int N, int K, hipStream_t st);
+void launch_dft_c2r(const DftArgs &a, hipStream_t st);
+void launch_dft_r2c(const DftArgs &a, hipStream_t st);
+void launch_gamma_c2r(const GammaArgs &a, hipStream_t st);
+void launch_gamma_r2c(const GammaArgs &a, hipStream_t st);
+void launch_combine(const CombineArgs &a, int B, hipStream_t st);
+void launch_pack_sigma(const double *in, double *out, int B, int nn, int M, int L, int npar, int M0,
+                       int M1, int dir, hipStream_t st);
+void launch_flm_to_ext(const double *in, double *out, int L, int B, hipStream_t st);
+void launch_flm_from_ext(const double *in, double *out, int L, int B, hipStream_t st);
+
+}  // namespace s2w

@@ -1,0 +1,851 @@
+// HIP kernels for the directional wavelet transform on MW sampling (gfx950).
+//
+// Per-scale Wigner transform, split into:
+//   k_lsum   sum over degree l of a_lmn d^l_mn(theta) for every (m >= 0, n, theta):
+//            lanes own theta samples; d generated on the fly by the scaled
+//            three-term recursion in l, started from the closed form at
+//            l0 = max(|m|,|n|) with per-lane power-of-two rescaling (FP64)
+//   k_tsum   sum over theta of d^l_mn(theta) h(theta) for every l (the
+//            transposed contraction), same recursion, cross-lane reduction
+//            through LDS
+//   k_gemm   exact MW theta quadrature h = T_sigma F (dense FP64)
+//   k_dft_*  odd-length DFTs (2L-1, 2N-1 points) by the prime-factor algorithm
+//   k_gamma_* azimuthal (gamma) DFT over the few nonzero n, fused with the
+//            layout change between the l-stage ((m, n) rows over theta) and
+//            the alpha-stage (rows over m)
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "s2w_kern.h"
+
+namespace s2w {
+
+// ------------------------------------------------------------ helpers ------
+
+__device__ inline void powexp(double x, int p, double &mt, int &et)
+{
+    mt = 1.0;
+    et = 0;
+    if (p == 0) return;
+    int bx;
+    double bm = frexp(x, &bx);
+    while (p) {
+        if (p & 1) {
+            int t;
+            mt = frexp(mt * bm, &t);
+            et += t + bx;
+        }
+        int t2;
+        bm = frexp(bm * bm, &t2);
+        bx = 2 * bx + t2;
+        p >>= 1;
+    }
+}
+
+// d^{l0}_mn(theta) as e * 2^(512 k), |e| in [2^-256, 2^256) or 0.
+__device__ inline void start_value(double mant, int ex, int p1, int p2, double ch, double sh,
+                                   double ceps, double seps, double &e, int &k)
+{
+    if ((ch == 0.0 && p1 > 0) || (sh == 0.0 && p2 > 0) || mant == 0.0) {
+        e = 0.0;
+        k = 0;
+        return;
+    }
+    double mc, ms;
+    int ec, es;
+    powexp(ch, p1, mc, ec);
+    powexp(sh, p2, ms, es);
+    mc *= fma((double)p1, ceps, 1.0);
+    ms *= fma((double)p2, seps, 1.0);
+    const double v = mant * mc * ms;
+    const int E = ex + ec + es;
+    int kk = (E + 256) >> 9;
+    if (kk > 0) kk = 0;
+    e = ldexp(v, E - 512 * kk);
+    k = kk;
+}
+
+// ------------------------------------------------------------- k_lsum ------
+//
+// C_s[b][ni][m][theta] = sum_{l=l0}^{L-1} u_s(l) e^l(theta),
+// u_s(l) = S_l w_s[ni][l] flm[b][m][l]   (so that u e^l = w flm d^l).
+
+template <int T, int NS>
+__global__ __launch_bounds__(64) void k_lsum(const LsumArgs a)
+{
+    const int m = blockIdx.x, ni = blockIdx.y;
+    const int nch = (a.L + 64 * T - 1) / (64 * T);
+    const int b = blockIdx.z / nch, chk = blockIdx.z % nch;
+    const int lane = threadIdx.x;
+    const int n = a.nval[ni], ng = a.nglob[ni];
+    const int am = m, an = n < 0 ? -n : n;
+    const int l0 = am > an ? am : an;
+    const int lmax = a.L;
+
+    __shared__ double2 sAB[64];
+    __shared__ double2 sU[NS][64];
+
+    double c[T], e[T], ep[T], acc[NS][2][T];
+    int k[T];
+    const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
+    const double mant = a.smant[(size_t)ng * a.Lrec + m];
+    const int ex = a.sexp[(size_t)ng * a.Lrec + m];
+    const int p1 = (m + n) < 0 ? -(m + n) : (m + n);
+    const int p2 = (m - n) < 0 ? -(m - n) : (m - n);
+    bool asleep_any = false;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int th = chk * 64 * T + t * 64 + lane;
+        e[t] = 0.0;
+        ep[t] = 0.0;
+        k[t] = 0;
+        c[t] = 0.0;
+        if (th < a.L && l0 < lmax) {
+            c[t] = a.cth[th];
+            start_value(mant, ex, p1, p2, a.ch[th], a.sh[th], a.ceps[th], a.seps[th], e[t], k[t]);
+        }
+        asleep_any |= (k[t] < 0);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) { acc[s][0][t] = 0.0; acc[s][1][t] = 0.0; }
+    }
+    bool anyAsleep = __any(asleep_any);
+
+    for (int lb = l0; lb < lmax; lb += 64) {
+        {
+            const int l = lb + lane;
+            double A = 0.0, Bv = 0.0;
+            double ur[NS], ui[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) { ur[s] = 0.0; ui[s] = 0.0; }
+            if (l < lmax) {
+                A = a.A[tabm + l];
+                Bv = a.B[tabm + l];
+                const double S = a.S[tabm + l];
+                const double *fl = a.flm + (((size_t)b * a.flm_m + m) * a.flm_l + l) * 2;
+                const double fr = fl[0], fi = fl[1];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const double w = S * a.w[s][(size_t)ni * a.wstride + l];
+                    ur[s] = w * fr;
+                    ui[s] = w * fi;
+                }
+            }
+            __syncthreads();
+            sAB[lane] = make_double2(A, Bv);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) sU[s][lane] = make_double2(ur[s], ui[s]);
+            __syncthreads();
+        }
+        const int cnt = (lmax - lb) < 64 ? (lmax - lb) : 64;
+        for (int g = 0; g < cnt; g += 8) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const double2 ab = sAB[g + i];
+                double2 u[NS];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) u[s] = sU[s][g + i];
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        acc[s][0][t] = fma(u[s].x, e[t], acc[s][0][t]);
+                        acc[s][1][t] = fma(u[s].y, e[t], acc[s][1][t]);
+                    }
+                    const double en = fma(fma(ab.x, c[t], -ab.y), e[t], -ep[t]);
+                    ep[t] = e[t];
+                    e[t] = en;
+                }
+            }
+            if (anyAsleep) {
+                bool any = false;
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    if (k[t] < 0) {
+                        if (fabs(e[t]) > 0x1p256) {
+                            e[t] *= 0x1p-512;
+                            ep[t] *= 0x1p-512;
+                            k[t] += 1;
+                            if (k[t] == 0) {
+#pragma unroll
+                                for (int s = 0; s < NS; ++s) { acc[s][0][t] = 0.0; acc[s][1][t] = 0.0; }
+                            }
+                        }
+                    }
+                    any |= (k[t] < 0);
+                }
+                anyAsleep = __any(any);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int th = chk * 64 * T + t * 64 + lane;
+        if (th >= a.L) continue;
+        const bool live = (k[t] == 0) && (l0 < lmax);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            double *o = a.out[s] + ((((size_t)b * a.nn + ni) * a.mcount + m) * a.L + th) * 2;
+            o[0] = live ? acc[s][0][t] : 0.0;
+            o[1] = live ? acc[s][1][t] : 0.0;
+        }
+    }
+}
+
+// ------------------------------------------------------------- k_tsum ------
+//
+// P_s[b][m][ni][l] = S_l w_s[ni][l] sum_theta e^l(theta) h_s(theta)   (l >= l0, else 0)
+// h_s rows (re, im) come from the sigma-grouped layout [sig][b][m'][ni][c][theta].
+
+template <int T, int NS>
+__global__ __launch_bounds__(64) void k_tsum(const TsumArgs a)
+{
+    constexpr int LB = 32 / NS;          // l-steps per reduction block: 2*NS*LB = 64 entries
+    constexpr int K = 2 * NS * LB;
+    const int m = blockIdx.x, ni = blockIdx.y;
+    const int b = blockIdx.z;
+    const int lane = threadIdx.x;
+    const int n = a.nval[ni], ng = a.nglob[ni];
+    const int an = n < 0 ? -n : n;
+    const int l0 = m > an ? m : an;
+    const int lmax = a.L;
+
+    __shared__ double red[64][K + 1];
+    __shared__ double2 sAB[LB];
+
+    // input rows
+    const int sig = (m + a.npar) & 1;
+    const int mp = m >> 1;
+    const size_t rbase = (sig == 0 ? 0 : (size_t)a.B * a.M0 * a.nn * 2)
+                         + ((((size_t)b * (sig == 0 ? a.M0 : a.M1) + mp) * a.nn + ni) * 2);
+
+    double c[T], e[T], ep[T], hr[NS][T], hi[NS][T];
+    int k[T];
+    const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
+    const double mant = a.smant[(size_t)ng * a.Lrec + m];
+    const int ex = a.sexp[(size_t)ng * a.Lrec + m];
+    const int p1 = (m + n) < 0 ? -(m + n) : (m + n);
+    const int p2 = (m - n) < 0 ? -(m - n) : (m - n);
+    bool asleep_any = false;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int th = t * 64 + lane;
+        e[t] = 0.0;
+        ep[t] = 0.0;
+        k[t] = 0;
+        c[t] = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) { hr[s][t] = 0.0; hi[s][t] = 0.0; }
+        if (th < a.L && l0 < lmax) {
+            c[t] = a.cth[th];
+            start_value(mant, ex, p1, p2, a.ch[th], a.sh[th], a.ceps[th], a.seps[th], e[t], k[t]);
+            if (k[t] == 0) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    hr[s][t] = a.h[s][(rbase + 0) * a.L + th];
+                    hi[s][t] = a.h[s][(rbase + 1) * a.L + th];
+                }
+            }
+        }
+        asleep_any |= (k[t] < 0);
+    }
+    bool anyAsleep = __any(asleep_any);
+
+    for (int lb = l0; lb < lmax; lb += LB) {
+        __syncthreads();
+        if (lane < LB) {
+            const int l = lb + lane;
+            double A = 0.0, Bv = 0.0;
+            if (l < lmax) { A = a.A[tabm + l]; Bv = a.B_[tabm + l]; }
+            sAB[lane] = make_double2(A, Bv);
+        }
+        __syncthreads();
+        for (int i = 0; i < LB; ++i) {
+            const double2 ab = sAB[i];
+            double pr[NS], pi[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) { pr[s] = 0.0; pi[s] = 0.0; }
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    pr[s] = fma(e[t], hr[s][t], pr[s]);
+                    pi[s] = fma(e[t], hi[s][t], pi[s]);
+                }
+                const double en = fma(fma(ab.x, c[t], -ab.y), e[t], -ep[t]);
+                ep[t] = e[t];
+                e[t] = en;
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                red[lane][(s * LB + i) * 2 + 0] = pr[s];
+                red[lane][(s * LB + i) * 2 + 1] = pi[s];
+            }
+            if (anyAsleep && ((i & 7) == 7)) {
+                bool any = false;
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    if (k[t] < 0) {
+                        if (fabs(e[t]) > 0x1p256) {
+                            e[t] *= 0x1p-512;
+                            ep[t] *= 0x1p-512;
+                            k[t] += 1;
+                            if (k[t] == 0) {
+                                const int th = t * 64 + lane;
+#pragma unroll
+                                for (int s = 0; s < NS; ++s) {
+                                    hr[s][t] = a.h[s][(rbase + 0) * a.L + th];
+                                    hi[s][t] = a.h[s][(rbase + 1) * a.L + th];
+                                }
+                            }
+                        }
+                    }
+                    any |= (k[t] < 0);
+                }
+                anyAsleep = __any(any);
+            }
+        }
+        __syncthreads();
+        // lane j sums entry j over the 64 source lanes
+        {
+            const int j = lane;
+            double v = 0.0;
+#pragma unroll 8
+            for (int src = 0; src < 64; ++src) v += red[src][j];
+            const int s = j / (2 * LB);
+            const int i = (j / 2) % LB;
+            const int cc = j & 1;
+            const int l = lb + i;
+            if (l < lmax) {
+                const double S = a.S[tabm + l];
+                const double w = a.w[s][(size_t)ni * a.wstride + l];
+                a.out[s][((((size_t)b * a.mcount + m) * a.nn + ni) * a.L + l) * 2 + cc] = v * S * w;
+            }
+        }
+    }
+    // zero the l < l0 part of the output rows
+    for (int l = lane; l < l0 && l < lmax; l += 64) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            double *o = a.out[s] + ((((size_t)b * a.mcount + m) * a.nn + ni) * a.L + l) * 2;
+            o[0] = 0.0;
+            o[1] = 0.0;
+        }
+    }
+}
+
+// ------------------------------------------------------------- k_gemm ------
+// C[M][N] = A[M][K] * Bm[K][N], row-major, FP64.  64x64 tiles, 256 threads, 4x4 per thread.
+
+__global__ __launch_bounds__(256) void k_gemm(const double *__restrict__ A, const double *__restrict__ Bm,
+                                              double *__restrict__ C, int M, int N, int K)
+{
+    __shared__ double As[16][64 + 1];
+    __shared__ double Bs[16][64 + 1];
+    const int tid = threadIdx.x;
+    const int tr = tid / 16, tc = tid % 16;
+    const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        // load A tile 64 x 16 and B tile 16 x 64
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int idx = tid + r * 256;         // 0..1023
+            const int ar = idx / 16, ak = idx % 16;
+            const int gr = row0 + ar, gk = k0 + ak;
+            As[ak][ar] = (gr < M && gk < K) ? A[(size_t)gr * K + gk] : 0.0;
+            const int bk = idx / 64, bc = idx % 64;
+            const int gk2 = k0 + bk, gc = col0 + bc;
+            Bs[bk][bc] = (gk2 < K && gc < N) ? Bm[(size_t)gk2 * N + gc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = As[kk][tr + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tc + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int gr = row0 + tr + 16 * i, gc = col0 + tc + 16 * j;
+            if (gr < M && gc < N) C[(size_t)gr * N + gc] = acc[i][j];
+        }
+}
+
+// -------------------------------------------------------------- DFTs -------
+//
+// Prime-factor DFT of length n = n1 n2 on a complex row in LDS.  The input is
+// placed at LDS position p = m1 n2 + m2 for input index (m1 n2 + m2 n1) mod n
+// (table pin[p]); stage 1 transforms over m1 (length n1), stage 2 over m2
+// (length n2); output (a1, a2) sits at LDS position a1 n2 + a2 and is frequency
+// pout[p] = (a1 e1 + a2 e2) mod n.  No twiddles between stages.
+
+__device__ inline void pfa_stages(double2 *Z, double2 *Y, const double2 *w1, const double2 *w2, int n1,
+                                  int n2, double sgn)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    // stage 1: Y[a1][m2] = sum_m1 Z[m1][m2] w1^{sgn m1 a1}
+    {
+        const int nb1 = (n1 + 3) / 4, nb2 = (n2 + 3) / 4;
+        for (int task = tid; task < nb1 * nb2; task += nt) {
+            const int a1b = (task / nb2) * 4, m2b = (task % nb2) * 4;
+            double2 acc[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+            int tw[4], st[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { st[i] = (a1b + i) % n1; tw[i] = 0; }
+            for (int m1 = 0; m1 < n1; ++m1) {
+                double2 z[4], w[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int m2 = m2b + j < n2 ? m2b + j : n2 - 1;
+                    z[j] = Z[m1 * n2 + m2];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    w[i] = w1[tw[i]];
+                    w[i].y *= sgn;
+                    tw[i] += st[i];
+                    if (tw[i] >= n1) tw[i] -= n1;
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        acc[i][j].x = fma(z[j].x, w[i].x, fma(-z[j].y, w[i].y, acc[i][j].x));
+                        acc[i][j].y = fma(z[j].x, w[i].y, fma(z[j].y, w[i].x, acc[i][j].y));
+                    }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (a1b + i < n1 && m2b + j < n2) Y[(a1b + i) * n2 + m2b + j] = acc[i][j];
+        }
+    }
+    __syncthreads();
+    // stage 2: Z[a1][a2] = sum_m2 Y[a1][m2] w2^{sgn m2 a2}
+    {
+        const int nb1 = (n1 + 3) / 4, nb2 = (n2 + 3) / 4;
+        for (int task = tid; task < nb1 * nb2; task += nt) {
+            const int a1b = (task / nb2) * 4, a2b = (task % nb2) * 4;
+            double2 acc[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+            int tw[4], st[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) { st[j] = (a2b + j) % n2; tw[j] = 0; }
+            for (int m2 = 0; m2 < n2; ++m2) {
+                double2 y[4], w[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int a1 = a1b + i < n1 ? a1b + i : n1 - 1;
+                    y[i] = Y[a1 * n2 + m2];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    w[j] = w2[tw[j]];
+                    w[j].y *= sgn;
+                    tw[j] += st[j];
+                    if (tw[j] >= n2) tw[j] -= n2;
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        acc[i][j].x = fma(y[i].x, w[j].x, fma(-y[i].y, w[j].y, acc[i][j].x));
+                        acc[i][j].y = fma(y[i].x, w[j].y, fma(y[i].y, w[j].x, acc[i][j].y));
+                    }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (a1b + i < n1 && a2b + j < n2) Z[(a1b + i) * n2 + a2b + j] = acc[i][j];
+        }
+    }
+    __syncthreads();
+}
+
+// c2r: two Hermitian rows E1, E2 (m = 0..Lh-1, complex) -> two real rows of length n.
+// x(a) = scale * (Re E_0 + 2 Re sum_{m>=1} E_m e^{+2 pi i m a/n})
+__global__ __launch_bounds__(128) void k_dft_c2r(const DftArgs a)
+{
+    extern __shared__ double2 smem[];
+    const int n = a.n, n1 = a.n1, n2 = a.n2, Lh = (n + 1) / 2;
+    double2 *Z = smem, *Y = smem + n;
+    const double2 *w1 = reinterpret_cast<const double2 *>(a.w1), *w2 = reinterpret_cast<const double2 *>(a.w2);
+    const int tid = threadIdx.x;
+    const long r1 = 2L * blockIdx.x, r2 = r1 + 1;
+    const bool has2 = r2 < a.nrows;
+    const double2 *E1 = reinterpret_cast<const double2 *>(a.in) + r1 * a.istride;
+    const double2 *E2 = reinterpret_cast<const double2 *>(a.in) + r2 * a.istride;
+    for (int p = tid; p < n; p += blockDim.x) {
+        const int mm = a.pin[p];
+        double2 z1, z2 = make_double2(0.0, 0.0);
+        if (mm < Lh) {
+            z1 = E1[mm];
+            if (has2) z2 = E2[mm];
+            if (mm == 0) { z1.y = 0.0; z2.y = 0.0; }
+        } else {
+            z1 = E1[n - mm];
+            z1.y = -z1.y;
+            if (has2) { z2 = E2[n - mm]; z2.y = -z2.y; }
+        }
+        // Z = z1 + i z2
+        Z[p] = make_double2(a.scale * (z1.x - z2.y), a.scale * (z1.y + z2.x));
+    }
+    __syncthreads();
+    pfa_stages(Z, Y, w1, w2, n1, n2, 1.0);
+    double *o1 = a.out + r1 * a.ostride, *o2 = a.out + r2 * a.ostride;
+    for (int p = tid; p < n; p += blockDim.x) {
+        const int aa = a.pout[p];
+        o1[aa] = Z[p].x;
+        if (has2) o2[aa] = Z[p].y;
+    }
+}
+
+// r2c: two real rows x1, x2 of length n -> X_m = scale * sum_a x(a) e^{-2 pi i m a/n}, m = 0..Lh-1.
+__global__ __launch_bounds__(128) void k_dft_r2c(const DftArgs a)
+{
+    extern __shared__ double2 smem[];
+    const int n = a.n, n1 = a.n1, n2 = a.n2, Lh = (n + 1) / 2;
+    double2 *Z = smem, *Y = smem + n;
+    const double2 *w1 = reinterpret_cast<const double2 *>(a.w1), *w2 = reinterpret_cast<const double2 *>(a.w2);
+    const int tid = threadIdx.x;
+    const long r1 = 2L * blockIdx.x, r2 = r1 + 1;
+    const bool has2 = r2 < a.nrows;
+    const double *x1 = a.in + r1 * a.istride, *x2 = a.in + r2 * a.istride;
+    for (int p = tid; p < n; p += blockDim.x) {
+        const int mm = a.pin[p];
+        Z[p] = make_double2(x1[mm], has2 ? x2[mm] : 0.0);
+    }
+    __syncthreads();
+    pfa_stages(Z, Y, w1, w2, n1, n2, -1.0);
+    double2 *O1 = reinterpret_cast<double2 *>(a.out) + r1 * a.ostride;
+    double2 *O2 = reinterpret_cast<double2 *>(a.out) + r2 * a.ostride;
+    for (int mm = tid; mm < Lh; mm += blockDim.x) {
+        const double2 X = Z[a.pinv[mm]];
+        const double2 Xc = Z[a.pinv[mm == 0 ? 0 : n - mm]];
+        // X1 = (X + conj(Xc))/2, X2 = (X - conj(Xc))/(2i)
+        O1[mm] = make_double2(0.5 * a.scale * (X.x + Xc.x), 0.5 * a.scale * (X.y - Xc.y));
+        if (has2) O2[mm] = make_double2(0.5 * a.scale * (X.y + Xc.y), -0.5 * a.scale * (X.x - Xc.x));
+    }
+}
+
+// --------------------------------------------------------- gamma stages ----
+//
+// c2r side: E[b][g][theta][m] = ph * sum_ni C[b][ni][m][theta] e^{+i n_ni gamma_g} (complex)
+// 16 x 16 (m, theta) tiles through LDS.
+
+__global__ __launch_bounds__(256) void k_gamma_c2r(const GammaArgs a)
+{
+    __shared__ double2 tile[GAMMA_MAXN][16][17];
+    const int tid = threadIdx.x;
+    const int m0 = blockIdx.x * 16, th0 = blockIdx.y * 16, b = blockIdx.z;
+    // load C tiles with theta fastest
+    {
+        const int tt = tid % 16, tm = tid / 16;
+        const int m = m0 + tm, th = th0 + tt;
+        for (int ni = 0; ni < a.nn; ++ni) {
+            double2 v = make_double2(0.0, 0.0);
+            if (m < a.M && th < a.L)
+                v = reinterpret_cast<const double2 *>(a.src)[(((size_t)b * a.nn + ni) * a.M + m) * a.L + th];
+            tile[ni][tm][tt] = v;
+        }
+    }
+    __syncthreads();
+    const int tm = tid % 16, tt = tid / 16;
+    const int m = m0 + tm, th = th0 + tt;
+    if (m >= a.M || th >= a.L) return;
+    for (int g = 0; g < a.ng; ++g) {
+        double re = 0.0, im = 0.0;
+        for (int ni = 0; ni < a.nn; ++ni) {
+            int idx = (a.nval[ni] * g) % a.ng;
+            if (idx < 0) idx += a.ng;
+            const double cw = a.tw[2 * idx], sw = a.sgn * a.tw[2 * idx + 1];
+            const double2 v = tile[ni][tm][tt];
+            re += v.x * cw - v.y * sw;
+            im += v.x * sw + v.y * cw;
+        }
+        const double fm = (m == 0) ? a.fm0 : a.fm1;
+        const double outr = a.phr * re - a.phi * im;
+        const double outi = a.phr * im + a.phi * re;
+        reinterpret_cast<double2 *>(a.dst)[(((size_t)b * a.ng + g) * a.L + th) * a.Mout + m] =
+            make_double2(a.wscale * fm * outr, a.wscale * fm * outi);
+    }
+}
+
+// r2c side: F[sig][b][m'][ni][c][theta] = w * fm(m) * ph * sum_g X[b][g][theta][m] e^{-i n_ni gamma_g}
+__global__ __launch_bounds__(256) void k_gamma_r2c(const GammaArgs a)
+{
+    __shared__ double tile[GAMMA_MAXN][2][16][17];
+    const int tid = threadIdx.x;
+    const int m0 = blockIdx.x * 16, th0 = blockIdx.y * 16, b = blockIdx.z;
+    {
+        const int tm = tid % 16, tt = tid / 16;
+        const int m = m0 + tm, th = th0 + tt;
+        double accr[GAMMA_MAXN], acci[GAMMA_MAXN];
+        for (int ni = 0; ni < a.nn; ++ni) { accr[ni] = 0.0; acci[ni] = 0.0; }
+        if (m < a.M && th < a.L) {
+            for (int g = 0; g < a.ng; ++g) {
+                const double2 v =
+                    reinterpret_cast<const double2 *>(a.src)[(((size_t)b * a.ng + g) * a.L + th) * a.Min + m];
+                for (int ni = 0; ni < a.nn; ++ni) {
+                    int idx = (a.nval[ni] * g) % a.ng;
+                    if (idx < 0) idx += a.ng;
+                    const double cw = a.tw[2 * idx], sw = a.sgn * a.tw[2 * idx + 1];
+                    accr[ni] += v.x * cw - v.y * sw;
+                    acci[ni] += v.x * sw + v.y * cw;
+                }
+            }
+        }
+        const double fm = (m == 0) ? a.fm0 : a.fm1;
+        for (int ni = 0; ni < a.nn; ++ni) {
+            const double re = a.phr * accr[ni] - a.phi * acci[ni];
+            const double im = a.phr * acci[ni] + a.phi * accr[ni];
+            tile[ni][0][tm][tt] = a.wscale * fm * re;
+            tile[ni][1][tm][tt] = a.wscale * fm * im;
+        }
+    }
+    __syncthreads();
+    const int tt = tid % 16, tm = tid / 16;
+    const int m = m0 + tm, th = th0 + tt;
+    if (m >= a.M || th >= a.L) return;
+    const int sig = (m + a.npar) & 1;
+    const int mp = m >> 1;
+    const size_t base = (sig == 0 ? 0 : (size_t)a.B * a.M0 * a.nn * 2)
+                        + (((size_t)b * (sig == 0 ? a.M0 : a.M1) + mp) * a.nn) * 2;
+    for (int ni = 0; ni < a.nn; ++ni) {
+        a.dst[(base + (size_t)ni * 2 + 0) * a.L + th] = tile[ni][0][tm][tt];
+        a.dst[(base + (size_t)ni * 2 + 1) * a.L + th] = tile[ni][1][tm][tt];
+    }
+}
+
+// -------------------------------------------------------------- combine ----
+// fhat[b][m][l] = sum_terms ph_t * sum_ni P_t[b][m][ni][l]   (FP64, fixed order)
+__global__ __launch_bounds__(256) void k_combine(const CombineArgs a)
+{
+    const int l = blockIdx.x * 256 + threadIdx.x;
+    const int m = blockIdx.y, b = blockIdx.z;
+    if (l >= a.L) return;
+    double re = 0.0, im = 0.0;
+    if (l >= m) {
+        for (int t = 0; t < a.nterms; ++t) {
+            const CombineTerm &c = a.t[t];
+            if (m >= c.L || l >= c.L) continue;
+            double sr = 0.0, si = 0.0;
+            for (int ni = 0; ni < c.nn; ++ni) {
+                const double *p = c.P + ((((size_t)b * c.L + m) * c.nn + ni) * c.L + l) * 2;
+                sr += p[0];
+                si += p[1];
+            }
+            re += c.phr * sr - c.phi * si;
+            im += c.phr * si + c.phi * sr;
+        }
+    }
+    double *o = a.out + (((size_t)b * a.L + m) * a.L + l) * 2;
+    o[0] = re;
+    o[1] = im;
+}
+
+// ------------------------------------------------- sigma-grouped rows ----
+// [b][ni][m][theta] complex  <->  [sig][b][m'][ni][c][theta] real rows, sig = (m + npar) & 1
+__global__ void k_pack_sigma(const double *in, double *out, int B, int nn, int M, int L, int npar,
+                             int M0, int M1, int dir)
+{
+    const int th = blockIdx.x * 256 + threadIdx.x;
+    const int m = blockIdx.y;
+    const int bn = blockIdx.z;          // b * nn + ni
+    if (th >= L) return;
+    const int b = bn / nn, ni = bn % nn;
+    const int sig = (m + npar) & 1, mp = m >> 1;
+    const size_t base = (sig == 0 ? 0 : (size_t)B * M0 * nn * 2)
+                        + ((((size_t)b * (sig == 0 ? M0 : M1) + mp) * nn + ni) * 2);
+    const size_t ci = (((size_t)b * nn + ni) * M + m) * L + th;
+    if (dir == 0) {
+        out[(base + 0) * L + th] = in[ci * 2 + 0];
+        out[(base + 1) * L + th] = in[ci * 2 + 1];
+    } else {
+        out[ci * 2 + 0] = in[(base + 0) * L + th];
+        out[ci * 2 + 1] = in[(base + 1) * L + th];
+    }
+}
+
+// ----------------------------------------------------- harmonic layouts ----
+// internal [b][m][l] (m >= 0)  <->  external [b][l][m + L - 1] (all m)
+__global__ void k_flm_to_ext(const double *in, double *out, int L, int B)
+{
+    const int l = blockIdx.x, b = blockIdx.y;
+    for (int mm = threadIdx.x; mm < 2 * L - 1; mm += blockDim.x) {
+        const int m = mm - (L - 1);
+        double re = 0.0, im = 0.0;
+        if (l >= (m < 0 ? -m : m)) {
+            const int am = m < 0 ? -m : m;
+            const double *p = in + (((size_t)b * L + am) * L + l) * 2;
+            re = p[0];
+            im = p[1];
+            if (m < 0) {  // f_{l,-m} = (-1)^m conj(f_lm)
+                im = -im;
+                if (am & 1) { re = -re; im = -im; }
+            }
+        }
+        double *o = out + (((size_t)b * L + l) * (2 * L - 1) + mm) * 2;
+        o[0] = re;
+        o[1] = im;
+    }
+}
+
+__global__ void k_flm_from_ext(const double *in, double *out, int L, int B)
+{
+    const int m = blockIdx.x, b = blockIdx.y;
+    for (int l = threadIdx.x; l < L; l += blockDim.x) {
+        double re = 0.0, im = 0.0;
+        if (l >= m) {
+            const double *p = in + (((size_t)b * L + l) * (2 * L - 1) + (m + L - 1)) * 2;
+            re = p[0];
+            im = p[1];
+        }
+        double *o = out + (((size_t)b * L + m) * L + l) * 2;
+        o[0] = re;
+        o[1] = im;
+    }
+}
+
+// ------------------------------------------------------------- launchers ---
+
+template <int T, int NS>
+static void launch_lsum_t(const LsumArgs &a, int B, hipStream_t st)
+{
+    const int nch = (a.L + 64 * T - 1) / (64 * T);
+    dim3 grid(a.mcount, a.nn, B * nch);
+    hipLaunchKernelGGL((k_lsum<T, NS>), grid, dim3(64), 0, st, a);
+}
+
+void launch_lsum(const LsumArgs &a, int NS, int B, hipStream_t st)
+{
+    const int T = a.L > 512 ? 8 : (a.L > 256 ? 8 : (a.L > 128 ? 4 : (a.L > 64 ? 2 : 1)));
+    if (NS == 1) {
+        switch (T) {
+            case 1: launch_lsum_t<1, 1>(a, B, st); break;
+            case 2: launch_lsum_t<2, 1>(a, B, st); break;
+            case 4: launch_lsum_t<4, 1>(a, B, st); break;
+            default: launch_lsum_t<8, 1>(a, B, st); break;
+        }
+    } else {
+        switch (T) {
+            case 1: launch_lsum_t<1, 2>(a, B, st); break;
+            case 2: launch_lsum_t<2, 2>(a, B, st); break;
+            case 4: launch_lsum_t<4, 2>(a, B, st); break;
+            default: launch_lsum_t<8, 2>(a, B, st); break;
+        }
+    }
+}
+
+template <int T, int NS>
+static void launch_tsum_t(const TsumArgs &a, int B, hipStream_t st)
+{
+    dim3 grid(a.mcount, a.nn, B);
+    hipLaunchKernelGGL((k_tsum<T, NS>), grid, dim3(64), 0, st, a);
+}
+
+void launch_tsum(const TsumArgs &a, int NS, int B, hipStream_t st)
+{
+    // one wave covers all theta: T = ceil(L / 64)
+    const int T = (a.L + 63) / 64;
+    if (NS == 1) {
+        if (T <= 1) launch_tsum_t<1, 1>(a, B, st);
+        else if (T <= 2) launch_tsum_t<2, 1>(a, B, st);
+        else if (T <= 4) launch_tsum_t<4, 1>(a, B, st);
+        else if (T <= 8) launch_tsum_t<8, 1>(a, B, st);
+        else launch_tsum_t<16, 1>(a, B, st);
+    } else {
+        if (T <= 1) launch_tsum_t<1, 2>(a, B, st);
+        else if (T <= 2) launch_tsum_t<2, 2>(a, B, st);
+        else if (T <= 4) launch_tsum_t<4, 2>(a, B, st);
+        else if (T <= 8) launch_tsum_t<8, 2>(a, B, st);
+        else launch_tsum_t<16, 2>(a, B, st);
+    }
+}
+
+void launch_gemm(const double *A, const double *Bm, double *C, int M, int N, int K, hipStream_t st)
+{
+    if (M <= 0 || N <= 0) return;
+    dim3 grid((N + 63) / 64, (M + 63) / 64);
+    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, A, Bm, C, M, N, K);
+}
+
+static size_t dft_smem(const DftArgs &a)
+{
+    return sizeof(double2) * (size_t)(2 * a.n);
+}
+
+void launch_dft_c2r(const DftArgs &a, hipStream_t st)
+{
+    if (a.nrows <= 0) return;
+    dim3 grid((a.nrows + 1) / 2);
+    hipLaunchKernelGGL(k_dft_c2r, grid, dim3(128), dft_smem(a), st, a);
+}
+
+void launch_dft_r2c(const DftArgs &a, hipStream_t st)
+{
+    if (a.nrows <= 0) return;
+    dim3 grid((a.nrows + 1) / 2);
+    hipLaunchKernelGGL(k_dft_r2c, grid, dim3(128), dft_smem(a), st, a);
+}
+
+void launch_gamma_c2r(const GammaArgs &a, hipStream_t st)
+{
+    dim3 grid((a.M + 15) / 16, (a.L + 15) / 16, a.B);
+    hipLaunchKernelGGL(k_gamma_c2r, grid, dim3(256), 0, st, a);
+}
+
+void launch_gamma_r2c(const GammaArgs &a, hipStream_t st)
+{
+    dim3 grid((a.M + 15) / 16, (a.L + 15) / 16, a.B);
+    hipLaunchKernelGGL(k_gamma_r2c, grid, dim3(256), 0, st, a);
+}
+
+void launch_combine(const CombineArgs &a, int B, hipStream_t st)
+{
+    dim3 grid((a.L + 255) / 256, a.L, B);
+    hipLaunchKernelGGL(k_combine, grid, dim3(256), 0, st, a);
+}
+
+void launch_pack_sigma(const double *in, double *out, int B, int nn, int M, int L, int npar, int M0,
+                       int M1, int dir, hipStream_t st)
+{
+    dim3 grid((L + 255) / 256, M, B * nn);
+    hipLaunchKernelGGL(k_pack_sigma, grid, dim3(256), 0, st, in, out, B, nn, M, L, npar, M0, M1, dir);
+}
+
+void launch_flm_to_ext(const double *in, double *out, int L, int B, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_flm_to_ext, dim3(L, B), dim3(256), 0, st, in, out, L, B);
+}
+
+void launch_flm_from_ext(const double *in, double *out, int L, int B, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_flm_from_ext, dim3(L, B), dim3(256), 0, st, in, out, L, B);
+}
+
+}  // namespace s2w
