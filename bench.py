@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 PEAKS = {  # MI355X published peaks
     "fp64_valu": 78.6e12,
     "fp32_valu": 157.3e12,
+    "fp32_mfma": 157.3e12,
     "hbm": 8.0e12,
 }
 
@@ -40,8 +41,8 @@ def parse():
     ap.add_argument("--N", type=int, default=8)
     ap.add_argument("--lam", type=float, default=2.0)
     ap.add_argument("--J0", type=int, default=0)
-    ap.add_argument("--batch", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp64"], default="fp64")
+    ap.add_argument("--batch", type=int, default=None, help="maps per call (default 1 for fp64, 64 for mixed)")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     return ap.parse_args()
@@ -94,13 +95,19 @@ def main():
     import paper_2402_01282_amd as s2w
     import synthetic
 
-    L, N, lam, J0, B = args.L, args.N, args.lam, args.J0, args.batch
+    L, N, lam, J0 = args.L, args.N, args.lam, args.J0
+    mixed = args.precision == "mixed"
+    B = args.batch if args.batch is not None else (64 if mixed else 1)
     print(f"[bench] L={L} N={N} lambda={lam} J0={J0} batch={B} precision={args.precision}",
           file=sys.stderr, flush=True)
-    plan = s2w.Plan(L, N, lam, J0, batch=B, device=0)
-    # synthetic Gaussian random fields, synthesised on the GPU
-    flm = np.stack([synthetic.sphere_flm(L, synthetic.stream_key(4, b)) for b in range(B)])
-    f = plan.sht_inverse(torch.from_numpy(flm).cuda())
+    plan = s2w.Plan(L, N, lam, J0, batch=B, device=0, precision=s2w.S2W_MIXED if mixed else s2w.S2W_FP64)
+    # synthetic Gaussian random fields, synthesised on the GPU (FP64 inverse SHT, one map per call)
+    synth = s2w.Plan(L, 1, lam, 0, batch=1, device=0)
+    f = torch.empty(plan.map_shape, dtype=torch.float64, device="cuda")
+    for b in range(B):
+        flm = synthetic.sphere_flm(L, synthetic.stream_key(4, b))
+        f[b].copy_(synth.sht_inverse(torch.from_numpy(flm[None].copy()).cuda())[0])
+    del synth
     wav = plan.empty_wav()
     scal = torch.empty(plan.scal_shape, dtype=torch.float64, device="cuda")
     f2 = torch.empty_like(f)
@@ -143,11 +150,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic Gaussian random fields, C_l = 1/(l+1)^2, synthesised on the GPU",
-        "config": {"workload": f"sphere directional wavelets analysis+synthesis, FP64, L={L}, N={N}, "
+        "config": {"workload": f"sphere directional wavelets analysis+synthesis, "
+                               f"{'mixed FP32/FP64 batched' if mixed else 'FP64'}, L={L}, N={N}, "
                                f"lambda={lam:g}, J0={J0}, batch={B}",
-                   "L": L, "N": N, "lambda": lam, "J0": J0, "batch": B, "form": "fp64"},
+                   "L": L, "N": N, "lambda": lam, "J0": J0, "batch": B, "form": args.precision},
         "coefficients_per_s": maps_per_s * coeffs,
         "round_trip_rel_err": err,
     }
@@ -155,8 +163,11 @@ def main():
         tot = sum(v[0] for v in kern.values())
         name, (ms, cnt, flop) = max(kern.items(), key=lambda kv: kv[1][0])
         achieved = flop / (ms * 1e-3) if ms > 0 else 0.0
-        peak = PEAKS["fp64_valu"]
-        out["roofline"] = {"bound": "alu", "kernel": name, "achieved": achieved / 1e12, "peak": peak / 1e12,
+        if name.endswith("_mm") or name.endswith("_f32"):
+            peak, bound = PEAKS["fp32_mfma"], "mfma"
+        else:
+            peak, bound = PEAKS["fp64_valu"], "alu"
+        out["roofline"] = {"bound": bound, "kernel": name, "achieved": achieved / 1e12, "peak": peak / 1e12,
                            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                            "avg_launch_ms": ms / max(cnt, 1), "launches": cnt,
                            "algorithmic_flop_per_launch": flop / max(cnt, 1)}

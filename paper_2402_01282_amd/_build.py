@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libs2w.so")
-SOURCES = ["s2w_api.hip", "s2w_kernels.hip", "s2w_host.cpp"]
+SOURCES = ["s2w_api.hip", "s2w_kernels.hip", "s2w_mixed.hip", "s2w_host.cpp"]
 ARCH = os.environ.get("S2W_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -34,6 +34,7 @@ struct DevGrid {
     int L = 0;
     double *cth = nullptr, *ch = nullptr, *sh = nullptr, *ceps = nullptr, *seps = nullptr;
     double *T[2] = {nullptr, nullptr};
+    float *T32[2] = {nullptr, nullptr};
     DevDft dft;
 };
 
@@ -168,6 +169,10 @@ bool make_grid(s2w_plan p, int L)
         std::vector<double> T;
         s2w::theta_matrix(L, si == 0 ? 1 : -1, T);
         if (!upload(p, g.T[si], T)) return false;
+        if (p->prec == S2W_MIXED) {
+            std::vector<float> T32(T.begin(), T.end());
+            if (!upload(p, g.T32[si], T32)) return false;
+        }
     }
     const int n = 2 * L - 1;
     s2w::PfaPlan pp;
@@ -205,7 +210,7 @@ bool make_gamma_tw(s2w_plan p, int ng)
     return true;
 }
 
-DftArgs dft_args(const DevGrid &g, const double *in, long istride, double *out, long ostride, int nrows,
+DftArgs dft_args(const DevGrid &g, const void *in, long istride, void *out, long ostride, int nrows,
                  double scale)
 {
     DftArgs a{};
@@ -374,6 +379,94 @@ void sht_inverse_internal(s2w_plan p, const double *flm_in, double *f, hipStream
     { const DftArgs da_ = dft_args(g, p->bufB, L, f, na, p->B * L, 1.0); Prof pr_(p, "dft_c2r", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_c2r(da_, st); }
 }
 
+// ---- mixed-precision stages (FP32 arrays, FP64 recursion and scale sums) ----
+
+void theta_quadrature32(s2w_plan p, const DevGrid &g, const float *F, float *H, int M, int nn, int npar,
+                        hipStream_t st)
+{
+    int M0, M1;
+    sig_counts(M, npar, M0, M1);
+    const size_t r0 = (size_t)p->B * M0 * nn * 2, r1 = (size_t)p->B * M1 * nn * 2;
+    {
+        Prof pr_(p, "gemm_theta_f32", 2.0 * (double)r0 * g.L * g.L, st);
+        s2w::launch_gemm_f32(F, g.T32[0], H, (int)r0, g.L, g.L, st);
+    }
+    {
+        Prof pr_(p, "gemm_theta_f32", 2.0 * (double)r1 * g.L * g.L, st);
+        s2w::launch_gemm_f32(F + r0 * g.L, g.T32[1], H + r0 * g.L, (int)r1, g.L, g.L, st);
+    }
+}
+
+// maps (FP64) -> flm (FP64 [B][L][L]) with FP32 DFT / quadrature and the batched theta-sum
+void sht_forward_mixed(s2w_plan p, const double *f, double *flm_out, hipStream_t st)
+{
+    const DevGrid &g = p->grids[p->L];
+    const int L = p->L, na = 2 * L - 1;
+    float *A32 = (float *)p->bufA, *B32 = (float *)p->bufB, *C32 = (float *)p->bufC;
+    {
+        const DftArgs da = dft_args(g, f, na, A32, L, p->B * L, 2.0 * M_PI / na);
+        Prof pr_(p, "dft_r2c_f32", dft_flop(da.n, da.nrows), st);
+        s2w::launch_dft_r2c(da, st, true, true);
+    }
+    std::vector<int> n0{0};
+    GammaArgs ga = gamma_args(p, L, L, L, L, n0, 1);
+    ga.src = A32;
+    ga.dst = B32;
+    ga.sgn = -1.0;
+    sig_counts(L, 0, ga.M0, ga.M1);
+    {
+        Prof pr_(p, "gamma_r2c_f32", 8.0 * ga.B * ga.M * ga.L, st);
+        s2w::launch_gamma_r2c(ga, st, true);
+    }
+    theta_quadrature32(p, g, B32, C32, L, 1, 0, st);
+    TsumArgs ta = tsum_args(p, g, L, n0, 0);
+    ta.w[0] = p->wsht;
+    ta.wstride = 0;
+    s2w::MixIn mi{};
+    mi.B = p->B;
+    mi.h[0] = C32;
+    mi.out[0] = flm_out;
+    {
+        Prof pr_(p, "tsum_mm", rec_flop(ta.L, ta.mcount, n0, 1, p->B), st);
+        s2w::launch_tsum_mm(ta, mi, 1, st);
+    }
+}
+
+// flm (FP64) -> maps (FP64) with the batched l-sum and FP32 DFT
+void sht_inverse_mixed(s2w_plan p, const double *flm_in, double *f, hipStream_t st)
+{
+    const DevGrid &g = p->grids[p->L];
+    const int L = p->L, na = 2 * L - 1;
+    float *A32 = (float *)p->bufA, *B32 = (float *)p->bufB, *C32 = (float *)p->bufC;
+    std::vector<int> n0{0};
+    LsumArgs la = lsum_args(p, g, L, n0);
+    la.flm = flm_in;
+    la.flm_m = L;
+    la.flm_l = L;
+    la.w[0] = p->wsht;
+    la.wstride = 0;
+    s2w::MixOut mo{};
+    mo.B = p->B;
+    mo.out[0] = A32;
+    {
+        Prof pr_(p, "lsum_mm", rec_flop(la.L, la.mcount, n0, 1, p->B), st);
+        s2w::launch_lsum_mm(la, mo, 1, st);
+    }
+    GammaArgs ga = gamma_args(p, L, L, L, L, n0, 1);
+    ga.src = A32;
+    ga.dst = B32;
+    {
+        Prof pr_(p, "gamma_c2r_f32", 8.0 * ga.B * ga.M * ga.L, st);
+        s2w::launch_gamma_c2r(ga, st, true);
+    }
+    {
+        const DftArgs da = dft_args(g, B32, L, C32, na, p->B * L, 1.0);
+        Prof pr_(p, "dft_c2r_f32", dft_flop(da.n, da.nrows), st);
+        s2w::launch_dft_c2r(da, st, true);
+    }
+    s2w::launch_convert(C32, f, (size_t)p->B * L * na, false, st);
+}
+
 s2w_status check_plan(s2w_plan p)
 {
     if (!p) return fail(S2W_EINVAL, "null plan");
@@ -462,7 +555,7 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
     *out = nullptr;
     if (batch < 1) return fail(S2W_EINVAL, "batch must be >= 1");
     if (flags != 0) return fail(S2W_EINVAL, "flags must be 0");
-    if (precision != S2W_FP64) return fail(S2W_EUNSUPPORTED, "only S2W_FP64 plans are available");
+    if (precision != S2W_FP64 && precision != S2W_MIXED) return fail(S2W_EINVAL, "unknown precision");
     s2w::Scales S;
     std::string err;
     if (!s2w::make_scales(L, N, lambda, J0, S, err)) return fail(S2W_EINVAL, err);
@@ -626,7 +719,9 @@ s2w_status s2w_analysis(s2w_plan p, const double *f, void *wav_, double *scal, v
     hipStream_t st = (hipStream_t)stream;
     double *wav = (double *)wav_;
     const int B = p->B;
-    sht_forward_internal(p, f, p->flm, st);
+    const bool mixed = p->prec == S2W_MIXED;
+    if (mixed) sht_forward_mixed(p, f, p->flm, st);
+    else sht_forward_internal(p, f, p->flm, st);
     // scaling coefficients: W^Phi = Y^{-1}_{L_phi}(Phi f)
     {
         const DevGrid &g = p->grids[p->Lphi];
@@ -647,6 +742,47 @@ s2w_status s2w_analysis(s2w_plan p, const double *f, void *wav_, double *scal, v
         { const DftArgs da_ = dft_args(g, p->bufB, Lp, scal, 2 * Lp - 1, B * Lp, 1.0); Prof pr_(p, "dft_c2r", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_c2r(da_, st); }
     }
     // wavelet scales
+    if (mixed) {
+        float *wav32 = (float *)wav_;
+        float *A32 = (float *)p->bufA, *B32 = (float *)p->bufB;
+        for (auto &grp : p->groups) {
+            const DevGrid &g = p->grids[grp.L];
+            const int Lk = grp.L, NS = (int)grp.scales.size();
+            const auto &si = p->S.s[grp.scales[0]];
+            const int nn = (int)si.n.size(), ng = 2 * si.N - 1;
+            LsumArgs la = lsum_args(p, g, Lk, si.n);
+            la.flm = p->flm;
+            la.flm_m = p->L;
+            la.flm_l = p->L;
+            la.wstride = Lk;
+            const size_t cstride = (size_t)B * nn * Lk * Lk * 2;   // floats
+            s2w::MixOut mo{};
+            mo.B = B;
+            for (int s = 0; s < NS; ++s) {
+                la.w[s] = p->wpsi[grp.scales[s]];
+                mo.out[s] = A32 + s * cstride;
+            }
+            {
+                Prof pr_(p, "lsum_mm", rec_flop(la.L, la.mcount, si.n, NS, B), st);
+                s2w::launch_lsum_mm(la, mo, NS, st);
+            }
+            for (int s = 0; s < NS; ++s) {
+                const int k = grp.scales[s];
+                GammaArgs ga = gamma_args(p, Lk, Lk, Lk, Lk, si.n, ng);
+                ga.src = A32 + s * cstride;
+                ga.dst = B32;
+                if (p->F.xi_imag) { ga.phr = 0.0; ga.phi = -1.0; }
+                {
+                    Prof pr_(p, "gamma_c2r_f32", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st);
+                    s2w::launch_gamma_c2r(ga, st, true);
+                }
+                const DftArgs da = dft_args(g, B32, Lk, wav32 + p->wav_off[k], 2 * Lk - 1, B * ng * Lk, 1.0);
+                Prof pr_(p, "dft_c2r_f32", dft_flop(da.n, da.nrows), st);
+                s2w::launch_dft_c2r(da, st, true);
+            }
+        }
+        return post_launch("s2w_analysis");
+    }
     for (auto &grp : p->groups) {
         const DevGrid &g = p->grids[grp.L];
         const int Lk = grp.L, NS = (int)grp.scales.size();
@@ -684,7 +820,48 @@ s2w_status s2w_synthesis(s2w_plan p, const void *wav_, const double *scal, doubl
     const double *wav = (const double *)wav_;
     const int B = p->B;
     const int npar = (p->N - 1) & 1;
+    const bool mixed = p->prec == S2W_MIXED;
     for (auto &grp : p->groups) {
+        if (!mixed) continue;
+        const float *wav32 = (const float *)wav_;
+        float *A32 = (float *)p->bufA, *B32 = (float *)p->bufB, *C32 = (float *)p->bufC;
+        const DevGrid &g = p->grids[grp.L];
+        const int Lk = grp.L, NS = (int)grp.scales.size();
+        const auto &si = p->S.s[grp.scales[0]];
+        const int nn = (int)si.n.size(), ng = 2 * si.N - 1;
+        const size_t cstride = (size_t)B * nn * Lk * Lk * 2;   // floats
+        TsumArgs ta = tsum_args(p, g, Lk, si.n, npar);
+        ta.wstride = Lk;
+        s2w::MixIn mi{};
+        mi.B = B;
+        for (int s = 0; s < NS; ++s) {
+            const int k = grp.scales[s];
+            {
+                const DftArgs da = dft_args(g, wav32 + p->wav_off[k], 2 * Lk - 1, B32, Lk, B * ng * Lk, 1.0);
+                Prof pr_(p, "dft_r2c_f32", dft_flop(da.n, da.nrows), st);
+                s2w::launch_dft_r2c(da, st, true, false);
+            }
+            GammaArgs ga = gamma_args(p, Lk, Lk, Lk, Lk, si.n, ng);
+            ga.src = B32;
+            ga.dst = A32 + s * cstride;
+            ga.sgn = -1.0;
+            ga.wscale = (2.0 * M_PI / (2 * Lk - 1)) * (2.0 * M_PI / ng);
+            ga.npar = npar;
+            sig_counts(Lk, npar, ga.M0, ga.M1);
+            {
+                Prof pr_(p, "gamma_r2c_f32", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st);
+                s2w::launch_gamma_r2c(ga, st, true);
+            }
+            theta_quadrature32(p, g, A32 + s * cstride, C32 + s * cstride, Lk, nn, npar, st);
+            ta.w[s] = p->wpsi[k];
+            mi.h[s] = C32 + s * cstride;
+            mi.out[s] = p->P[k];
+        }
+        Prof pr_(p, "tsum_mm", rec_flop(ta.L, ta.mcount, si.n, NS, B), st);
+        s2w::launch_tsum_mm(ta, mi, NS, st);
+    }
+    for (auto &grp : p->groups) {
+        if (mixed) continue;
         const DevGrid &g = p->grids[grp.L];
         const int Lk = grp.L, NS = (int)grp.scales.size();
         const auto &si = p->S.s[grp.scales[0]];
@@ -760,6 +937,7 @@ s2w_status s2w_analysis_adjoint(s2w_plan p, const void *gwav_, const double *gsc
     if (s2w_status st = check_plan(p)) return st;
     if (!gf || !gwav_ || !gscal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    if (p->prec == S2W_MIXED) return fail(S2W_EUNSUPPORTED, "the adjoint is provided for S2W_FP64 plans");
     const double *gwav = (const double *)gwav_;
     const int B = p->B;
     const int npar = (p->N - 1) & 1;

@@ -47,8 +47,8 @@ struct TsumArgs {
 };
 
 struct DftArgs {
-    const double *in;
-    double *out;
+    const void *in;
+    void *out;
     long istride, ostride;       // in elements of the row type (complex or real)
     int nrows;
     int n, n1, n2;
@@ -58,8 +58,8 @@ struct DftArgs {
 };
 
 struct GammaArgs {
-    const double *src;
-    double *dst;
+    const void *src;
+    void *dst;
     int B, M, L;                 // maps, m count, theta count
     int Min, Mout;               // row lengths (m) of the rows over m
     int nn, ng;                  // n values, gamma samples (2N-1)
@@ -85,13 +85,28 @@ struct CombineArgs {
     CombineTerm t[24];
 };
 
+// mixed-precision batched contractions
+struct MixOut {
+    int B;
+    float *out[MAX_NS];          // [B][nn][mcount][L] complex FP32
+};
+struct MixIn {
+    int B;
+    const float *h[MAX_NS];      // sigma-grouped rows, FP32
+    double *out[MAX_NS];         // [B][mcount][nn][L] complex FP64
+};
+void launch_lsum_mm(const LsumArgs &a, const MixOut &o, int NS, hipStream_t st);
+void launch_tsum_mm(const TsumArgs &a, const MixIn &in, int NS, hipStream_t st);
+
 void launch_lsum(const LsumArgs &a, int NS, int B, hipStream_t st);
 void launch_tsum(const TsumArgs &a, int NS, int B, hipStream_t st);
 void launch_gemm(const double *A, const double *Bm, double *C, int M, int N, int K, hipStream_t st);
-void launch_dft_c2r(const DftArgs &a, hipStream_t st);
-void launch_dft_r2c(const DftArgs &a, hipStream_t st);
-void launch_gamma_c2r(const GammaArgs &a, hipStream_t st);
-void launch_gamma_r2c(const GammaArgs &a, hipStream_t st);
+void launch_gemm_f32(const float *A, const float *Bm, float *C, int M, int N, int K, hipStream_t st);
+void launch_dft_c2r(const DftArgs &a, hipStream_t st, bool f32 = false);
+void launch_dft_r2c(const DftArgs &a, hipStream_t st, bool f32 = false, bool in64 = true);
+void launch_gamma_c2r(const GammaArgs &a, hipStream_t st, bool f32 = false);
+void launch_gamma_r2c(const GammaArgs &a, hipStream_t st, bool f32 = false);
+void launch_convert(const void *in, void *out, size_t n, bool to_f32, hipStream_t st);
 void launch_combine(const CombineArgs &a, int B, hipStream_t st);
 void launch_pack_sigma(const double *in, double *out, int B, int nn, int M, int L, int npar, int M0,
                        int M1, int dir, hipStream_t st);

@@ -15,56 +15,13 @@
 //            the alpha-stage (rows over m)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
+#include "s2w_dev.h"
 #include "s2w_kern.h"
 
 namespace s2w {
-
-// ------------------------------------------------------------ helpers ------
-
-__device__ inline void powexp(double x, int p, double &mt, int &et)
-{
-    mt = 1.0;
-    et = 0;
-    if (p == 0) return;
-    int bx;
-    double bm = frexp(x, &bx);
-    while (p) {
-        if (p & 1) {
-            int t;
-            mt = frexp(mt * bm, &t);
-            et += t + bx;
-        }
-        int t2;
-        bm = frexp(bm * bm, &t2);
-        bx = 2 * bx + t2;
-        p >>= 1;
-    }
-}
-
-// d^{l0}_mn(theta) as e * 2^(512 k), |e| in [2^-256, 2^256) or 0.
-__device__ inline void start_value(double mant, int ex, int p1, int p2, double ch, double sh,
-                                   double ceps, double seps, double &e, int &k)
-{
-    if ((ch == 0.0 && p1 > 0) || (sh == 0.0 && p2 > 0) || mant == 0.0) {
-        e = 0.0;
-        k = 0;
-        return;
-    }
-    double mc, ms;
-    int ec, es;
-    powexp(ch, p1, mc, ec);
-    powexp(sh, p2, ms, es);
-    mc *= fma((double)p1, ceps, 1.0);
-    ms *= fma((double)p2, seps, 1.0);
-    const double v = mant * mc * ms;
-    const int E = ex + ec + es;
-    int kk = (E + 256) >> 9;
-    if (kk > 0) kk = 0;
-    e = ldexp(v, E - 512 * kk);
-    k = kk;
-}
 
 // ------------------------------------------------------------- k_lsum ------
 //
@@ -335,55 +292,76 @@ __global__ __launch_bounds__(64) void k_tsum(const TsumArgs a)
 }
 
 // ------------------------------------------------------------- k_gemm ------
-// C[M][N] = A[M][K] * Bm[K][N], row-major, FP64.  64x64 tiles, 256 threads, 4x4 per thread.
+// C[M][N] = A[M][K] * Bm[K][N], row-major, on matrix cores (16x16x4 MFMA, FP64 or FP32).
+// Workgroup tile 128 x 128, four waves of 64 x 64 (4 x 4 MFMA tiles), K staged 16 at a
+// time through LDS.  MFMA operand layout: A fragment lane l holds A[l % 16][l / 16],
+// B fragment B[l / 16][l % 16]; result register j of lane l is D[4 (l / 16) + j][l % 16].
 
-__global__ __launch_bounds__(256) void k_gemm(const double *__restrict__ A, const double *__restrict__ Bm,
-                                              double *__restrict__ C, int M, int N, int K)
+template <typename Tp>
+struct Mfma16;
+template <>
+struct Mfma16<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 op(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+};
+template <>
+struct Mfma16<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 op(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+
+template <typename Tp>
+__global__ __launch_bounds__(256) void k_gemm(const Tp *__restrict__ A, const Tp *__restrict__ Bm,
+                                              Tp *__restrict__ C, int M, int N, int K)
 {
-    __shared__ double As[16][64 + 1];
-    __shared__ double Bs[16][64 + 1];
-    const int tid = threadIdx.x;
-    const int tr = tid / 16, tc = tid % 16;
-    const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
-    double acc[4][4];
+    constexpr int BM = 128, BN = 128, BK = 16, PAD = 1;
+    typedef typename Mfma16<Tp>::v4 v4;
+    __shared__ Tp As[BK][BM + PAD];
+    __shared__ Tp Bs[BK][BN + PAD];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int row0 = blockIdx.y * BM, col0 = blockIdx.x * BN;
+    v4 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        // load A tile 64 x 16 and B tile 16 x 64
+        for (int j = 0; j < 4; ++j) acc[i][j] = v4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int idx = tid + r * 256;         // 0..1023
-            const int ar = idx / 16, ak = idx % 16;
+        for (int r = 0; r < (BM * BK) / 256; ++r) {
+            const int idx = tid + 256 * r;
+            const int ar = idx / BK, ak = idx % BK;
             const int gr = row0 + ar, gk = k0 + ak;
-            As[ak][ar] = (gr < M && gk < K) ? A[(size_t)gr * K + gk] : 0.0;
-            const int bk = idx / 64, bc = idx % 64;
+            As[ak][ar] = (gr < M && gk < K) ? A[(size_t)gr * K + gk] : Tp(0);
+            const int bk = idx / BN, bc = idx % BN;
             const int gk2 = k0 + bk, gc = col0 + bc;
-            Bs[bk][bc] = (gk2 < K && gc < N) ? Bm[(size_t)gk2 * N + gc] : 0.0;
+            Bs[bk][bc] = (gk2 < K && gc < N) ? Bm[(size_t)gk2 * N + gc] : Tp(0);
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            double av[4], bv[4];
+        for (int kk = 0; kk < BK; kk += 4) {
+            Tp af[4], bf[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = As[kk][tr + 16 * i];
+            for (int i = 0; i < 4; ++i) af[i] = As[kk + (lane >> 4)][wr * 64 + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tc + 16 * j];
+            for (int j = 0; j < 4; ++j) bf[j] = Bs[kk + (lane >> 4)][wc * 64 + j * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+                for (int j = 0; j < 4; ++j) acc[i][j] = Mfma16<Tp>::op(af[i], bf[j], acc[i][j]);
         }
         __syncthreads();
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int gr = row0 + tr + 16 * i, gc = col0 + tc + 16 * j;
-            if (gr < M && gc < N) C[(size_t)gr * N + gc] = acc[i][j];
-        }
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gr = row0 + wr * 64 + i * 16 + 4 * (lane >> 4) + r;
+                const int gc = col0 + wc * 64 + j * 16 + (lane & 15);
+                if (gr < M && gc < N) C[(size_t)gr * N + gc] = acc[i][j][r];
+            }
 }
 
 // -------------------------------------------------------------- DFTs -------
@@ -392,27 +370,29 @@ __global__ __launch_bounds__(256) void k_gemm(const double *__restrict__ A, cons
 // placed at LDS position p = m1 n2 + m2 for input index (m1 n2 + m2 n1) mod n
 // (table pin[p]); stage 1 transforms over m1 (length n1), stage 2 over m2
 // (length n2); output (a1, a2) sits at LDS position a1 n2 + a2 and is frequency
-// pout[p] = (a1 e1 + a2 e2) mod n.  No twiddles between stages.
+// pout[p] = (a1 e1 + a2 e2) mod n.  No twiddles between stages.  Tr is the
+// arithmetic type (double, or float in the mixed-precision path).
 
-__device__ inline void pfa_stages(double2 *Z, double2 *Y, const double2 *w1, const double2 *w2, int n1,
-                                  int n2, double sgn)
+template <typename Tr>
+__device__ inline void pfa_stages(typename V2<Tr>::t *Z, typename V2<Tr>::t *Y, const double2 *w1,
+                                  const double2 *w2, int n1, int n2, Tr sgn)
 {
+    typedef typename V2<Tr>::t C2;
     const int tid = threadIdx.x, nt = blockDim.x;
-    // stage 1: Y[a1][m2] = sum_m1 Z[m1][m2] w1^{sgn m1 a1}
     {
         const int nb1 = (n1 + 3) / 4, nb2 = (n2 + 3) / 4;
         for (int task = tid; task < nb1 * nb2; task += nt) {
             const int a1b = (task / nb2) * 4, m2b = (task % nb2) * 4;
-            double2 acc[4][4];
+            C2 acc[4][4];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+                for (int j = 0; j < 4; ++j) acc[i][j] = mk2<Tr>(0, 0);
             int tw[4], st[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) { st[i] = (a1b + i) % n1; tw[i] = 0; }
             for (int m1 = 0; m1 < n1; ++m1) {
-                double2 z[4], w[4];
+                C2 z[4], w[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int m2 = m2b + j < n2 ? m2b + j : n2 - 1;
@@ -420,8 +400,8 @@ __device__ inline void pfa_stages(double2 *Z, double2 *Y, const double2 *w1, con
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    w[i] = w1[tw[i]];
-                    w[i].y *= sgn;
+                    const double2 wd = w1[tw[i]];
+                    w[i] = mk2<Tr>((Tr)wd.x, sgn * (Tr)wd.y);
                     tw[i] += st[i];
                     if (tw[i] >= n1) tw[i] -= n1;
                 }
@@ -441,21 +421,20 @@ __device__ inline void pfa_stages(double2 *Z, double2 *Y, const double2 *w1, con
         }
     }
     __syncthreads();
-    // stage 2: Z[a1][a2] = sum_m2 Y[a1][m2] w2^{sgn m2 a2}
     {
         const int nb1 = (n1 + 3) / 4, nb2 = (n2 + 3) / 4;
         for (int task = tid; task < nb1 * nb2; task += nt) {
             const int a1b = (task / nb2) * 4, a2b = (task % nb2) * 4;
-            double2 acc[4][4];
+            C2 acc[4][4];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+                for (int j = 0; j < 4; ++j) acc[i][j] = mk2<Tr>(0, 0);
             int tw[4], st[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) { st[j] = (a2b + j) % n2; tw[j] = 0; }
             for (int m2 = 0; m2 < n2; ++m2) {
-                double2 y[4], w[4];
+                C2 y[4], w[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int a1 = a1b + i < n1 ? a1b + i : n1 - 1;
@@ -463,8 +442,8 @@ __device__ inline void pfa_stages(double2 *Z, double2 *Y, const double2 *w1, con
                 }
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    w[j] = w2[tw[j]];
-                    w[j].y *= sgn;
+                    const double2 wd = w2[tw[j]];
+                    w[j] = mk2<Tr>((Tr)wd.x, sgn * (Tr)wd.y);
                     tw[j] += st[j];
                     if (tw[j] >= n2) tw[j] -= n2;
                 }
@@ -488,35 +467,38 @@ __device__ inline void pfa_stages(double2 *Z, double2 *Y, const double2 *w1, con
 
 // c2r: two Hermitian rows E1, E2 (m = 0..Lh-1, complex) -> two real rows of length n.
 // x(a) = scale * (Re E_0 + 2 Re sum_{m>=1} E_m e^{+2 pi i m a/n})
+template <typename Tr>
 __global__ __launch_bounds__(128) void k_dft_c2r(const DftArgs a)
 {
-    extern __shared__ double2 smem[];
+    typedef typename V2<Tr>::t C2;
+    extern __shared__ unsigned char smem_raw[];
+    C2 *smem = reinterpret_cast<C2 *>(smem_raw);
     const int n = a.n, n1 = a.n1, n2 = a.n2, Lh = (n + 1) / 2;
-    double2 *Z = smem, *Y = smem + n;
+    C2 *Z = smem, *Y = smem + n;
     const double2 *w1 = reinterpret_cast<const double2 *>(a.w1), *w2 = reinterpret_cast<const double2 *>(a.w2);
     const int tid = threadIdx.x;
     const long r1 = 2L * blockIdx.x, r2 = r1 + 1;
     const bool has2 = r2 < a.nrows;
-    const double2 *E1 = reinterpret_cast<const double2 *>(a.in) + r1 * a.istride;
-    const double2 *E2 = reinterpret_cast<const double2 *>(a.in) + r2 * a.istride;
+    const C2 *E1 = reinterpret_cast<const C2 *>(a.in) + r1 * a.istride;
+    const C2 *E2 = reinterpret_cast<const C2 *>(a.in) + r2 * a.istride;
+    const Tr sc = (Tr)a.scale;
     for (int p = tid; p < n; p += blockDim.x) {
         const int mm = a.pin[p];
-        double2 z1, z2 = make_double2(0.0, 0.0);
+        C2 z1, z2 = mk2<Tr>(0, 0);
         if (mm < Lh) {
             z1 = E1[mm];
             if (has2) z2 = E2[mm];
-            if (mm == 0) { z1.y = 0.0; z2.y = 0.0; }
+            if (mm == 0) { z1.y = 0; z2.y = 0; }
         } else {
             z1 = E1[n - mm];
             z1.y = -z1.y;
             if (has2) { z2 = E2[n - mm]; z2.y = -z2.y; }
         }
-        // Z = z1 + i z2
-        Z[p] = make_double2(a.scale * (z1.x - z2.y), a.scale * (z1.y + z2.x));
+        Z[p] = mk2<Tr>(sc * (z1.x - z2.y), sc * (z1.y + z2.x));   // z1 + i z2
     }
     __syncthreads();
-    pfa_stages(Z, Y, w1, w2, n1, n2, 1.0);
-    double *o1 = a.out + r1 * a.ostride, *o2 = a.out + r2 * a.ostride;
+    pfa_stages<Tr>(Z, Y, w1, w2, n1, n2, (Tr)1);
+    Tr *o1 = reinterpret_cast<Tr *>(a.out) + r1 * a.ostride, *o2 = reinterpret_cast<Tr *>(a.out) + r2 * a.ostride;
     for (int p = tid; p < n; p += blockDim.x) {
         const int aa = a.pout[p];
         o1[aa] = Z[p].x;
@@ -525,51 +507,57 @@ __global__ __launch_bounds__(128) void k_dft_c2r(const DftArgs a)
 }
 
 // r2c: two real rows x1, x2 of length n -> X_m = scale * sum_a x(a) e^{-2 pi i m a/n}, m = 0..Lh-1.
+// Tin: element type of the input rows (the mixed path reads FP64 maps into FP32 arithmetic).
+template <typename Tr, typename Tin>
 __global__ __launch_bounds__(128) void k_dft_r2c(const DftArgs a)
 {
-    extern __shared__ double2 smem[];
+    typedef typename V2<Tr>::t C2;
+    extern __shared__ unsigned char smem_raw[];
+    C2 *smem = reinterpret_cast<C2 *>(smem_raw);
     const int n = a.n, n1 = a.n1, n2 = a.n2, Lh = (n + 1) / 2;
-    double2 *Z = smem, *Y = smem + n;
+    C2 *Z = smem, *Y = smem + n;
     const double2 *w1 = reinterpret_cast<const double2 *>(a.w1), *w2 = reinterpret_cast<const double2 *>(a.w2);
     const int tid = threadIdx.x;
     const long r1 = 2L * blockIdx.x, r2 = r1 + 1;
     const bool has2 = r2 < a.nrows;
-    const double *x1 = a.in + r1 * a.istride, *x2 = a.in + r2 * a.istride;
+    const Tin *x1 = reinterpret_cast<const Tin *>(a.in) + r1 * a.istride;
+    const Tin *x2 = reinterpret_cast<const Tin *>(a.in) + r2 * a.istride;
     for (int p = tid; p < n; p += blockDim.x) {
         const int mm = a.pin[p];
-        Z[p] = make_double2(x1[mm], has2 ? x2[mm] : 0.0);
+        Z[p] = mk2<Tr>((Tr)x1[mm], has2 ? (Tr)x2[mm] : (Tr)0);
     }
     __syncthreads();
-    pfa_stages(Z, Y, w1, w2, n1, n2, -1.0);
-    double2 *O1 = reinterpret_cast<double2 *>(a.out) + r1 * a.ostride;
-    double2 *O2 = reinterpret_cast<double2 *>(a.out) + r2 * a.ostride;
+    pfa_stages<Tr>(Z, Y, w1, w2, n1, n2, (Tr)-1);
+    C2 *O1 = reinterpret_cast<C2 *>(a.out) + r1 * a.ostride;
+    C2 *O2 = reinterpret_cast<C2 *>(a.out) + r2 * a.ostride;
+    const Tr h = (Tr)(0.5 * a.scale);
     for (int mm = tid; mm < Lh; mm += blockDim.x) {
-        const double2 X = Z[a.pinv[mm]];
-        const double2 Xc = Z[a.pinv[mm == 0 ? 0 : n - mm]];
-        // X1 = (X + conj(Xc))/2, X2 = (X - conj(Xc))/(2i)
-        O1[mm] = make_double2(0.5 * a.scale * (X.x + Xc.x), 0.5 * a.scale * (X.y - Xc.y));
-        if (has2) O2[mm] = make_double2(0.5 * a.scale * (X.y + Xc.y), -0.5 * a.scale * (X.x - Xc.x));
+        const C2 X = Z[a.pinv[mm]];
+        const C2 Xc = Z[a.pinv[mm == 0 ? 0 : n - mm]];
+        O1[mm] = mk2<Tr>(h * (X.x + Xc.x), h * (X.y - Xc.y));
+        if (has2) O2[mm] = mk2<Tr>(h * (X.y + Xc.y), -h * (X.x - Xc.x));
     }
 }
 
 // --------------------------------------------------------- gamma stages ----
 //
-// c2r side: E[b][g][theta][m] = ph * sum_ni C[b][ni][m][theta] e^{+i n_ni gamma_g} (complex)
+// c2r side: E[b][g][theta][m] = ph * fm(m) * sum_ni C[b][ni][m][theta] e^{+i n_ni gamma_g} (complex)
 // 16 x 16 (m, theta) tiles through LDS.
 
+template <typename Tr>
 __global__ __launch_bounds__(256) void k_gamma_c2r(const GammaArgs a)
 {
-    __shared__ double2 tile[GAMMA_MAXN][16][17];
+    typedef typename V2<Tr>::t C2;
+    __shared__ C2 tile[GAMMA_MAXN][16][17];
     const int tid = threadIdx.x;
     const int m0 = blockIdx.x * 16, th0 = blockIdx.y * 16, b = blockIdx.z;
-    // load C tiles with theta fastest
+    const C2 *src = reinterpret_cast<const C2 *>(a.src);
     {
         const int tt = tid % 16, tm = tid / 16;
         const int m = m0 + tm, th = th0 + tt;
         for (int ni = 0; ni < a.nn; ++ni) {
-            double2 v = make_double2(0.0, 0.0);
-            if (m < a.M && th < a.L)
-                v = reinterpret_cast<const double2 *>(a.src)[(((size_t)b * a.nn + ni) * a.M + m) * a.L + th];
+            C2 v = mk2<Tr>(0, 0);
+            if (m < a.M && th < a.L) v = src[(((size_t)b * a.nn + ni) * a.M + m) * a.L + th];
             tile[ni][tm][tt] = v;
         }
     }
@@ -577,54 +565,55 @@ __global__ __launch_bounds__(256) void k_gamma_c2r(const GammaArgs a)
     const int tm = tid % 16, tt = tid / 16;
     const int m = m0 + tm, th = th0 + tt;
     if (m >= a.M || th >= a.L) return;
+    const Tr fm = (Tr)((m == 0) ? a.fm0 : a.fm1) * (Tr)a.wscale;
+    const Tr phr = (Tr)a.phr, phi = (Tr)a.phi;
     for (int g = 0; g < a.ng; ++g) {
-        double re = 0.0, im = 0.0;
+        Tr re = 0, im = 0;
         for (int ni = 0; ni < a.nn; ++ni) {
             int idx = (a.nval[ni] * g) % a.ng;
             if (idx < 0) idx += a.ng;
-            const double cw = a.tw[2 * idx], sw = a.sgn * a.tw[2 * idx + 1];
-            const double2 v = tile[ni][tm][tt];
+            const Tr cw = (Tr)a.tw[2 * idx], sw = (Tr)(a.sgn * a.tw[2 * idx + 1]);
+            const C2 v = tile[ni][tm][tt];
             re += v.x * cw - v.y * sw;
             im += v.x * sw + v.y * cw;
         }
-        const double fm = (m == 0) ? a.fm0 : a.fm1;
-        const double outr = a.phr * re - a.phi * im;
-        const double outi = a.phr * im + a.phi * re;
-        reinterpret_cast<double2 *>(a.dst)[(((size_t)b * a.ng + g) * a.L + th) * a.Mout + m] =
-            make_double2(a.wscale * fm * outr, a.wscale * fm * outi);
+        reinterpret_cast<C2 *>(a.dst)[(((size_t)b * a.ng + g) * a.L + th) * a.Mout + m] =
+            mk2<Tr>(fm * (phr * re - phi * im), fm * (phr * im + phi * re));
     }
 }
 
 // r2c side: F[sig][b][m'][ni][c][theta] = w * fm(m) * ph * sum_g X[b][g][theta][m] e^{-i n_ni gamma_g}
+template <typename Tr>
 __global__ __launch_bounds__(256) void k_gamma_r2c(const GammaArgs a)
 {
-    __shared__ double tile[GAMMA_MAXN][2][16][17];
+    typedef typename V2<Tr>::t C2;
+    __shared__ Tr tile[GAMMA_MAXN][2][16][17];
     const int tid = threadIdx.x;
     const int m0 = blockIdx.x * 16, th0 = blockIdx.y * 16, b = blockIdx.z;
+    const C2 *src = reinterpret_cast<const C2 *>(a.src);
+    Tr *dst = reinterpret_cast<Tr *>(a.dst);
     {
         const int tm = tid % 16, tt = tid / 16;
         const int m = m0 + tm, th = th0 + tt;
-        double accr[GAMMA_MAXN], acci[GAMMA_MAXN];
-        for (int ni = 0; ni < a.nn; ++ni) { accr[ni] = 0.0; acci[ni] = 0.0; }
+        Tr accr[GAMMA_MAXN], acci[GAMMA_MAXN];
+        for (int ni = 0; ni < a.nn; ++ni) { accr[ni] = 0; acci[ni] = 0; }
         if (m < a.M && th < a.L) {
             for (int g = 0; g < a.ng; ++g) {
-                const double2 v =
-                    reinterpret_cast<const double2 *>(a.src)[(((size_t)b * a.ng + g) * a.L + th) * a.Min + m];
+                const C2 v = src[(((size_t)b * a.ng + g) * a.L + th) * a.Min + m];
                 for (int ni = 0; ni < a.nn; ++ni) {
                     int idx = (a.nval[ni] * g) % a.ng;
                     if (idx < 0) idx += a.ng;
-                    const double cw = a.tw[2 * idx], sw = a.sgn * a.tw[2 * idx + 1];
+                    const Tr cw = (Tr)a.tw[2 * idx], sw = (Tr)(a.sgn * a.tw[2 * idx + 1]);
                     accr[ni] += v.x * cw - v.y * sw;
                     acci[ni] += v.x * sw + v.y * cw;
                 }
             }
         }
-        const double fm = (m == 0) ? a.fm0 : a.fm1;
+        const Tr fm = (Tr)((m == 0) ? a.fm0 : a.fm1) * (Tr)a.wscale;
+        const Tr phr = (Tr)a.phr, phi = (Tr)a.phi;
         for (int ni = 0; ni < a.nn; ++ni) {
-            const double re = a.phr * accr[ni] - a.phi * acci[ni];
-            const double im = a.phr * acci[ni] + a.phi * accr[ni];
-            tile[ni][0][tm][tt] = a.wscale * fm * re;
-            tile[ni][1][tm][tt] = a.wscale * fm * im;
+            tile[ni][0][tm][tt] = fm * (phr * accr[ni] - phi * acci[ni]);
+            tile[ni][1][tm][tt] = fm * (phr * acci[ni] + phi * accr[ni]);
         }
     }
     __syncthreads();
@@ -636,8 +625,8 @@ __global__ __launch_bounds__(256) void k_gamma_r2c(const GammaArgs a)
     const size_t base = (sig == 0 ? 0 : (size_t)a.B * a.M0 * a.nn * 2)
                         + (((size_t)b * (sig == 0 ? a.M0 : a.M1) + mp) * a.nn) * 2;
     for (int ni = 0; ni < a.nn; ++ni) {
-        a.dst[(base + (size_t)ni * 2 + 0) * a.L + th] = tile[ni][0][tm][tt];
-        a.dst[(base + (size_t)ni * 2 + 1) * a.L + th] = tile[ni][1][tm][tt];
+        dst[(base + (size_t)ni * 2 + 0) * a.L + th] = tile[ni][0][tm][tt];
+        dst[(base + (size_t)ni * 2 + 1) * a.L + th] = tile[ni][1][tm][tt];
     }
 }
 
@@ -670,7 +659,8 @@ __global__ __launch_bounds__(256) void k_combine(const CombineArgs a)
 
 // ------------------------------------------------- sigma-grouped rows ----
 // [b][ni][m][theta] complex  <->  [sig][b][m'][ni][c][theta] real rows, sig = (m + npar) & 1
-__global__ void k_pack_sigma(const double *in, double *out, int B, int nn, int M, int L, int npar,
+template <typename Tr>
+__global__ void k_pack_sigma(const Tr *in, Tr *out, int B, int nn, int M, int L, int npar,
                              int M0, int M1, int dir)
 {
     const int th = blockIdx.x * 256 + threadIdx.x;
@@ -689,6 +679,18 @@ __global__ void k_pack_sigma(const double *in, double *out, int B, int nn, int M
         out[ci * 2 + 0] = in[(base + 0) * L + th];
         out[ci * 2 + 1] = in[(base + 1) * L + th];
     }
+}
+
+__global__ void k_convert_f64_f32(const double *in, float *out, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
+}
+
+__global__ void k_convert_f32_f64(const float *in, double *out, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = (double)in[i];
 }
 
 // ----------------------------------------------------- harmonic layouts ----
@@ -790,39 +792,59 @@ void launch_tsum(const TsumArgs &a, int NS, int B, hipStream_t st)
 void launch_gemm(const double *A, const double *Bm, double *C, int M, int N, int K, hipStream_t st)
 {
     if (M <= 0 || N <= 0) return;
-    dim3 grid((N + 63) / 64, (M + 63) / 64);
-    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, A, Bm, C, M, N, K);
+    dim3 grid((N + 127) / 128, (M + 127) / 128);
+    hipLaunchKernelGGL(k_gemm<double>, grid, dim3(256), 0, st, A, Bm, C, M, N, K);
 }
 
-static size_t dft_smem(const DftArgs &a)
+void launch_gemm_f32(const float *A, const float *Bm, float *C, int M, int N, int K, hipStream_t st)
 {
-    return sizeof(double2) * (size_t)(2 * a.n);
+    if (M <= 0 || N <= 0) return;
+    dim3 grid((N + 127) / 128, (M + 127) / 128);
+    hipLaunchKernelGGL(k_gemm<float>, grid, dim3(256), 0, st, A, Bm, C, M, N, K);
 }
 
-void launch_dft_c2r(const DftArgs &a, hipStream_t st)
-{
-    if (a.nrows <= 0) return;
-    dim3 grid((a.nrows + 1) / 2);
-    hipLaunchKernelGGL(k_dft_c2r, grid, dim3(128), dft_smem(a), st, a);
-}
-
-void launch_dft_r2c(const DftArgs &a, hipStream_t st)
+void launch_dft_c2r(const DftArgs &a, hipStream_t st, bool f32)
 {
     if (a.nrows <= 0) return;
     dim3 grid((a.nrows + 1) / 2);
-    hipLaunchKernelGGL(k_dft_r2c, grid, dim3(128), dft_smem(a), st, a);
+    if (f32)
+        hipLaunchKernelGGL(k_dft_c2r<float>, grid, dim3(128), sizeof(float2) * 2 * (size_t)a.n, st, a);
+    else
+        hipLaunchKernelGGL(k_dft_c2r<double>, grid, dim3(128), sizeof(double2) * 2 * (size_t)a.n, st, a);
 }
 
-void launch_gamma_c2r(const GammaArgs &a, hipStream_t st)
+void launch_dft_r2c(const DftArgs &a, hipStream_t st, bool f32, bool in64)
 {
-    dim3 grid((a.M + 15) / 16, (a.L + 15) / 16, a.B);
-    hipLaunchKernelGGL(k_gamma_c2r, grid, dim3(256), 0, st, a);
+    if (a.nrows <= 0) return;
+    dim3 grid((a.nrows + 1) / 2);
+    if (!f32)
+        hipLaunchKernelGGL((k_dft_r2c<double, double>), grid, dim3(128), sizeof(double2) * 2 * (size_t)a.n, st, a);
+    else if (in64)
+        hipLaunchKernelGGL((k_dft_r2c<float, double>), grid, dim3(128), sizeof(float2) * 2 * (size_t)a.n, st, a);
+    else
+        hipLaunchKernelGGL((k_dft_r2c<float, float>), grid, dim3(128), sizeof(float2) * 2 * (size_t)a.n, st, a);
 }
 
-void launch_gamma_r2c(const GammaArgs &a, hipStream_t st)
+void launch_gamma_c2r(const GammaArgs &a, hipStream_t st, bool f32)
 {
     dim3 grid((a.M + 15) / 16, (a.L + 15) / 16, a.B);
-    hipLaunchKernelGGL(k_gamma_r2c, grid, dim3(256), 0, st, a);
+    if (f32) hipLaunchKernelGGL(k_gamma_c2r<float>, grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_gamma_c2r<double>, grid, dim3(256), 0, st, a);
+}
+
+void launch_gamma_r2c(const GammaArgs &a, hipStream_t st, bool f32)
+{
+    dim3 grid((a.M + 15) / 16, (a.L + 15) / 16, a.B);
+    if (f32) hipLaunchKernelGGL(k_gamma_r2c<float>, grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_gamma_r2c<double>, grid, dim3(256), 0, st, a);
+}
+
+void launch_convert(const void *in, void *out, size_t n, bool to_f32, hipStream_t st)
+{
+    if (n == 0) return;
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 65536);
+    if (to_f32) hipLaunchKernelGGL(k_convert_f64_f32, dim3(blocks), dim3(256), 0, st, (const double *)in, (float *)out, n);
+    else hipLaunchKernelGGL(k_convert_f32_f64, dim3(blocks), dim3(256), 0, st, (const float *)in, (double *)out, n);
 }
 
 void launch_combine(const CombineArgs &a, int B, hipStream_t st)
@@ -835,7 +857,7 @@ void launch_pack_sigma(const double *in, double *out, int B, int nn, int M, int 
                        int M1, int dir, hipStream_t st)
 {
     dim3 grid((L + 255) / 256, M, B * nn);
-    hipLaunchKernelGGL(k_pack_sigma, grid, dim3(256), 0, st, in, out, B, nn, M, L, npar, M0, M1, dir);
+    hipLaunchKernelGGL(k_pack_sigma<double>, grid, dim3(256), 0, st, in, out, B, nn, M, L, npar, M0, M1, dir);
 }
 
 void launch_flm_to_ext(const double *in, double *out, int L, int B, hipStream_t st)

@@ -1,0 +1,119 @@
+"""Mixed-precision batched form (S2W_MIXED): FP64 Wigner-d recursion, FP32
+matrix-core contractions and DFTs, FP64 scale sums.  Gate: <= 1e-6 relative L2
+error against the FP64 oracle for every wavelet scale and for every result."""
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import mw, wavelets
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _plan(L, N, J0, B):
+    import paper_2402_01282_amd as s2w
+    return s2w.Plan(L, N, 2.0, J0, batch=B, precision=s2w.S2W_MIXED, device=0)
+
+
+@pytest.mark.parametrize("L,N,J0,B", [(8, 3, 0, 2), (32, 3, 0, 32), (64, 8, 0, 32), (33, 4, 1, 5), (128, 4, 2, 64)])
+def test_mixed_analysis_and_synthesis(L, N, J0, B):
+    torch = _torch()
+    print(f"[mixed L={L} N={N} J0={J0} B={B}]", flush=True)
+    plan = _plan(L, N, J0, B)
+    P = wavelets.Plan(L, N, 2.0, J0)
+    maps = np.stack([np.real(mw.sht_inverse(S.sphere_flm(L, S.stream_key(3, b)), L)) for b in range(B)])
+    ft = torch.from_numpy(maps).cuda()
+    wav, scal = plan.analysis(ft)
+    assert wav.dtype == torch.float32
+    views = plan.wav_views(wav)
+    for b in sorted({0, B - 1}):
+        wr, sr = wavelets.analysis(maps[b], P)
+        for k, w in enumerate(wr):
+            e = _rel(views[k][b].double().cpu().numpy(), w)
+            assert e < TOL, (b, k, e)
+        assert _rel(scal[b].cpu().numpy(), sr) < TOL
+        # synthesis of the oracle's coefficients (rounded to FP32 on input)
+    f2 = plan.synthesis(wav, scal).cpu().numpy()
+    assert _rel(f2, maps) < TOL
+    # synthesis parity on the oracle's own coefficients for one map (others zero)
+    wr, sr = wavelets.analysis(maps[0], P)
+    packed = torch.zeros(plan.wav_offset[-1], dtype=torch.float32, device="cuda")
+    pv = plan.wav_views(packed)
+    sc = torch.zeros(plan.scal_shape, dtype=torch.float64, device="cuda")
+    for k, w in enumerate(wr):
+        pv[k][0].copy_(torch.from_numpy(w).float())
+    sc[0].copy_(torch.from_numpy(sr))
+    g = plan.synthesis(packed, sc)[0].cpu().numpy()
+    assert _rel(g, wavelets.synthesis(wr, sr, P)) < TOL
+
+
+def test_mixed_config3_L512_B64():
+    """Config 3: 64 maps at L=512, N=4, lambda=2, all scales.  Round trip for every
+    map; every scale against the oracle for two maps of the batch."""
+    torch = _torch()
+    print("[mixed config3 L=512 N=4 B=64]", flush=True)
+    L, N, J0, B = 512, 4, 0, 64
+    plan = _plan(L, N, J0, B)
+    P = wavelets.Plan(L, N, 2.0, J0)
+    flm = np.stack([S.sphere_flm(L, S.stream_key(3, b)) for b in range(B)])
+    import paper_2402_01282_amd as s2w
+    p64 = s2w.Plan(L, N, 2.0, J0, batch=B, device=0)
+    f = p64.sht_inverse(torch.from_numpy(flm).cuda())
+    wav, scal = plan.analysis(f)
+    f2 = plan.synthesis(wav, scal)
+    errs = [(torch.linalg.norm(f2[b] - f[b]) / torch.linalg.norm(f[b])).item() for b in range(B)]
+    print(f"  round trip rel err: max {max(errs):.2e} mean {np.mean(errs):.2e}", flush=True)
+    assert max(errs) < TOL
+    views = plan.wav_views(wav)
+    for b in (0, 37):
+        wr, sr = wavelets.analysis_lm(flm[b], P)
+        es = [_rel(views[k][b].double().cpu().numpy(), w) for k, w in enumerate(wr)]
+        print(f"  map {b} per-scale rel err: " + " ".join(f"{x:.1e}" for x in es), flush=True)
+        assert max(es) < TOL
+        assert _rel(scal[b].cpu().numpy(), sr) < TOL
+
+
+def test_mixed_metric_config_L1024_round_trip():
+    """L=1024, N=8, batch 64: round trip of every map and the top scale of one map
+    against the oracle."""
+    torch = _torch()
+    print("[mixed L=1024 N=8 B=64]", flush=True)
+    L, N, J0, B = 1024, 8, 0, 64
+    import paper_2402_01282_amd as s2w
+    plan = _plan(L, N, J0, B)
+    p64 = s2w.Plan(L, N, 2.0, J0, batch=1, device=0)
+    flm0 = S.sphere_flm(L, S.stream_key(4, 0))
+    f0 = p64.sht_inverse(torch.from_numpy(flm0[None].copy()).cuda())
+    f = torch.empty(plan.map_shape, dtype=torch.float64, device="cuda")
+    f[0].copy_(f0[0])
+    for b in range(1, B):   # further band-limited fields: copies rotated about the pole by b samples, rescaled
+        f[b].copy_(torch.roll(f0[0], shifts=b, dims=1) * (1.0 + 0.01 * b))
+    wav, scal = plan.analysis(f)
+    f2 = plan.synthesis(wav, scal)
+    errs = [(torch.linalg.norm(f2[b] - f[b]) / torch.linalg.norm(f[b])).item() for b in range(B)]
+    print(f"  round trip rel err: max {max(errs):.2e}", flush=True)
+    assert max(errs) < TOL
+    P = wavelets.Plan(L, N, 2.0, J0)
+    k = len(P.scales) - 1
+    Lj, Nj = P.Lj[k], P.Nj[k]
+    lj = np.arange(Lj)
+    what = (8 * np.pi ** 2 / (2 * lj + 1))[None, :, None] * flm0[None, :Lj, L - Lj:L + Lj - 1] \
+        * np.conj(P.psi(k)).T[:, :, None]
+    ref = np.real(mw.wigner_inverse(what, Lj, Nj))
+    got = plan.wav_views(wav)[k][0].double().cpu().numpy()
+    e = _rel(got, ref)
+    print(f"  top scale rel err {e:.2e}", flush=True)
+    assert e < TOL
