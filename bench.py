@@ -87,7 +87,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+              "sharding across GPUs is not built", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

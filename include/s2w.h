@@ -112,6 +112,53 @@ s2w_status s2w_plan_profile(s2w_plan plan, int capacity);
 s2w_status s2w_plan_profile_read(s2w_plan plan, int max, char *names, double *total_ms,
                                  int64_t *launches, double *flop, int *count, int64_t *dropped);
 
+/* ---- ball B^3 = R+ x S^2 (Section 3.2, Section 5: eq:forward_ball_wavelet,
+ * eq:synthesis_b3; radial Laguerre basis of Section 2.3; filters of Appendix A.3-A.4) ----
+ *
+ *   analysis   W^{Psi^{jj'}} = Q^{-1} N Psi^{jj'} Z f,   W^Phi = Z^{-1} Phi Z f
+ *   synthesis  f = Z^{-1}(Phi Z W^Phi + sum_{jj'} Psi^{jj' dagger} Q W^{jj'})
+ *   Psi^{jj'}_lmp = sqrt((2l+1)/(8 pi^2)) kappa_lambda(l/lambda^j) kappa_nu(p/nu^j') zeta_lm,
+ *   4pi/(2l+1)|Phi_l0p|^2 = a + b - ab,  a = k_lambda(l/lambda^J0), b = k_nu(p/nu^J0')
+ *   (the scaling filter is taken from the admissibility condition of Section 3.2).
+ *
+ * Radial sampling: P nodes r_k = tau x_k, x_k the roots of the Laguerre polynomial
+ * L^{(2)}_P (exact quadrature for radial band limit P, p = 0..P-1).  Radial scale j'
+ * (J0' <= j' <= J', J' the smallest integer with nu^J' >= P) has band limit
+ * P_j' = min(ceil(nu^(j'+1)), P) and is sampled on the P_j' nodes of its own rule.
+ *
+ * Layouts (row-major):
+ *   map f, scaling coeffs  [B][P][L][2L-1] FP64 on the P radial nodes (shell k = r_k)
+ *   wavelet coeffs         blocks (i, k), radial scale i = j'-J0' outer, angular scale
+ *                          k = j-J0 inner, block (i, k) = [B][P_j'][2N_k-1][L_k][2L_k-1]
+ *                          starting at element wav_offset[i * nang + k]; FP64, or FP32 for
+ *                          S2W_MIXED plans (radial stages stay FP64).
+ * Ownership, asynchrony and errors as for s2w plans.  Each transform runs the sphere
+ * transform of the plan on B P_j' shells at a time (one internal s2w plan). */
+typedef struct b3w_plan_s *b3w_plan;
+
+/* Create a ball plan: L >= 2, 1 <= N <= L, P >= 1, lambda > 1, nu > 1, 0 <= J0 <= J,
+ * 0 <= J0p <= J', tau > 0, batch >= 1.  Errors: S2W_EINVAL, S2W_EUNSUPPORTED (N > 8),
+ * S2W_ENOMEM, S2W_EHIP. */
+s2w_status b3w_plan_create(b3w_plan *out, int L, int N, int P, double lambda, double nu, int J0,
+                           int J0p, double tau, int batch, s2w_precision precision, int device,
+                           unsigned flags);
+s2w_status b3w_plan_destroy(b3w_plan plan);
+
+/* Layout: nang angular and nrad radial scales; Lk, Nk need J - J0 + 1 entries, Pk
+ * J' - J0' + 1, wav_offset nrad * nang + 1 (the last is the total element count),
+ * nodes P (radial nodes r_k).  Any output pointer may be NULL. */
+s2w_status b3w_plan_layout(b3w_plan plan, int *nang, int *nrad, int *Lk, int *Nk, int *Pk,
+                           int64_t *wav_offset, double *nodes);
+
+/* Ball wavelet analysis and synthesis (device buffers as laid out above). */
+s2w_status b3w_analysis(b3w_plan plan, const double *f, void *wav, double *scal, void *stream);
+s2w_status b3w_synthesis(b3w_plan plan, const void *wav, const double *scal, double *f, void *stream);
+
+/* Kernel timing for ball transforms: as s2w_plan_profile / s2w_plan_profile_read. */
+s2w_status b3w_plan_profile(b3w_plan plan, int capacity);
+s2w_status b3w_plan_profile_read(b3w_plan plan, int max, char *names, double *total_ms,
+                                 int64_t *launches, double *flop, int *count, int64_t *dropped);
+
 /* Message for the last failure on the calling thread. */
 const char *s2w_last_error(void);
 
@@ -130,6 +177,10 @@ s2w_status s2w_host_filters(int L, int N, double lambda, int J0, double *psi, do
  * with parity F(2pi - t) = sigma F(t) and any d of band limit L with the same parity,
  * int_0^pi F d sin t dt = sum_b d(theta_b) (T_sigma F)(theta_b). sigma = +1 or -1. */
 s2w_status s2w_host_theta_matrix(int L, int sigma, double *T);
+
+/* Radial Laguerre rule of the ball (Section 2.3): the P nodes r_k = tau x_k (roots of
+ * L^{(2)}_P) and weights W_k with f_p = sum_k W_k K_p(r_k) f(r_k) exact for p < P. */
+s2w_status s2w_host_laguerre_rule(int P, double tau, double *nodes, double *weights);
 
 /* Wigner d^l_mn(theta_b) for l = 0..L-1 on the MW grid of band limit L, computed on the
  * host by the same scaled, log-rescaled three-term recursion the device uses

@@ -20,6 +20,6 @@ Layout of the oracle:
                    Section 5, Algorithm 2)
 
 Every function cites the passage of the paper it follows.  Readings of
-passages that are silent or garbled are listed in the design doc.
+passages that are silent or garbled are stated where they are used.
 """
 from . import _lib  # noqa: F401

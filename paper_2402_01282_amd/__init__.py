@@ -55,6 +55,16 @@ def _load():
         "s2w_host_filters": [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp],
         "s2w_host_theta_matrix": [ctypes.c_int, ctypes.c_int, dp],
         "s2w_host_wigner_d": [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp],
+        "s2w_host_laguerre_rule": [ctypes.c_int, ctypes.c_double, dp, dp],
+        "b3w_plan_create": [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                            ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                            ctypes.c_int, ctypes.c_int, ctypes.c_uint],
+        "b3w_plan_destroy": [vp],
+        "b3w_plan_layout": [vp, ip, ip, ip, ip, ip, i64p, dp],
+        "b3w_analysis": [vp, vp, vp, vp, vp],
+        "b3w_synthesis": [vp, vp, vp, vp, vp],
+        "b3w_plan_profile": [vp, ctypes.c_int],
+        "b3w_plan_profile_read": [vp, ctypes.c_int, ctypes.c_char_p, dp, i64p, dp, ip, i64p],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -72,7 +82,9 @@ EXPORTS = ["s2w_plan_create", "s2w_plan_destroy", "s2w_plan_layout", "s2w_analys
            "s2w_analysis_adjoint", "s2w_synthesis_adjoint", "s2w_sht_forward", "s2w_sht_inverse",
            "s2w_plan_profile", "s2w_plan_profile_read",
            "s2w_last_error", "s2w_host_scales", "s2w_host_filters", "s2w_host_theta_matrix",
-           "s2w_host_wigner_d"]
+           "s2w_host_wigner_d", "s2w_host_laguerre_rule",
+           "b3w_plan_create", "b3w_plan_destroy", "b3w_plan_layout", "b3w_analysis", "b3w_synthesis",
+           "b3w_plan_profile", "b3w_plan_profile_read"]
 
 
 def lib():
@@ -117,6 +129,14 @@ def host_wigner_d(L, m, n):
     out = np.zeros(L * L)
     _check(_lib.s2w_host_wigner_d(L, m, n, _dptr(out)))
     return out.reshape(L, L)
+
+
+def host_laguerre_rule(P, tau=1.0):
+    """Radial nodes r_k and weights W_k of the ball's Laguerre rule."""
+    r = np.zeros(P)
+    w = np.zeros(P)
+    _check(_lib.s2w_host_laguerre_rule(P, float(tau), _dptr(r), _dptr(w)))
+    return r, w
 
 
 # --------------------------------------------------------------- GPU plans
@@ -221,20 +241,7 @@ class Plan:
 
     def profile_read(self):
         """{kernel name: (total ms, launches, algorithmic flop)} since profiling started."""
-        mx = 64
-        names = ctypes.create_string_buffer(32 * mx)
-        ms = (ctypes.c_double * mx)()
-        cnt = (ctypes.c_int64 * mx)()
-        fl = (ctypes.c_double * mx)()
-        k = ctypes.c_int()
-        dropped = ctypes.c_int64()
-        _check(_lib.s2w_plan_profile_read(self._h, mx, names, ms, cnt, fl, ctypes.byref(k),
-                                          ctypes.byref(dropped)))
-        out = {}
-        for i in range(k.value):
-            name = names.raw[32 * i:32 * (i + 1)].split(b"\0", 1)[0].decode()
-            out[name] = (ms[i], cnt[i], fl[i])
-        return out, dropped.value
+        return _profile_read(_lib.s2w_plan_profile_read, self._h)
 
     def sht_forward(self, f):
         torch = self._torch
@@ -249,6 +256,106 @@ class Plan:
         f = torch.empty(self.map_shape, dtype=torch.float64, device=self._dev())
         _check(_lib.s2w_sht_inverse(self._h, self._p(flm), self._p(f), _stream_ptr(torch, self.device)))
         return f
+
+
+def _profile_read(fn, h):
+    mx = 64
+    names = ctypes.create_string_buffer(32 * mx)
+    ms = (ctypes.c_double * mx)()
+    cnt = (ctypes.c_int64 * mx)()
+    fl = (ctypes.c_double * mx)()
+    k = ctypes.c_int()
+    dropped = ctypes.c_int64()
+    _check(fn(h, mx, names, ms, cnt, fl, ctypes.byref(k), ctypes.byref(dropped)))
+    out = {}
+    for i in range(k.value):
+        name = names.raw[32 * i:32 * (i + 1)].split(b"\0", 1)[0].decode()
+        out[name] = (ms[i], cnt[i], fl[i])
+    return out, dropped.value
+
+
+class BallPlan:
+    """Ball wavelet plan for (L, N, P, lambda, nu, J0, J0', tau, batch).
+
+    Maps and scaling coefficients are float64 tensors [B, P, L, 2L-1] on the radial
+    nodes (``nodes``); wavelet coefficients are one packed tensor with a view per
+    (radial scale i, angular scale k) of shape [B, P_i, 2N_k-1, L_k, 2L_k-1].
+    """
+
+    def __init__(self, L, N, P, lam=2.0, nu=2.0, J0=0, J0p=0, tau=1.0, batch=1, precision=S2W_FP64, device=0):
+        import torch
+        self._torch = torch
+        self.L, self.N, self.P, self.lam, self.nu = L, N, P, float(lam), float(nu)
+        self.J0, self.J0p, self.tau, self.batch, self.precision, self.device = J0, J0p, float(tau), batch, precision, device
+        h = ctypes.c_void_p()
+        _check(_lib.b3w_plan_create(ctypes.byref(h), L, N, P, float(lam), float(nu), J0, J0p, float(tau), batch,
+                                    precision, device, 0))
+        self._h = h
+        na, nr = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.b3w_plan_layout(h, ctypes.byref(na), ctypes.byref(nr), None, None, None, None, None))
+        Lk = (ctypes.c_int * na.value)()
+        Nk = (ctypes.c_int * na.value)()
+        Pk = (ctypes.c_int * nr.value)()
+        off = (ctypes.c_int64 * (na.value * nr.value + 1))()
+        nodes = np.zeros(P)
+        _check(_lib.b3w_plan_layout(h, ctypes.byref(na), ctypes.byref(nr), Lk, Nk, Pk, off, _dptr(nodes)))
+        self.nang, self.nrad = na.value, nr.value
+        self.Lk, self.Nk, self.Pk = list(Lk), list(Nk), list(Pk)
+        self.wav_offset = list(off)
+        self.nodes = nodes
+        self.wav_dtype = torch.float64 if precision == S2W_FP64 else torch.float32
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.b3w_plan_destroy(h)
+            self._h = None
+
+    @property
+    def map_shape(self):
+        return (self.batch, self.P, self.L, 2 * self.L - 1)
+
+    def block_shape(self, i, k):
+        return (self.batch, self.Pk[i], 2 * self.Nk[k] - 1, self.Lk[k], 2 * self.Lk[k] - 1)
+
+    def wav_views(self, packed):
+        """{(i, k): view of block (radial scale i, angular scale k)}."""
+        out = {}
+        for i in range(self.nrad):
+            for k in range(self.nang):
+                o = self.wav_offset[i * self.nang + k]
+                shp = self.block_shape(i, k)
+                out[(i, k)] = packed[o:o + int(np.prod(shp))].view(shp)
+        return out
+
+    def _dev(self):
+        return self._torch.device("cuda", self.device)
+
+    def empty_wav(self):
+        return self._torch.empty(self.wav_offset[-1], dtype=self.wav_dtype, device=self._dev())
+
+    def analysis(self, f, wav=None, scal=None):
+        torch = self._torch
+        if f.dtype != torch.float64 or not f.is_cuda or tuple(f.shape) != self.map_shape or not f.is_contiguous():
+            raise ValueError(f"expected a contiguous float64 CUDA tensor of shape {self.map_shape}")
+        wav = self.empty_wav() if wav is None else wav
+        scal = torch.empty(self.map_shape, dtype=torch.float64, device=self._dev()) if scal is None else scal
+        _check(_lib.b3w_analysis(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(wav.data_ptr()),
+                                 ctypes.c_void_p(scal.data_ptr()), _stream_ptr(torch, self.device)))
+        return wav, scal
+
+    def synthesis(self, wav, scal, f=None):
+        torch = self._torch
+        f = torch.empty(self.map_shape, dtype=torch.float64, device=self._dev()) if f is None else f
+        _check(_lib.b3w_synthesis(self._h, ctypes.c_void_p(wav.data_ptr()), ctypes.c_void_p(scal.data_ptr()),
+                                  ctypes.c_void_p(f.data_ptr()), _stream_ptr(torch, self.device)))
+        return f
+
+    def profile(self, capacity):
+        _check(_lib.b3w_plan_profile(self._h, int(capacity)))
+
+    def profile_read(self):
+        return _profile_read(_lib.b3w_plan_profile_read, self._h)
 
 
 def _autograd():

@@ -26,13 +26,15 @@ s2w_status fail(s2w_status st, const std::string &msg)
 
 struct DevDft {
     int n = 0, n1 = 0, n2 = 0;
-    int *pin = nullptr, *pout = nullptr, *pinv = nullptr;
+    int *pin = nullptr, *pout = nullptr, *inpos = nullptr, *outpos = nullptr;
     double *w1 = nullptr, *w2 = nullptr;
 };
 
 struct DevGrid {
     int L = 0;
-    double *cth = nullptr, *ch = nullptr, *sh = nullptr, *ceps = nullptr, *seps = nullptr;
+    double *pol = nullptr;
+    int npol = 0;
+    double *cth = nullptr, *ctl = nullptr, *ch = nullptr, *sh = nullptr, *ceps = nullptr, *seps = nullptr;
     double *T[2] = {nullptr, nullptr};
     float *T32[2] = {nullptr, nullptr};
     DevDft dft;
@@ -75,6 +77,23 @@ struct s2w_plan_s {
     std::vector<std::string> prof_names;
     int64_t prof_dropped = 0;
     int prof_cap = 0;
+};
+
+struct b3w_plan_s {
+    int L = 0, N = 0, P = 0, B = 1, J0 = 0, J0p = 0, Jp = 0;
+    double lambda = 2.0, nu = 2.0, tau = 1.0;
+    s2w_precision prec = S2W_FP64;
+    s2w_plan sp = nullptr;                   // sphere plan over B * P shells
+    int nang = 0, nrad = 0;
+    std::vector<int> Pj;                     // radial band limit per radial scale
+    std::vector<int64_t> wav_off;            // [nrad * nang + 1]
+    std::vector<double> nodes;
+    double *Zf = nullptr, *Zi = nullptr;     // [P][P]: W_k K_p(r_k) and K_p(r_k) (as [k][p])
+    double *phi = nullptr;                   // [P][L]: sqrt(4pi/(2l+1)) Phi_l0p
+    std::vector<double *> G, H;              // per radial scale: [P_j'][P], [P][P_j']
+    double *flmp = nullptr, *shell = nullptr, *shell2 = nullptr;
+    std::vector<void *> allocs;
+    bool alive = true;
 };
 
 namespace {
@@ -162,9 +181,15 @@ bool make_grid(s2w_plan p, int L)
     g.L = L;
     s2w::ThetaTables tt;
     s2w::theta_tables(L, tt);
-    if (!upload(p, g.cth, tt.cth) || !upload(p, g.ch, tt.ch) || !upload(p, g.sh, tt.sh) ||
+    if (!upload(p, g.cth, tt.cth) || !upload(p, g.ctl, tt.cth_lo) || !upload(p, g.ch, tt.ch) || !upload(p, g.sh, tt.sh) ||
         !upload(p, g.ceps, tt.ch_eps) || !upload(p, g.seps, tt.sh_eps))
         return false;
+    g.npol = s2w::polar_count(L);
+    if (g.npol > 0) {
+        std::vector<double> pt;
+        s2w::polar_table(L, p->nglob, g.npol, pt);
+        if (!upload(p, g.pol, pt)) return false;
+    }
     for (int si = 0; si < 2; ++si) {
         std::vector<double> T;
         s2w::theta_matrix(L, si == 0 ? 1 : -1, T);
@@ -177,18 +202,22 @@ bool make_grid(s2w_plan p, int L)
     const int n = 2 * L - 1;
     s2w::PfaPlan pp;
     s2w::pfa_plan(n, pp);
-    std::vector<int> pin(n), pout(n), pinv(n);
+    // input index (m1 n2 + m2 n1) mod n sits at LDS position m1 n2 + m2; output
+    // frequency (a1 e1 + a2 e2) mod n ends at position a1 n2 + a2
+    std::vector<int> pin(n), pout(n), inpos(n), outpos(n);
     for (int m1 = 0; m1 < pp.n1; ++m1)
         for (int m2 = 0; m2 < pp.n2; ++m2) {
             const int pos = m1 * pp.n2 + m2;
             pin[pos] = (int)(((long long)m1 * pp.n2 + (long long)m2 * pp.n1) % n);
             pout[pos] = (int)(((long long)m1 * pp.e1 + (long long)m2 * pp.e2) % n);
+            inpos[pin[pos]] = pos;
+            outpos[pout[pos]] = pos;
         }
-    for (int pos = 0; pos < n; ++pos) pinv[pout[pos]] = pos;
     g.dft.n = n;
     g.dft.n1 = pp.n1;
     g.dft.n2 = pp.n2;
-    if (!upload(p, g.dft.pin, pin) || !upload(p, g.dft.pout, pout) || !upload(p, g.dft.pinv, pinv) ||
+    if (!upload(p, g.dft.pin, pin) || !upload(p, g.dft.pout, pout) || !upload(p, g.dft.inpos, inpos) ||
+        !upload(p, g.dft.outpos, outpos) ||
         !upload(p, g.dft.w1, pp.w1) || !upload(p, g.dft.w2, pp.w2))
         return false;
     p->grids[L] = g;
@@ -224,7 +253,8 @@ DftArgs dft_args(const DevGrid &g, const void *in, long istride, void *out, long
     a.n2 = g.dft.n2;
     a.pin = g.dft.pin;
     a.pout = g.dft.pout;
-    a.pinv = g.dft.pinv;
+    a.inpos = g.dft.inpos;
+    a.outpos = g.dft.outpos;
     a.w1 = g.dft.w1;
     a.w2 = g.dft.w2;
     a.scale = scale;
@@ -254,6 +284,9 @@ LsumArgs lsum_args(s2w_plan p, const DevGrid &g, int mcount, const std::vector<i
     a.smant = p->smant;
     a.sexp = p->sexp;
     a.cth = g.cth;
+    a.ctl = g.ctl;
+    a.pol = g.pol;
+    a.npol = g.npol;
     a.ch = g.ch;
     a.sh = g.sh;
     a.ceps = g.ceps;
@@ -279,6 +312,9 @@ TsumArgs tsum_args(s2w_plan p, const DevGrid &g, int mcount, const std::vector<i
     a.smant = p->smant;
     a.sexp = p->sexp;
     a.cth = g.cth;
+    a.ctl = g.ctl;
+    a.pol = g.pol;
+    a.npol = g.npol;
     a.ch = g.ch;
     a.sh = g.sh;
     a.ceps = g.ceps;
@@ -397,75 +433,25 @@ void theta_quadrature32(s2w_plan p, const DevGrid &g, const float *F, float *H, 
     }
 }
 
-// maps (FP64) -> flm (FP64 [B][L][L]) with FP32 DFT / quadrature and the batched theta-sum
-void sht_forward_mixed(s2w_plan p, const double *f, double *flm_out, hipStream_t st)
-{
-    const DevGrid &g = p->grids[p->L];
-    const int L = p->L, na = 2 * L - 1;
-    float *A32 = (float *)p->bufA, *B32 = (float *)p->bufB, *C32 = (float *)p->bufC;
+// Runs a plan on its first nb <= B maps: the plan's batch and the packed scale
+// offsets follow nb while the scope lives (workspace is sized for B).
+struct BatchScope {
+    s2w_plan p;
+    int B0;
+    std::vector<int64_t> off0;
+    BatchScope(s2w_plan p_, int nb) : p(p_), B0(p_->B), off0(p_->wav_off)
     {
-        const DftArgs da = dft_args(g, f, na, A32, L, p->B * L, 2.0 * M_PI / na);
-        Prof pr_(p, "dft_r2c_f32", dft_flop(da.n, da.nrows), st);
-        s2w::launch_dft_r2c(da, st, true, true);
+        p->B = nb;
+        const int K = (int)p->S.s.size();
+        for (int k = 0; k < K; ++k)
+            p->wav_off[k + 1] = p->wav_off[k] + (int64_t)nb * (2 * p->S.s[k].N - 1) * p->S.s[k].L * (2 * p->S.s[k].L - 1);
     }
-    std::vector<int> n0{0};
-    GammaArgs ga = gamma_args(p, L, L, L, L, n0, 1);
-    ga.src = A32;
-    ga.dst = B32;
-    ga.sgn = -1.0;
-    sig_counts(L, 0, ga.M0, ga.M1);
+    ~BatchScope()
     {
-        Prof pr_(p, "gamma_r2c_f32", 8.0 * ga.B * ga.M * ga.L, st);
-        s2w::launch_gamma_r2c(ga, st, true);
+        p->B = B0;
+        p->wav_off = off0;
     }
-    theta_quadrature32(p, g, B32, C32, L, 1, 0, st);
-    TsumArgs ta = tsum_args(p, g, L, n0, 0);
-    ta.w[0] = p->wsht;
-    ta.wstride = 0;
-    s2w::MixIn mi{};
-    mi.B = p->B;
-    mi.h[0] = C32;
-    mi.out[0] = flm_out;
-    {
-        Prof pr_(p, "tsum_mm", rec_flop(ta.L, ta.mcount, n0, 1, p->B), st);
-        s2w::launch_tsum_mm(ta, mi, 1, st);
-    }
-}
-
-// flm (FP64) -> maps (FP64) with the batched l-sum and FP32 DFT
-void sht_inverse_mixed(s2w_plan p, const double *flm_in, double *f, hipStream_t st)
-{
-    const DevGrid &g = p->grids[p->L];
-    const int L = p->L, na = 2 * L - 1;
-    float *A32 = (float *)p->bufA, *B32 = (float *)p->bufB, *C32 = (float *)p->bufC;
-    std::vector<int> n0{0};
-    LsumArgs la = lsum_args(p, g, L, n0);
-    la.flm = flm_in;
-    la.flm_m = L;
-    la.flm_l = L;
-    la.w[0] = p->wsht;
-    la.wstride = 0;
-    s2w::MixOut mo{};
-    mo.B = p->B;
-    mo.out[0] = A32;
-    {
-        Prof pr_(p, "lsum_mm", rec_flop(la.L, la.mcount, n0, 1, p->B), st);
-        s2w::launch_lsum_mm(la, mo, 1, st);
-    }
-    GammaArgs ga = gamma_args(p, L, L, L, L, n0, 1);
-    ga.src = A32;
-    ga.dst = B32;
-    {
-        Prof pr_(p, "gamma_c2r_f32", 8.0 * ga.B * ga.M * ga.L, st);
-        s2w::launch_gamma_c2r(ga, st, true);
-    }
-    {
-        const DftArgs da = dft_args(g, B32, L, C32, na, p->B * L, 1.0);
-        Prof pr_(p, "dft_c2r_f32", dft_flop(da.n, da.nrows), st);
-        s2w::launch_dft_c2r(da, st, true);
-    }
-    s2w::launch_convert(C32, f, (size_t)p->B * L * na, false, st);
-}
+};
 
 s2w_status check_plan(s2w_plan p)
 {
@@ -585,6 +571,10 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
     for (int k = 0; k < K; ++k)
         p->wav_off[k + 1] = p->wav_off[k] + (int64_t)batch * (2 * S.s[k].N - 1) * S.s[k].L * (2 * S.s[k].L - 1);
 
+    // global n list: top scale's n values plus n = 0
+    p->nglob = S.s.back().n;
+    if (std::find(p->nglob.begin(), p->nglob.end(), 0) == p->nglob.end()) p->nglob.push_back(0);
+
     // grids
     if (!make_grid(p, L) || !make_grid(p, p->Lphi)) return oom("grid tables");
     for (int k = 0; k < K; ++k) {
@@ -592,10 +582,6 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
         if (!make_gamma_tw(p, 2 * S.s[k].N - 1)) return oom("gamma twiddles");
     }
     if (!make_gamma_tw(p, 1)) return oom("gamma twiddles");
-
-    // global n list: top scale's n values plus n = 0
-    p->nglob = S.s.back().n;
-    if (std::find(p->nglob.begin(), p->nglob.end(), 0) == p->nglob.end()) p->nglob.push_back(0);
     {
         s2w::RecTables R;
         s2w::rec_tables(L, p->nglob, R);
@@ -712,23 +698,20 @@ s2w_status s2w_sht_inverse(s2w_plan p, const double *flm, double *f, void *strea
     return post_launch("s2w_sht_inverse");
 }
 
-s2w_status s2w_analysis(s2w_plan p, const double *f, void *wav_, double *scal, void *stream)
+// Scaling and wavelet coefficients from harmonic coefficients flm (internal
+// layout [B][L][L], m-major); the scaling part is skipped when scal is null.
+static void analysis_from_flm(s2w_plan p, const double *flm, void *wav_, double *scal, hipStream_t st)
 {
-    if (s2w_status st = check_plan(p)) return st;
-    if (!f || !wav_ || !scal) return fail(S2W_EINVAL, "null buffer");
-    hipStream_t st = (hipStream_t)stream;
     double *wav = (double *)wav_;
     const int B = p->B;
     const bool mixed = p->prec == S2W_MIXED;
-    if (mixed) sht_forward_mixed(p, f, p->flm, st);
-    else sht_forward_internal(p, f, p->flm, st);
     // scaling coefficients: W^Phi = Y^{-1}_{L_phi}(Phi f)
-    {
+    if (scal) {
         const DevGrid &g = p->grids[p->Lphi];
         const int Lp = p->Lphi;
         std::vector<int> n0{0};
         LsumArgs la = lsum_args(p, g, Lp, n0);
-        la.flm = p->flm;
+        la.flm = flm;
         la.flm_m = p->L;
         la.flm_l = p->L;
         la.w[0] = p->wphi;
@@ -751,7 +734,7 @@ s2w_status s2w_analysis(s2w_plan p, const double *f, void *wav_, double *scal, v
             const auto &si = p->S.s[grp.scales[0]];
             const int nn = (int)si.n.size(), ng = 2 * si.N - 1;
             LsumArgs la = lsum_args(p, g, Lk, si.n);
-            la.flm = p->flm;
+            la.flm = flm;
             la.flm_m = p->L;
             la.flm_l = p->L;
             la.wstride = Lk;
@@ -781,7 +764,7 @@ s2w_status s2w_analysis(s2w_plan p, const double *f, void *wav_, double *scal, v
                 s2w::launch_dft_c2r(da, st, true);
             }
         }
-        return post_launch("s2w_analysis");
+        return;
     }
     for (auto &grp : p->groups) {
         const DevGrid &g = p->grids[grp.L];
@@ -789,7 +772,7 @@ s2w_status s2w_analysis(s2w_plan p, const double *f, void *wav_, double *scal, v
         const auto &si = p->S.s[grp.scales[0]];
         const int nn = (int)si.n.size(), ng = 2 * si.N - 1;
         LsumArgs la = lsum_args(p, g, Lk, si.n);
-        la.flm = p->flm;
+        la.flm = flm;
         la.flm_m = p->L;
         la.flm_l = p->L;
         la.wstride = Lk;
@@ -809,14 +792,24 @@ s2w_status s2w_analysis(s2w_plan p, const double *f, void *wav_, double *scal, v
             { const DftArgs da_ = dft_args(g, p->bufB, Lk, wav + p->wav_off[k], 2 * Lk - 1, B * ng * Lk, 1.0); Prof pr_(p, "dft_c2r", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_c2r(da_, st); }
         }
     }
-    return post_launch("s2w_analysis");
-}
+    }
 
-s2w_status s2w_synthesis(s2w_plan p, const void *wav_, const double *scal, double *f, void *stream)
+s2w_status s2w_analysis(s2w_plan p, const double *f, void *wav_, double *scal, void *stream)
 {
     if (s2w_status st = check_plan(p)) return st;
     if (!f || !wav_ || !scal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    // the forward SHT of the input map runs in FP64 in both forms: it is shared by every
+    // scale, and FP32 rounding here would spread as white noise across all degrees
+    sht_forward_internal(p, f, p->flm, st);
+    analysis_from_flm(p, p->flm, wav_, scal, st);
+    return post_launch("s2w_analysis");
+}
+
+// Harmonic coefficients fhat (internal layout) of the synthesis before the
+// final inverse SHT; the scaling part is left out when scal is null.
+static void synthesis_to_fhat(s2w_plan p, const void *wav_, const double *scal, double *fhat, hipStream_t st)
+{
     const double *wav = (const double *)wav_;
     const int B = p->B;
     const int npar = (p->N - 1) & 1;
@@ -888,7 +881,7 @@ s2w_status s2w_synthesis(s2w_plan p, const void *wav_, const double *scal, doubl
         { std::vector<int> ns_(ta.nval, ta.nval + ta.nn); Prof pr_(p, "tsum", rec_flop(ta.L, ta.mcount, ns_, NS, B), st); s2w::launch_tsum(ta, NS, B, st); }
     }
     // scaling: Phi * Y(W^Phi)
-    {
+    if (scal) {
         const DevGrid &g = p->grids[p->Lphi];
         const int Lp = p->Lphi;
         std::vector<int> n0{0};
@@ -908,7 +901,7 @@ s2w_status s2w_synthesis(s2w_plan p, const void *wav_, const double *scal, doubl
         { std::vector<int> ns_(ta.nval, ta.nval + ta.nn); Prof pr_(p, "tsum", rec_flop(ta.L, ta.mcount, ns_, 1, B), st); s2w::launch_tsum(ta, 1, B, st); }
     }
     CombineArgs ca{};
-    ca.out = p->fhat;
+    ca.out = fhat;
     ca.L = p->L;
     ca.nterms = 0;
     for (size_t k = 0; k < p->S.s.size(); ++k) {
@@ -919,7 +912,7 @@ s2w_status s2w_synthesis(s2w_plan p, const void *wav_, const double *scal, doubl
         t.phr = p->F.xi_imag ? 0.0 : 1.0;
         t.phi = p->F.xi_imag ? 1.0 : 0.0;
     }
-    {
+    if (scal) {
         auto &t = ca.t[ca.nterms++];
         t.P = p->Pphi;
         t.L = p->Lphi;
@@ -928,6 +921,14 @@ s2w_status s2w_synthesis(s2w_plan p, const void *wav_, const double *scal, doubl
         t.phi = 0.0;
     }
     { Prof pr_(p, "combine", 0.0, st); s2w::launch_combine(ca, B, st); }
+}
+
+s2w_status s2w_synthesis(s2w_plan p, const void *wav_, const double *scal, double *f, void *stream)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (!f || !wav_ || !scal) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    synthesis_to_fhat(p, wav_, scal, p->fhat, st);
     sht_inverse_internal(p, p->fhat, f, st);
     return post_launch("s2w_synthesis");
 }
@@ -1103,6 +1104,251 @@ s2w_status s2w_synthesis_adjoint(s2w_plan p, const double *gf, void *gwav, doubl
     (void)gf; (void)gwav; (void)gscal; (void)stream;
     if (s2w_status st = check_plan(p)) return st;
     return fail(S2W_EUNSUPPORTED, "s2w_synthesis_adjoint is not implemented yet");
+}
+
+
+// ------------------------------------------------------------------ ball ---
+
+s2w_status s2w_host_laguerre_rule(int P, double tau, double *nodes, double *weights)
+{
+    if (P < 1 || !(tau > 0.0) || !nodes || !weights) return fail(S2W_EINVAL, "bad arguments");
+    s2w::LaguerreRule R;
+    s2w::laguerre_rule(P, tau, R);
+    std::memcpy(nodes, R.r.data(), sizeof(double) * P);
+    std::memcpy(weights, R.W.data(), sizeof(double) * P);
+    return S2W_OK;
+}
+
+static void free_ball(b3w_plan p)
+{
+    for (void *v : p->allocs) (void)hipFree(v);
+    p->allocs.clear();
+    if (p->sp) s2w_plan_destroy(p->sp);
+    p->sp = nullptr;
+}
+
+static bool ball_upload(b3w_plan p, double *&ptr, const std::vector<double> &h)
+{
+    void *v = nullptr;
+    if (hipMalloc(&v, std::max<size_t>(h.size(), 1) * sizeof(double)) != hipSuccess) return false;
+    p->allocs.push_back(v);
+    ptr = (double *)v;
+    return hipMemcpy(ptr, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+static bool ball_alloc(b3w_plan p, double *&ptr, size_t count)
+{
+    void *v = nullptr;
+    if (hipMalloc(&v, std::max<size_t>(count, 1) * sizeof(double)) != hipSuccess) return false;
+    p->allocs.push_back(v);
+    ptr = (double *)v;
+    return true;
+}
+
+s2w_status b3w_plan_create(b3w_plan *out, int L, int N, int P, double lambda, double nu, int J0, int J0p,
+                           double tau, int batch, s2w_precision precision, int device, unsigned flags)
+{
+    if (!out) return fail(S2W_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (P < 1) return fail(S2W_EINVAL, "P must be >= 1");
+    if (!(nu > 1.0)) return fail(S2W_EINVAL, "nu must be > 1");
+    if (!(tau > 0.0)) return fail(S2W_EINVAL, "tau must be > 0");
+    if (batch < 1) return fail(S2W_EINVAL, "batch must be >= 1");
+    if (flags != 0) return fail(S2W_EINVAL, "flags must be 0");
+    int Jp = 0;
+    while (std::pow(nu, (double)Jp) < (double)P) ++Jp;
+    if (J0p < 0 || J0p > Jp) return fail(S2W_EINVAL, "J0p must satisfy 0 <= J0p <= J'");
+    if ((long long)batch * P > (1LL << 30)) return fail(S2W_EINVAL, "batch * P too large");
+    b3w_plan p = new (std::nothrow) b3w_plan_s;
+    if (!p) return fail(S2W_ENOMEM, "host allocation failed");
+    p->L = L; p->N = N; p->P = P; p->B = batch; p->J0 = J0; p->J0p = J0p; p->Jp = Jp;
+    p->lambda = lambda; p->nu = nu; p->tau = tau; p->prec = precision;
+    if (s2w_status st = s2w_plan_create(&p->sp, L, N, lambda, J0, batch * P, precision, device, 0)) {
+        delete p;
+        return st;
+    }
+    auto oom = [&](const char *what) {
+        free_ball(p);
+        delete p;
+        return fail(S2W_ENOMEM, std::string("device allocation failed: ") + what);
+    };
+    s2w_plan sp = p->sp;
+    p->nang = (int)sp->S.s.size();
+    for (int jp = J0p; jp <= Jp; ++jp) {
+        const double v = std::ceil(std::pow(nu, (double)jp + 1.0) - 1e-12);
+        p->Pj.push_back((int)std::min<double>(v, (double)P));
+    }
+    p->nrad = (int)p->Pj.size();
+    // layout
+    p->wav_off.assign((size_t)p->nrad * p->nang + 1, 0);
+    {
+        int64_t off = 0;
+        for (int i = 0; i < p->nrad; ++i)
+            for (int k = 0; k < p->nang; ++k) {
+                p->wav_off[(size_t)i * p->nang + k] = off;
+                const auto &si = sp->S.s[k];
+                off += (int64_t)batch * p->Pj[i] * (2 * si.N - 1) * si.L * (2 * si.L - 1);
+            }
+        p->wav_off.back() = off;
+    }
+    // radial rules and matrices
+    s2w::LaguerreRule R;
+    s2w::laguerre_rule(P, tau, R);
+    p->nodes = R.r;
+    std::vector<double> K;
+    s2w::laguerre_basis(R, P, K);                       // [p][k]
+    std::vector<double> zf((size_t)P * P), zi((size_t)P * P);
+    for (int q = 0; q < P; ++q)
+        for (int k = 0; k < P; ++k) {
+            zf[(size_t)q * P + k] = R.W[k] * K[(size_t)q * P + k];
+            zi[(size_t)k * P + q] = K[(size_t)q * P + k];
+        }
+    if (!ball_upload(p, p->Zf, zf) || !ball_upload(p, p->Zi, zi)) return oom("radial tables");
+    p->G.assign(p->nrad, nullptr);
+    p->H.assign(p->nrad, nullptr);
+    for (int i = 0; i < p->nrad; ++i) {
+        const int jp = J0p + i, Pi = p->Pj[i];
+        std::vector<double> kap(P);
+        for (int q = 0; q < P; ++q) kap[q] = std::sqrt(std::max(0.0, s2w::kappa2_lambda(q / std::pow(nu, (double)jp), nu)));
+        s2w::LaguerreRule Ri;
+        s2w::laguerre_rule(Pi, tau, Ri);
+        std::vector<double> Ki;
+        s2w::laguerre_basis(Ri, P, Ki);                 // [p < P][k < Pi]
+        std::vector<double> g((size_t)Pi * P), h((size_t)P * Pi);
+        for (int q = 0; q < P; ++q)
+            for (int k = 0; k < Pi; ++k) {
+                g[(size_t)k * P + q] = Ki[(size_t)q * Pi + k] * kap[q];
+                h[(size_t)q * Pi + k] = kap[q] * Ri.W[k] * Ki[(size_t)q * Pi + k];
+            }
+        if (!ball_upload(p, p->G[i], g) || !ball_upload(p, p->H[i], h)) return oom("radial tables");
+    }
+    {
+        std::vector<double> ph((size_t)P * L);
+        for (int q = 0; q < P; ++q) {
+            const double b = s2w::k_lambda(q / std::pow(nu, (double)J0p), nu);
+            for (int l = 0; l < L; ++l) {
+                const double a = s2w::k_lambda(l / std::pow(lambda, (double)J0), lambda);
+                ph[(size_t)q * L + l] = std::sqrt(std::max(0.0, a + b - a * b));
+            }
+        }
+        if (!ball_upload(p, p->phi, ph)) return oom("scaling filter");
+    }
+    const size_t per = (size_t)batch * P * L * L * 2;
+    if (!ball_alloc(p, p->flmp, per) || !ball_alloc(p, p->shell, per) || !ball_alloc(p, p->shell2, per))
+        return oom("workspace");
+    if (hipDeviceSynchronize() != hipSuccess) {
+        free_ball(p);
+        delete p;
+        return fail(S2W_EHIP, "device synchronisation failed during plan creation");
+    }
+    *out = p;
+    return S2W_OK;
+}
+
+s2w_status b3w_plan_destroy(b3w_plan p)
+{
+    if (!p) return S2W_OK;
+    if (!p->alive) return fail(S2W_ESTATE, "plan destroyed twice");
+    p->alive = false;
+    free_ball(p);
+    delete p;
+    return S2W_OK;
+}
+
+s2w_status b3w_plan_layout(b3w_plan p, int *nang, int *nrad, int *Lk, int *Nk, int *Pk, int64_t *wav_offset,
+                           double *nodes)
+{
+    if (!p || !p->alive) return fail(S2W_EINVAL, "invalid plan");
+    if (nang) *nang = p->nang;
+    if (nrad) *nrad = p->nrad;
+    for (int k = 0; k < p->nang; ++k) {
+        if (Lk) Lk[k] = p->sp->S.s[k].L;
+        if (Nk) Nk[k] = p->sp->S.s[k].N;
+    }
+    if (Pk)
+        for (int i = 0; i < p->nrad; ++i) Pk[i] = p->Pj[i];
+    if (wav_offset)
+        for (size_t i = 0; i < p->wav_off.size(); ++i) wav_offset[i] = p->wav_off[i];
+    if (nodes) std::memcpy(nodes, p->nodes.data(), sizeof(double) * p->P);
+    return S2W_OK;
+}
+
+// Radial matrix A ([rows][kin]) applied to every map: out[b] = A in[b] (+ out[b] when acc),
+// rows of 2 L^2 doubles (internal harmonic layout).
+static void ball_radial(b3w_plan p, const double *A, const double *in, int kin, double *out, int rows, bool acc,
+                        hipStream_t st)
+{
+    const size_t row = (size_t)2 * p->L * p->L;
+    for (int b = 0; b < p->B; ++b) {
+        Prof pr_(p->sp, "gemm_radial", 2.0 * rows * kin * (double)row, st);
+        s2w::launch_gemm(A, in + (size_t)b * kin * row, out + (size_t)b * rows * row, rows, (int)row, kin, st, acc);
+    }
+}
+
+s2w_status b3w_analysis(b3w_plan p, const double *f, void *wav, double *scal, void *stream)
+{
+    if (!p || !p->alive) return fail(S2W_EINVAL, "invalid plan");
+    if (!f || !wav || !scal) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    s2w_plan sp = p->sp;
+    const int B = p->B, P = p->P, L = p->L;
+    const size_t esz = p->prec == S2W_MIXED ? sizeof(float) : sizeof(double);
+    {
+        BatchScope bs(sp, B * P);
+        sht_forward_internal(sp, f, p->shell, st);                         // Y per shell
+        ball_radial(p, p->Zf, p->shell, P, p->flmp, P, false, st);          // f_lmp
+        { Prof pr_(sp, "scale_pl", 0.0, st); s2w::launch_scale_pl(p->flmp, p->shell2, p->phi, P, L, (size_t)B * P * L * L, st); }
+        ball_radial(p, p->Zi, p->shell2, P, p->shell, P, false, st);        // Phi f at the nodes
+        sht_inverse_internal(sp, p->shell, scal, st);                        // W^Phi
+    }
+    for (int i = 0; i < p->nrad; ++i) {
+        const int Pi = p->Pj[i];
+        BatchScope bs(sp, B * Pi);
+        ball_radial(p, p->G[i], p->flmp, P, p->shell, Pi, false, st);        // g^{j'}_lm(r'_k)
+        analysis_from_flm(sp, p->shell, (char *)wav + esz * p->wav_off[(size_t)i * p->nang], nullptr, st);
+    }
+    return post_launch("b3w_analysis");
+}
+
+s2w_status b3w_synthesis(b3w_plan p, const void *wav, const double *scal, double *f, void *stream)
+{
+    if (!p || !p->alive) return fail(S2W_EINVAL, "invalid plan");
+    if (!f || !wav || !scal) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    s2w_plan sp = p->sp;
+    const int B = p->B, P = p->P, L = p->L;
+    const size_t esz = p->prec == S2W_MIXED ? sizeof(float) : sizeof(double);
+    {
+        BatchScope bs(sp, B * P);
+        sht_forward_internal(sp, scal, p->shell, st);
+        ball_radial(p, p->Zf, p->shell, P, p->shell2, P, false, st);
+        { Prof pr_(sp, "scale_pl", 0.0, st); s2w::launch_scale_pl(p->shell2, p->flmp, p->phi, P, L, (size_t)B * P * L * L, st); }
+    }
+    for (int i = 0; i < p->nrad; ++i) {
+        const int Pi = p->Pj[i];
+        BatchScope bs(sp, B * Pi);
+        synthesis_to_fhat(sp, (const char *)wav + esz * p->wav_off[(size_t)i * p->nang], nullptr, p->shell, st);
+        ball_radial(p, p->H[i], p->shell, Pi, p->flmp, P, true, st);        // f_lmp += Psi^dagger Q W
+    }
+    {
+        BatchScope bs(sp, B * P);
+        ball_radial(p, p->Zi, p->flmp, P, p->shell, P, false, st);
+        sht_inverse_internal(sp, p->shell, f, st);
+    }
+    return post_launch("b3w_synthesis");
+}
+
+s2w_status b3w_plan_profile(b3w_plan p, int capacity)
+{
+    if (!p || !p->alive) return fail(S2W_EINVAL, "invalid plan");
+    return s2w_plan_profile(p->sp, capacity);
+}
+
+s2w_status b3w_plan_profile_read(b3w_plan p, int max, char *names, double *total_ms, int64_t *launches,
+                                 double *flop, int *count, int64_t *dropped)
+{
+    if (!p || !p->alive) return fail(S2W_EINVAL, "invalid plan");
+    return s2w_plan_profile_read(p->sp, max, names, total_ms, launches, flop, count, dropped);
 }
 
 }  // extern "C"

@@ -151,6 +151,99 @@ void make_filters(const Scales &S, Filters &F)
     }
 }
 
+double kappa2_lambda(double t, double lambda)
+{
+    const long double lam = lambda;
+    const long double lo = std::max((long double)t / lam, 1.0L / lam), hi = std::min((long double)t, 1.0L);
+    if (!(hi > lo)) return 0.0;
+    return (double)(ts_integral(lo, hi, lam) / ts_integral(1.0L / lam, 1.0L, lam));
+}
+
+// ------------------------------------------------------- Laguerre rule -----
+//
+// The monic polynomials orthogonal for x^2 e^{-x} obey
+//   pi_{k+1} = (x - (2k+3)) pi_k - k(k+2) pi_{k-1},
+// so the rule's nodes are the eigenvalues of the symmetric tridiagonal matrix
+// with diagonal 2k+3 and off-diagonal sqrt(k(k+2)) (Golub-Welsch).  They are
+// found by Sturm-sequence bisection in long double and polished by Newton steps
+// on the orthonormal functions psi_p(x) = sqrt(p!/(p+2)!) e^{-x/2} L^{(2)}_p(x),
+//   psi_{p+1} = ((2p+3-x) psi_p - sqrt(p(p+2)) psi_{p-1}) / sqrt((p+1)(p+3)),
+// whose squares also give the Christoffel numbers: e^{x_k} w_k = 1 / sum_p psi_p(x_k)^2.
+
+namespace {
+
+void laguerre_psi(int P, long double x, std::vector<long double> &ps)
+{
+    ps.assign(P + 1, 0.0L);
+    ps[0] = expl(-0.5L * x) / sqrtl(2.0L);
+    if (P >= 1) ps[1] = (3.0L - x) * ps[0] / sqrtl(3.0L);
+    for (int p = 1; p < P; ++p)
+        ps[p + 1] = ((2.0L * p + 3.0L - x) * ps[p] - sqrtl((long double)p * (p + 2.0L)) * ps[p - 1]) /
+                    sqrtl((p + 1.0L) * (p + 3.0L));
+}
+
+int sturm_below(int P, long double x)
+{
+    int cnt = 0;
+    long double q = 0.0L;
+    for (int k = 0; k < P; ++k) {
+        const long double d = 2.0L * k + 3.0L;
+        const long double e2 = (long double)k * (k + 2.0L);
+        q = (k == 0) ? d - x : d - x - e2 / q;
+        if (q == 0.0L) q = -1e-4000L;
+        if (q < 0.0L) ++cnt;
+    }
+    return cnt;
+}
+
+}  // namespace
+
+void laguerre_rule(int P, double tau, LaguerreRule &R)
+{
+    R.P = P;
+    R.tau = tau;
+    R.x.assign(P, 0.0);
+    R.r.assign(P, 0.0);
+    R.W.assign(P, 0.0);
+    if (P <= 0) return;
+    long double hi = 0.0L;
+    for (int k = 0; k < P; ++k)
+        hi = std::max(hi, 2.0L * k + 3.0L + sqrtl((long double)k * (k + 2.0L)) + sqrtl((k + 1.0L) * (k + 3.0L)));
+    std::vector<long double> ps;
+    for (int i = 0; i < P; ++i) {
+        long double a = 0.0L, b = hi;
+        for (int it = 0; it < 200 && b - a > 1e-19L * b; ++it) {
+            const long double m = 0.5L * (a + b);
+            if (sturm_below(P, m) > i) b = m;
+            else a = m;
+        }
+        long double x = 0.5L * (a + b);
+        for (int it = 0; it < 3; ++it) {
+            laguerre_psi(P, x, ps);
+            // x d/dx (e^{-x/2} c_P L_P) = P psi_P - sqrt(P(P+2)) psi_{P-1} - x psi_P / 2
+            const long double D = P * ps[P] - sqrtl((long double)P * (P + 2.0L)) * ps[P - 1] - 0.5L * x * ps[P];
+            if (D != 0.0L) x -= x * ps[P] / D;
+        }
+        laguerre_psi(P, x, ps);
+        long double s2 = 0.0L;
+        for (int p = 0; p < P; ++p) s2 += ps[p] * ps[p];
+        R.x[i] = (double)x;
+        R.r[i] = (double)((long double)tau * x);
+        R.W[i] = (double)(powl((long double)tau, 3.0L) / s2);
+    }
+}
+
+void laguerre_basis(const LaguerreRule &R, int Pb, std::vector<double> &K)
+{
+    K.assign((size_t)Pb * R.P, 0.0);
+    std::vector<long double> ps;
+    const long double s = powl((long double)R.tau, -1.5L);
+    for (int k = 0; k < R.P; ++k) {
+        laguerre_psi(std::max(Pb, 1), (long double)R.x[k], ps);
+        for (int p = 0; p < Pb; ++p) K[(size_t)p * R.P + k] = (double)(ps[p] * s);
+    }
+}
+
 // -------------------------------------------------- theta quadrature (MW) ---
 //
 // For F, d of band limit L and parity sigma on the torus, with n = 2L-1 samples
@@ -225,12 +318,16 @@ void theta_matrix(int L, int sigma, std::vector<double> &T)
 void theta_tables(int L, ThetaTables &T)
 {
     const int n = 2 * L - 1;
-    T.cth.resize(L); T.ch.resize(L); T.sh.resize(L); T.ch_eps.resize(L); T.sh_eps.resize(L);
+    T.cth.resize(L); T.cth_lo.resize(L); T.ch.resize(L); T.sh.resize(L); T.ch_eps.resize(L); T.sh_eps.resize(L);
     for (int b = 0; b < L; ++b) {
         long double th = kPiL * (2.0L * b + 1.0L) / n;
         long double c = cosl(0.5L * th), s = sinl(0.5L * th);
         if (b == L - 1) { c = 0.0L; s = 1.0L; th = kPiL; }
-        T.cth[b] = (b == L - 1) ? -1.0 : (double)cosl(th);
+        // cos(theta) from the half angle, measured from the nearer pole, so that 1 - |cos|
+        // keeps its relative precision there (the recursion is most sensitive near the poles)
+        const long double ct = (2 * (2 * b + 1) < n) ? 1.0L - 2.0L * s * s : 2.0L * c * c - 1.0L;
+        T.cth[b] = (b == L - 1) ? -1.0 : (double)ct;
+        T.cth_lo[b] = (b == L - 1) ? 0.0 : (double)(ct - (long double)T.cth[b]);
         T.ch[b] = (double)c;
         T.sh[b] = (double)s;
         T.ch_eps[b] = (c != 0.0L) ? (double)((c - (long double)T.ch[b]) / (long double)T.ch[b]) : 0.0;
@@ -307,6 +404,84 @@ void rec_tables(int L, const std::vector<int> &ns, RecTables &R)
     });
 }
 
+int polar_count(int L) { return L >= 64 ? 4 : 0; }
+
+// Near theta = 0 and pi the characteristic roots of the three-term recursion
+// nearly coincide, and FP64 rounding grows like u l^2 there (about 1e-11 at
+// l ~ 10^3 on the first and last samples).  The few samples next to the poles are
+// therefore taken from this table: the unscaled recursion
+//   l sqrt(((l+1)^2-m^2)((l+1)^2-n^2)) d^{l+1}
+//       = (2l+1)(l(l+1) cos(theta) - mn) d^l - (l+1) sqrt((l^2-m^2)(l^2-n^2)) d^{l-1}
+// in long double (64-bit mantissa), from the closed-form start at l0 = max(|m|,|n|),
+// with cos(theta) from the half angle and a power-of-two exponent carried aside.
+namespace {
+// one (m, n) column: out[p][l], p < 2 np, already zeroed
+void polar_column(int L, int m, int n, int np, double *out)
+{
+    const int P = 2 * np, nsamp = 2 * L - 1;
+    {
+        const int l0 = std::max(std::abs(m), std::abs(n));
+        if (l0 >= L) return;
+        std::vector<double> A(L), B(L), S(L);
+        double mant;
+        int ex;
+        rec_column(L, m, n, A.data(), B.data(), S.data(), mant, ex);
+        if (mant == 0.0) return;
+        const int p1 = std::abs(m + n), p2 = std::abs(m - n);
+        const long double mm = (long double)m * m, nq = (long double)n * n, mn = (long double)m * n;
+        for (int p = 0; p < P; ++p) {
+            const int b = p < np ? p : L - P + p;
+            const long double th = kPiL * (2.0L * b + 1.0L) / nsamp;
+            long double c = cosl(0.5L * th), s = sinl(0.5L * th), x;
+            if (b == L - 1) { c = 0.0L; s = 1.0L; x = -1.0L; }
+            else x = (2 * (2 * b + 1) < nsamp) ? 1.0L - 2.0L * s * s : 2.0L * c * c - 1.0L;
+            if ((c == 0.0L && p1 > 0) || (s == 0.0L && p2 > 0)) continue;
+            double *o = out + (size_t)p * L;
+            const long double lg = log2l(fabsl((long double)mant)) + ex + (p1 ? p1 * log2l(c) : 0.0L) +
+                                   (p2 ? p2 * log2l(s) : 0.0L);
+            int E = (int)floorl(lg);
+            long double d = copysignl(exp2l(lg - E), (long double)mant), dm = 0.0L;
+            for (int l = l0; l < L; ++l) {
+                o[l] = (double)ldexpl(d, E);
+                if (l + 1 >= L) break;
+                long double dn;
+                if (l == 0) {
+                    dn = x * d;
+                } else {
+                    const long double l1 = (long double)(l + 1) * (l + 1), lq = (long double)l * l;
+                    const long double den = l * sqrtl((l1 - mm) * (l1 - nq));
+                    const long double a1 = (2.0L * l + 1.0L) * ((long double)l * (l + 1) * x - mn);
+                    const long double a2 = (l + 1.0L) * sqrtl((lq - mm) * (lq - nq));
+                    dn = (a1 * d - a2 * dm) / den;
+                }
+                dm = d;
+                d = dn;
+                if (d != 0.0L) {
+                    int f;
+                    frexpl(d, &f);
+                    if (f > 64 || f < -64) {
+                        d = ldexpl(d, -f);
+                        dm = ldexpl(dm, -f);
+                        E += f;
+                    }
+                }
+            }
+        }
+    }
+}
+}  // namespace
+
+void polar_table(int L, const std::vector<int> &ns, int np, std::vector<double> &out)
+{
+    const int nn = (int)ns.size(), P = 2 * np;
+    out.assign((size_t)nn * L * P * L, 0.0);
+    if (np == 0) return;
+    parallel_for(nn * L, [&](int idx) {
+        const int ni = idx / L, m = idx % L;
+        polar_column(L, m, ns[ni], np, &out[((size_t)ni * L + m) * P * L]);
+    });
+}
+
 void host_wigner_d(int L, int m, int n, std::vector<double> &out)
 {
     out.assign((size_t)L * L, 0.0);
@@ -351,15 +526,24 @@ void host_wigner_d(int L, int m, int n, std::vector<double> &out)
         int k = (int)std::floor((E + 256.0) / 512.0);
         if (k > 0) k = 0;
         double e = ldexp(v, E - 512 * k), ep = 0.0;
-        const double cth = T.cth[b];
+        const double cth = T.cth[b], ctl = T.cth_lo[b];
         for (int l = l0; l < L; ++l) {
             out[(size_t)l * L + b] = (k == 0) ? S[l] * e : 0.0;
-            double en = (A[l] * cth - B[l]) * e - ep;
+            const double en = std::fma(std::fma(A[l], ctl, std::fma(A[l], cth, -B[l])), e, -ep);
             ep = e;
             e = en;
             if (k < 0 && std::fabs(e) > 0x1p256) {
                 e *= 0x1p-512; ep *= 0x1p-512; ++k;
             }
+        }
+    }    const int np = polar_count(L);
+    if (np > 0) {
+        const int P = 2 * np;
+        std::vector<double> pt((size_t)P * L, 0.0);
+        polar_column(L, m, n, np, pt.data());
+        for (int p = 0; p < P; ++p) {
+            const int b = p < np ? p : L - P + p;
+            for (int l = 0; l < L; ++l) out[(size_t)l * L + b] = pt[(size_t)p * L + l];
         }
     }
 }

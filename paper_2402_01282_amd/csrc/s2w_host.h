@@ -37,13 +37,28 @@ struct Filters {
 };
 void make_filters(const Scales &S, Filters &F);
 
+// kappa_lambda(t)^2 = k_lambda(t/lambda) - k_lambda(t), as one integral over [t/lambda, t].
+double kappa2_lambda(double t, double lambda);
+
+// Radial Laguerre rule (ball, Section 2.3): nodes r_k = tau x_k with x_k the P roots
+// of L^{(2)}_P, weights W_k = tau^3 e^{x_k} w_k (w_k the Gauss weights for x^2 e^{-x})
+// so that f_p = sum_k W_k K_p(r_k) f(r_k) is exact for p < P.
+struct LaguerreRule {
+    int P = 0;
+    double tau = 1.0;
+    std::vector<double> x, r, W;
+};
+void laguerre_rule(int P, double tau, LaguerreRule &R);
+// K_p(r_k) = sqrt(p!/(p+2)!) e^{-x_k/2} L^{(2)}_p(x_k) / tau^{3/2} for p < Pb: [Pb][nodes].
+void laguerre_basis(const LaguerreRule &R, int Pb, std::vector<double> &K);
+
 // Exact MW theta-quadrature matrix, row-major [L][L].
 void theta_matrix(int L, int sigma, std::vector<double> &T);
 
 // Grid tables for band limit L: cos(theta_b), cos(theta_b/2), sin(theta_b/2) and
 // the relative rounding residuals of the half-angle values (for accurate powers).
 struct ThetaTables {
-    std::vector<double> cth, ch, sh, ch_eps, sh_eps;
+    std::vector<double> cth, cth_lo, ch, sh, ch_eps, sh_eps;   // cos(theta) = cth + cth_lo (double-double)
 };
 void theta_tables(int L, ThetaTables &T);
 
@@ -62,7 +77,15 @@ struct RecTables {
 };
 void rec_tables(int L, const std::vector<int> &ns, RecTables &R);
 
-// Host evaluation of d^l_mn(theta_b) with the same recursion (tests).
+// Samples next to each pole whose d^l_mn come from the polar table instead of
+// the FP64 recursion (0 for small L, where the recursion error stays small).
+int polar_count(int L);
+// d^l_mn(theta_b) at the 2 np samples nearest the poles (b < np and b >= L - np),
+// layout [ni][m][p][l], p < np: b = p, else b = L - 2 np + p.
+void polar_table(int L, const std::vector<int> &ns, int np, std::vector<double> &out);
+
+// Host evaluation of d^l_mn(theta_b) as the device computes it: the FP64
+// recursion, with the polar samples from the polar table (tests).
 void host_wigner_d(int L, int m, int n, std::vector<double> &out);
 
 // Prime-factor (Good-Thomas) factorisation n = n1 * n2, gcd(n1, n2) = 1.

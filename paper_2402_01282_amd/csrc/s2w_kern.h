@@ -22,7 +22,9 @@ struct LsumArgs {
     const double *A, *B, *S;     // [NG][Lrec][Lrec]
     const double *smant;         // [NG][Lrec]
     const int *sexp;
-    const double *cth, *ch, *sh, *ceps, *seps;   // [L]
+    const double *cth, *ctl, *ch, *sh, *ceps, *seps;   // [L]; cos(theta) = cth + ctl
+    const double *pol;           // d at the 2 npol samples next to the poles [NG][L][2 npol][L]
+    int npol;
     const double *flm;           // [B][flm_m][flm_l] complex
     int flm_m, flm_l;
     const double *w[MAX_NS];     // weights [nn][wstride] (wstride 0: shared by all n)
@@ -37,7 +39,9 @@ struct TsumArgs {
     const double *A, *B_, *S;
     const double *smant;
     const int *sexp;
-    const double *cth, *ch, *sh, *ceps, *seps;
+    const double *cth, *ctl, *ch, *sh, *ceps, *seps;   // [L]; cos(theta) = cth + ctl
+    const double *pol;           // d at the 2 npol samples next to the poles [NG][L][2 npol][L]
+    int npol;
     int npar;                    // parity of n in this launch: sigma index = (m + npar) & 1
     int M0, M1;                  // number of m with sigma index 0 / 1
     const double *h[MAX_NS];     // rows [sig][b][m'][ni][c][L]
@@ -52,9 +56,14 @@ struct DftArgs {
     long istride, ostride;       // in elements of the row type (complex or real)
     int nrows;
     int n, n1, n2;
-    const int *pin, *pout, *pinv;
-    const double *w1, *w2;
+    const int *pin;              // input index held at LDS position p (prime-factor order)
+    const int *pout;             // output frequency held at LDS position p after both stages
+    const int *inpos;            // LDS position of input index i
+    const int *outpos;           // LDS position holding output frequency k
+    const double *w1, *w2;       // cos, sin of 2 pi k / n1 and 2 pi k / n2
     double scale;
+    int rpb;                     // row pairs per block (set by the launcher)
+    int inplace;                 // stages overwrite their input (set by the launcher)
 };
 
 struct GammaArgs {
@@ -100,10 +109,12 @@ void launch_tsum_mm(const TsumArgs &a, const MixIn &in, int NS, hipStream_t st);
 
 void launch_lsum(const LsumArgs &a, int NS, int B, hipStream_t st);
 void launch_tsum(const TsumArgs &a, int NS, int B, hipStream_t st);
-void launch_gemm(const double *A, const double *Bm, double *C, int M, int N, int K, hipStream_t st);
+void launch_gemm(const double *A, const double *Bm, double *C, int M, int N, int K, hipStream_t st,
+                 bool accum = false);
+void launch_scale_pl(const double *in, double *out, const double *phi, int P, int L, size_t total, hipStream_t st);
 void launch_gemm_f32(const float *A, const float *Bm, float *C, int M, int N, int K, hipStream_t st);
-void launch_dft_c2r(const DftArgs &a, hipStream_t st, bool f32 = false);
-void launch_dft_r2c(const DftArgs &a, hipStream_t st, bool f32 = false, bool in64 = true);
+void launch_dft_c2r(DftArgs a, hipStream_t st, bool f32 = false);
+void launch_dft_r2c(DftArgs a, hipStream_t st, bool f32 = false, bool in64 = true);
 void launch_gamma_c2r(const GammaArgs &a, hipStream_t st, bool f32 = false);
 void launch_gamma_r2c(const GammaArgs &a, hipStream_t st, bool f32 = false);
 void launch_convert(const void *in, void *out, size_t n, bool to_f32, hipStream_t st);

@@ -4,11 +4,14 @@
 //   k_lsum   sum over degree l of a_lmn d^l_mn(theta) for every (m >= 0, n, theta):
 //            lanes own theta samples; d generated on the fly by the scaled
 //            three-term recursion in l, started from the closed form at
-//            l0 = max(|m|,|n|) with per-lane power-of-two rescaling (FP64)
+//            l0 = max(|m|,|n|) with per-lane power-of-two rescaling (FP64).
+//            cos(theta) enters as a double-double pair (hi + lo, one extra FMA
+//            per step): near the poles a single rounding of cos(theta) shifts
+//            d^l by about l^2 u / 2, far above the FP64 target at l ~ 10^3
 //   k_tsum   sum over theta of d^l_mn(theta) h(theta) for every l (the
 //            transposed contraction), same recursion, cross-lane reduction
 //            through LDS
-//   k_gemm   exact MW theta quadrature h = T_sigma F (dense FP64)
+//   k_gemm   exact MW theta quadrature h = T_sigma F (MFMA, FP64 or FP32)
 //   k_dft_*  odd-length DFTs (2L-1, 2N-1 points) by the prime-factor algorithm
 //   k_gamma_* azimuthal (gamma) DFT over the few nonzero n, fused with the
 //            layout change between the l-stage ((m, n) rows over theta) and
@@ -22,6 +25,10 @@
 #include "s2w_kern.h"
 
 namespace s2w {
+
+// theta samples next to the poles whose d come from the polar table
+__device__ inline bool is_polar(int th, int L, int npol) { return th < npol || th >= L - npol; }
+__device__ inline int polar_theta(int p, int L, int npol) { return p < npol ? p : L - 2 * npol + p; }
 
 // ------------------------------------------------------------- k_lsum ------
 //
@@ -43,7 +50,7 @@ __global__ __launch_bounds__(64) void k_lsum(const LsumArgs a)
     __shared__ double2 sAB[64];
     __shared__ double2 sU[NS][64];
 
-    double c[T], e[T], ep[T], acc[NS][2][T];
+    double c[T], cl[T], e[T], ep[T], acc[NS][2][T];
     int k[T];
     const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
     const double mant = a.smant[(size_t)ng * a.Lrec + m];
@@ -58,8 +65,10 @@ __global__ __launch_bounds__(64) void k_lsum(const LsumArgs a)
         ep[t] = 0.0;
         k[t] = 0;
         c[t] = 0.0;
+        cl[t] = 0.0;
         if (th < a.L && l0 < lmax) {
             c[t] = a.cth[th];
+            cl[t] = a.ctl[th];
             start_value(mant, ex, p1, p2, a.ch[th], a.sh[th], a.ceps[th], a.seps[th], e[t], k[t]);
         }
         asleep_any |= (k[t] < 0);
@@ -109,7 +118,7 @@ __global__ __launch_bounds__(64) void k_lsum(const LsumArgs a)
                         acc[s][0][t] = fma(u[s].x, e[t], acc[s][0][t]);
                         acc[s][1][t] = fma(u[s].y, e[t], acc[s][1][t]);
                     }
-                    const double en = fma(fma(ab.x, c[t], -ab.y), e[t], -ep[t]);
+                    const double en = fma(fma(ab.x, cl[t], fma(ab.x, c[t], -ab.y)), e[t], -ep[t]);
                     ep[t] = e[t];
                     e[t] = en;
                 }
@@ -176,7 +185,7 @@ __global__ __launch_bounds__(64) void k_tsum(const TsumArgs a)
     const size_t rbase = (sig == 0 ? 0 : (size_t)a.B * a.M0 * a.nn * 2)
                          + ((((size_t)b * (sig == 0 ? a.M0 : a.M1) + mp) * a.nn + ni) * 2);
 
-    double c[T], e[T], ep[T], hr[NS][T], hi[NS][T];
+    double c[T], cl[T], e[T], ep[T], hr[NS][T], hi[NS][T];
     int k[T];
     const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
     const double mant = a.smant[(size_t)ng * a.Lrec + m];
@@ -191,12 +200,14 @@ __global__ __launch_bounds__(64) void k_tsum(const TsumArgs a)
         ep[t] = 0.0;
         k[t] = 0;
         c[t] = 0.0;
+        cl[t] = 0.0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) { hr[s][t] = 0.0; hi[s][t] = 0.0; }
         if (th < a.L && l0 < lmax) {
             c[t] = a.cth[th];
+            cl[t] = a.ctl[th];
             start_value(mant, ex, p1, p2, a.ch[th], a.sh[th], a.ceps[th], a.seps[th], e[t], k[t]);
-            if (k[t] == 0) {
+            if (k[t] == 0 && !is_polar(th, a.L, a.npol)) {
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     hr[s][t] = a.h[s][(rbase + 0) * a.L + th];
@@ -229,7 +240,7 @@ __global__ __launch_bounds__(64) void k_tsum(const TsumArgs a)
                     pr[s] = fma(e[t], hr[s][t], pr[s]);
                     pi[s] = fma(e[t], hi[s][t], pi[s]);
                 }
-                const double en = fma(fma(ab.x, c[t], -ab.y), e[t], -ep[t]);
+                const double en = fma(fma(ab.x, cl[t], fma(ab.x, c[t], -ab.y)), e[t], -ep[t]);
                 ep[t] = e[t];
                 e[t] = en;
             }
@@ -247,8 +258,8 @@ __global__ __launch_bounds__(64) void k_tsum(const TsumArgs a)
                             e[t] *= 0x1p-512;
                             ep[t] *= 0x1p-512;
                             k[t] += 1;
-                            if (k[t] == 0) {
-                                const int th = t * 64 + lane;
+                            const int th = t * 64 + lane;
+                            if (k[t] == 0 && !is_polar(th, a.L, a.npol)) {
 #pragma unroll
                                 for (int s = 0; s < NS; ++s) {
                                     hr[s][t] = a.h[s][(rbase + 0) * a.L + th];
@@ -291,11 +302,123 @@ __global__ __launch_bounds__(64) void k_tsum(const TsumArgs a)
     }
 }
 
+// --------------------------------------------------------- polar samples ----
+//
+// The 2 npol samples next to the poles take d from the long-double table (the
+// FP64 recursion loses about u l^2 there).  k_lsum_polar overwrites k_lsum's
+// output at those samples; k_tsum skips them and k_tsum_polar adds their terms.
+
+template <int NS>
+__global__ __launch_bounds__(64) void k_lsum_polar(const LsumArgs a)
+{
+    constexpr int PM = 8;                // 2 npol <= PM
+    const int m = blockIdx.x, ni = blockIdx.y, b = blockIdx.z, lane = threadIdx.x;
+    const int n = a.nval[ni], ng = a.nglob[ni];
+    const int an = n < 0 ? -n : n, l0 = m > an ? m : an;
+    const int P = 2 * a.npol;
+    double acc[PM][NS][2];
+#pragma unroll
+    for (int p = 0; p < PM; ++p)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) { acc[p][s][0] = 0.0; acc[p][s][1] = 0.0; }
+    const double *tab = a.pol + ((size_t)ng * a.L + m) * P * a.L;
+    for (int l = l0 + lane; l < a.L; l += 64) {
+        const double *fl = a.flm + (((size_t)b * a.flm_m + m) * a.flm_l + l) * 2;
+        const double fr = fl[0], fi = fl[1];
+        double ur[NS], ui[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const double w = a.w[s][(size_t)ni * a.wstride + l];
+            ur[s] = w * fr;
+            ui[s] = w * fi;
+        }
+#pragma unroll
+        for (int p = 0; p < PM; ++p) {
+            if (p >= P) break;
+            const double d = tab[(size_t)p * a.L + l];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                acc[p][s][0] = fma(ur[s], d, acc[p][s][0]);
+                acc[p][s][1] = fma(ui[s], d, acc[p][s][1]);
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < PM; ++p)
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) acc[p][s][c] += __shfl_xor(acc[p][s][c], off, 64);
+    if (lane == 0) {
+#pragma unroll
+        for (int p = 0; p < PM; ++p) {
+            if (p >= P) break;
+            const int th = polar_theta(p, a.L, a.npol);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                double *o = a.out[s] + ((((size_t)b * a.nn + ni) * a.mcount + m) * a.L + th) * 2;
+                o[0] = acc[p][s][0];
+                o[1] = acc[p][s][1];
+            }
+        }
+    }
+}
+
+template <int NS>
+__global__ __launch_bounds__(64) void k_tsum_polar(const TsumArgs a)
+{
+    constexpr int PM = 8;
+    const int m = blockIdx.x, ni = blockIdx.y, b = blockIdx.z, lane = threadIdx.x;
+    const int n = a.nval[ni], ng = a.nglob[ni];
+    const int an = n < 0 ? -n : n, l0 = m > an ? m : an;
+    const int P = 2 * a.npol;
+    const int sig = (m + a.npar) & 1, mp = m >> 1;
+    const size_t rbase = (sig == 0 ? 0 : (size_t)a.B * a.M0 * a.nn * 2)
+                         + ((((size_t)b * (sig == 0 ? a.M0 : a.M1) + mp) * a.nn + ni) * 2);
+    double hr[PM][NS], hi[PM][NS];
+#pragma unroll
+    for (int p = 0; p < PM; ++p) {
+        const int th = polar_theta(p < P ? p : 0, a.L, a.npol);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            hr[p][s] = p < P ? a.h[s][(rbase + 0) * a.L + th] : 0.0;
+            hi[p][s] = p < P ? a.h[s][(rbase + 1) * a.L + th] : 0.0;
+        }
+    }
+    const double *tab = a.pol + ((size_t)ng * a.L + m) * P * a.L;
+    for (int l = l0 + lane; l < a.L; l += 64) {
+        double vr[NS], vi[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) { vr[s] = 0.0; vi[s] = 0.0; }
+#pragma unroll
+        for (int p = 0; p < PM; ++p) {
+            if (p >= P) break;
+            const double d = tab[(size_t)p * a.L + l];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                vr[s] = fma(d, hr[p][s], vr[s]);
+                vi[s] = fma(d, hi[p][s], vi[s]);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const double w = a.w[s][(size_t)ni * a.wstride + l];
+            double *o = a.out[s] + ((((size_t)b * a.mcount + m) * a.nn + ni) * a.L + l) * 2;
+            o[0] += w * vr[s];
+            o[1] += w * vi[s];
+        }
+    }
+}
+
 // ------------------------------------------------------------- k_gemm ------
 // C[M][N] = A[M][K] * Bm[K][N], row-major, on matrix cores (16x16x4 MFMA, FP64 or FP32).
 // Workgroup tile 128 x 128, four waves of 64 x 64 (4 x 4 MFMA tiles), K staged 16 at a
-// time through LDS.  MFMA operand layout: A fragment lane l holds A[l % 16][l / 16],
-// B fragment B[l / 16][l % 16]; result register j of lane l is D[4 (l / 16) + j][l % 16].
+// time through LDS.  MFMA operand layout (both types): A fragment lane l holds
+// A[l % 16][l / 16], B fragment B[l / 16][l % 16].  Result register j of lane l holds
+// column l % 16 and row 4 (l / 16) + j for FP32 but row l / 16 + 4 j for FP64
+// (checked on the device).
 
 template <typename Tp>
 struct Mfma16;
@@ -303,16 +426,18 @@ template <>
 struct Mfma16<double> {
     typedef double v4 __attribute__((ext_vector_type(4)));
     static __device__ inline v4 op(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int lane, int j) { return (lane >> 4) + 4 * j; }
 };
 template <>
 struct Mfma16<float> {
     typedef float v4 __attribute__((ext_vector_type(4)));
     static __device__ inline v4 op(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int lane, int j) { return 4 * (lane >> 4) + j; }
 };
 
 template <typename Tp>
 __global__ __launch_bounds__(256) void k_gemm(const Tp *__restrict__ A, const Tp *__restrict__ Bm,
-                                              Tp *__restrict__ C, int M, int N, int K)
+                                              Tp *__restrict__ C, int M, int N, int K, int accum)
 {
     constexpr int BM = 128, BN = 128, BK = 16, PAD = 1;
     typedef typename Mfma16<Tp>::v4 v4;
@@ -358,23 +483,258 @@ __global__ __launch_bounds__(256) void k_gemm(const Tp *__restrict__ A, const Tp
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int gr = row0 + wr * 64 + i * 16 + 4 * (lane >> 4) + r;
+                const int gr = row0 + wr * 64 + i * 16 + Mfma16<Tp>::row(lane, r);
                 const int gc = col0 + wc * 64 + j * 16 + (lane & 15);
-                if (gr < M && gc < N) C[(size_t)gr * N + gc] = acc[i][j][r];
+                if (gr < M && gc < N) {
+                    Tp *c = C + (size_t)gr * N + gc;
+                    *c = accum ? *c + acc[i][j][r] : acc[i][j][r];
+                }
             }
 }
 
 // -------------------------------------------------------------- DFTs -------
 //
-// Prime-factor DFT of length n = n1 n2 on a complex row in LDS.  The input is
-// placed at LDS position p = m1 n2 + m2 for input index (m1 n2 + m2 n1) mod n
-// (table pin[p]); stage 1 transforms over m1 (length n1), stage 2 over m2
-// (length n2); output (a1, a2) sits at LDS position a1 n2 + a2 and is frequency
-// pout[p] = (a1 e1 + a2 e2) mod n.  No twiddles between stages.  Tr is the
-// arithmetic type (double, or float in the mixed-precision path).
+// Prime-factor DFT of length n = n1 n2 (gcd(n1, n2) = 1) of complex rows held
+// in LDS.  Input index (m1 n2 + m2 n1) mod n sits at LDS position m1 n2 + m2
+// (table inpos maps the index to its position); stage 1 transforms over m1
+// (length n1), stage 2 over m2 (length n2), with no twiddles between stages;
+// output frequency (a1 e1 + a2 e2) mod n ends at position a1 n2 + a2 (table
+// outpos).  Each stage pairs indices k and p-k of an odd length p:
+//   u_k = x_k + x_{p-k},  v_k = x_k - x_{p-k},  h = (p-1)/2,
+//   A_j = x_0 + sum_{k=1..h} u_k cos(2 pi jk/p),  B_j = sum_{k=1..h} v_k sin(2 pi jk/p),
+//   X_j = A_j + i sgn B_j,  X_{p-j} = A_j - i sgn B_j,
+// a quarter of the real multiplications of the plain sum.  A thread owns a
+// block of J outputs j by C sequences (DftBlk); when every thread of the block
+// holds at most one such task per stage, a stage reads its buffer, waits at a
+// barrier and overwrites it in place (one LDS buffer of n per row pair).
+// Rows are paired as z = x1 + i x2 (two real rows per complex DFT).  Tr is the
+// arithmetic type (double; float in the mixed-precision path).
 
 template <typename Tr>
-__device__ inline void pfa_stages(typename V2<Tr>::t *Z, typename V2<Tr>::t *Y, const double2 *w1,
+struct DftBlk;
+template <>
+struct DftBlk<float> {
+    static constexpr int J = 4, C = 3;
+};
+template <>
+struct DftBlk<double> {
+    static constexpr int J = 2, C = 3;
+};
+
+template <typename Tr>
+struct DftTask {
+    typedef typename V2<Tr>::t C2;
+    static constexpr int DJB = DftBlk<Tr>::J, DCB = DftBlk<Tr>::C;
+    C2 A[DJB][DCB], Bv[DJB][DCB];
+};
+
+// Compute the task (jb, cb) of one stage: element (k, c) at buf[k*sj + c*sc].
+template <typename Tr>
+__device__ inline void dft_task(const typename V2<Tr>::t *buf, const typename V2<Tr>::t *tw, int p, int q, int sj,
+                                int sc, int jb, int cb, DftTask<Tr> &T)
+{
+    typedef typename V2<Tr>::t C2;
+    constexpr int DJB = DftBlk<Tr>::J, DCB = DftBlk<Tr>::C;
+    const int h = (p - 1) / 2, j0 = jb * DJB, c0 = cb * DCB;
+    int off[DCB];
+#pragma unroll
+    for (int c = 0; c < DCB; ++c) off[c] = (c0 + c < q ? c0 + c : q - 1) * sc;
+#pragma unroll
+    for (int c = 0; c < DCB; ++c) {
+        const C2 x0 = buf[off[c]];
+#pragma unroll
+        for (int j = 0; j < DJB; ++j) {
+            T.A[j][c] = x0;
+            T.Bv[j][c] = mk2<Tr>(0, 0);
+        }
+    }
+    int t[DJB];
+#pragma unroll
+    for (int j = 0; j < DJB; ++j) t[j] = 0;
+#pragma unroll 1
+    for (int k = 1; k <= h; ++k) {
+        C2 u[DCB], v[DCB];
+#pragma unroll
+        for (int c = 0; c < DCB; ++c) {
+            const C2 z1 = buf[k * sj + off[c]], z2 = buf[(p - k) * sj + off[c]];
+            u[c] = mk2<Tr>(z1.x + z2.x, z1.y + z2.y);
+            v[c] = mk2<Tr>(z1.x - z2.x, z1.y - z2.y);
+        }
+#pragma unroll
+        for (int j = 0; j < DJB; ++j) {
+            t[j] += j0 + j;
+            if (t[j] >= p) t[j] -= p;
+            const C2 w = tw[t[j]];
+#pragma unroll
+            for (int c = 0; c < DCB; ++c) {
+                T.A[j][c].x = fma(u[c].x, w.x, T.A[j][c].x);
+                T.A[j][c].y = fma(u[c].y, w.x, T.A[j][c].y);
+                T.Bv[j][c].x = fma(v[c].x, w.y, T.Bv[j][c].x);
+                T.Bv[j][c].y = fma(v[c].y, w.y, T.Bv[j][c].y);
+            }
+        }
+    }
+}
+
+template <typename Tr>
+__device__ inline void dft_task_store(typename V2<Tr>::t *buf, int p, int q, int sj, int sc, int jb, int cb,
+                                      const DftTask<Tr> &T, Tr sgn)
+{
+    constexpr int DJB = DftBlk<Tr>::J, DCB = DftBlk<Tr>::C;
+    const int h = (p - 1) / 2, j0 = jb * DJB, c0 = cb * DCB;
+#pragma unroll
+    for (int j = 0; j < DJB; ++j) {
+        const int jj = j0 + j;
+        if (jj > h) continue;
+#pragma unroll
+        for (int c = 0; c < DCB; ++c) {
+            if (c0 + c >= q) continue;
+            const int o = (c0 + c) * sc;
+            const auto &A = T.A[j][c];
+            const auto &B = T.Bv[j][c];
+            buf[jj * sj + o] = mk2<Tr>(A.x - sgn * B.y, A.y + sgn * B.x);
+            if (jj > 0) buf[(p - jj) * sj + o] = mk2<Tr>(A.x + sgn * B.y, A.y - sgn * B.x);
+        }
+    }
+}
+
+template <typename Tr>
+__host__ __device__ inline int dft_tasks(int p, int q)
+{
+    return ((p - 1) / 2 + DftBlk<Tr>::J) / DftBlk<Tr>::J * ((q + DftBlk<Tr>::C - 1) / DftBlk<Tr>::C);
+}
+
+// One stage over R slots of n elements: src -> dst (dst == src when every thread
+// holds at most one task, else a separate buffer; then tasks loop).
+template <typename Tr>
+__device__ inline void pfa_stage(typename V2<Tr>::t *src, typename V2<Tr>::t *dst, const typename V2<Tr>::t *tw,
+                                 int n, int p, int q, int sj, int sc, int R, Tr sgn)
+{
+    const int t1 = dft_tasks<Tr>(p, q), nc = (q + DftBlk<Tr>::C - 1) / DftBlk<Tr>::C;
+    if (src == dst) {
+        const bool act = (int)threadIdx.x < R * t1;
+        const int s = act ? threadIdx.x / t1 : 0, t = act ? threadIdx.x % t1 : 0;
+        DftTask<Tr> T;
+        if (act) dft_task<Tr>(src + (size_t)s * n, tw, p, q, sj, sc, t / nc, t % nc, T);
+        __syncthreads();
+        if (act) dft_task_store<Tr>(dst + (size_t)s * n, p, q, sj, sc, t / nc, t % nc, T, sgn);
+    } else {
+        for (int task = threadIdx.x; task < R * t1; task += blockDim.x) {
+            const int s = task / t1, t = task % t1;
+            DftTask<Tr> T;
+            dft_task<Tr>(src + (size_t)s * n, tw, p, q, sj, sc, t / nc, t % nc, T);
+            dft_task_store<Tr>(dst + (size_t)s * n, p, q, sj, sc, t / nc, t % nc, T, sgn);
+        }
+    }
+    __syncthreads();
+}
+
+// Both stages on R row pairs (slots) held at Z + s n; the result ends in Z.  Y is
+// Z itself when every thread holds at most one task per stage, else R n more
+// elements of LDS.  tw1, tw2: twiddles in LDS.
+template <typename Tr>
+__device__ inline void pfa_stages(typename V2<Tr>::t *Z, typename V2<Tr>::t *Y, const typename V2<Tr>::t *tw1,
+                                  const typename V2<Tr>::t *tw2, int n, int n1, int n2, int R, Tr sgn)
+{
+    pfa_stage<Tr>(Z, Y, tw1, n, n1, n2, n2, 1, R, sgn);
+    pfa_stage<Tr>(Y, Z, tw2, n, n2, n1, 1, n2, R, sgn);
+}
+
+template <typename Tr>
+__device__ inline typename V2<Tr>::t *dft_smem_setup(const DftArgs &a, unsigned char *raw)
+{
+    typedef typename V2<Tr>::t C2;
+    C2 *tw = reinterpret_cast<C2 *>(raw);
+    const double2 *w1 = reinterpret_cast<const double2 *>(a.w1), *w2 = reinterpret_cast<const double2 *>(a.w2);
+    for (int i = threadIdx.x; i < a.n1 + a.n2; i += blockDim.x) {
+        const double2 w = i < a.n1 ? w1[i] : w2[i - a.n1];
+        tw[i] = mk2<Tr>((Tr)w.x, (Tr)w.y);
+    }
+    return tw + a.n1 + a.n2;
+}
+
+// c2r: two Hermitian rows E1, E2 (m = 0..Lh-1, complex) -> two real rows of length n.
+// x(a) = scale * (Re E_0 + 2 Re sum_{m>=1} E_m e^{+2 pi i m a/n})
+template <typename Tr>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_dft_c2r(const DftArgs a)
+{
+    typedef typename V2<Tr>::t C2;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2 *Z = dft_smem_setup<Tr>(a, smem_raw);
+    const C2 *tw1 = reinterpret_cast<const C2 *>(smem_raw), *tw2 = tw1 + a.n1;
+    const int n = a.n, Lh = (n + 1) / 2, R = a.rpb;
+    const long pair0 = (long)blockIdx.x * R;
+    const Tr sc = (Tr)a.scale;
+    for (int idx = threadIdx.x; idx < R * Lh; idx += blockDim.x) {
+        const int s = idx / Lh, mm = idx - s * Lh;
+        const long r1 = 2 * (pair0 + s);
+        if (r1 >= a.nrows) continue;
+        const bool has2 = r1 + 1 < a.nrows;
+        C2 z1 = reinterpret_cast<const C2 *>(a.in)[r1 * a.istride + mm];
+        C2 z2 = has2 ? reinterpret_cast<const C2 *>(a.in)[(r1 + 1) * a.istride + mm] : mk2<Tr>(0, 0);
+        C2 *Zs = Z + (size_t)s * n;
+        if (mm == 0) {
+            Zs[a.inpos[0]] = mk2<Tr>(sc * z1.x, sc * z2.x);
+        } else {
+            Zs[a.inpos[mm]] = mk2<Tr>(sc * (z1.x - z2.y), sc * (z1.y + z2.x));       // z1 + i z2
+            Zs[a.inpos[n - mm]] = mk2<Tr>(sc * (z1.x + z2.y), sc * (z2.x - z1.y));   // conj(z1) + i conj(z2)
+        }
+    }
+    __syncthreads();
+    pfa_stages<Tr>(Z, a.inplace ? Z : Z + (size_t)R * n, tw1, tw2, n, a.n1, a.n2, R, (Tr)1);
+    for (int idx = threadIdx.x; idx < R * n; idx += blockDim.x) {
+        const int s = idx / n, aa = idx - s * n;
+        const long r1 = 2 * (pair0 + s);
+        if (r1 >= a.nrows) continue;
+        const C2 z = Z[(size_t)s * n + a.outpos[aa]];
+        reinterpret_cast<Tr *>(a.out)[r1 * a.ostride + aa] = z.x;
+        if (r1 + 1 < a.nrows) reinterpret_cast<Tr *>(a.out)[(r1 + 1) * a.ostride + aa] = z.y;
+    }
+}
+
+// r2c: two real rows x1, x2 of length n -> X_m = scale * sum_a x(a) e^{-2 pi i m a/n}, m = 0..Lh-1.
+// Tin: element type of the input rows.
+template <typename Tr, typename Tin>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_dft_r2c(const DftArgs a)
+{
+    typedef typename V2<Tr>::t C2;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2 *Z = dft_smem_setup<Tr>(a, smem_raw);
+    const C2 *tw1 = reinterpret_cast<const C2 *>(smem_raw), *tw2 = tw1 + a.n1;
+    const int n = a.n, Lh = (n + 1) / 2, R = a.rpb;
+    const long pair0 = (long)blockIdx.x * R;
+    for (int idx = threadIdx.x; idx < R * n; idx += blockDim.x) {
+        const int s = idx / n, mm = idx - s * n;
+        const long r1 = 2 * (pair0 + s);
+        if (r1 >= a.nrows) continue;
+        const Tin *x = reinterpret_cast<const Tin *>(a.in);
+        const Tr x1 = (Tr)x[r1 * a.istride + mm];
+        const Tr x2 = r1 + 1 < a.nrows ? (Tr)x[(r1 + 1) * a.istride + mm] : (Tr)0;
+        Z[(size_t)s * n + a.inpos[mm]] = mk2<Tr>(x1, x2);
+    }
+    __syncthreads();
+    pfa_stages<Tr>(Z, a.inplace ? Z : Z + (size_t)R * n, tw1, tw2, n, a.n1, a.n2, R, (Tr)-1);
+    const Tr h = (Tr)(0.5 * a.scale);
+    for (int idx = threadIdx.x; idx < R * Lh; idx += blockDim.x) {
+        const int s = idx / Lh, mm = idx - s * Lh;
+        const long r1 = 2 * (pair0 + s);
+        if (r1 >= a.nrows) continue;
+        const C2 *Zs = Z + (size_t)s * n;
+        const C2 X = Zs[a.outpos[mm]];
+        const C2 Xc = Zs[a.outpos[mm == 0 ? 0 : n - mm]];
+        C2 *O = reinterpret_cast<C2 *>(a.out);
+        O[r1 * a.ostride + mm] = mk2<Tr>(h * (X.x + Xc.x), h * (X.y - Xc.y));
+        if (r1 + 1 < a.nrows) O[(r1 + 1) * a.ostride + mm] = mk2<Tr>(h * (X.y + Xc.y), -h * (X.x - Xc.x));
+    }
+}
+
+// Plain prime-factor stages (direct length-n1 and length-n2 sums, twiddles read
+// from global memory, two LDS buffers per row pair); used by the FP32 (mixed)
+// path.  Position p holds input index pin[p] and, after both stages, output
+// frequency pout[p].
+
+template <typename Tr>
+__device__ inline void pfa_stages_direct(typename V2<Tr>::t *Z, typename V2<Tr>::t *Y, const double2 *w1,
                                   const double2 *w2, int n1, int n2, Tr sgn)
 {
     typedef typename V2<Tr>::t C2;
@@ -468,7 +828,7 @@ __device__ inline void pfa_stages(typename V2<Tr>::t *Z, typename V2<Tr>::t *Y, 
 // c2r: two Hermitian rows E1, E2 (m = 0..Lh-1, complex) -> two real rows of length n.
 // x(a) = scale * (Re E_0 + 2 Re sum_{m>=1} E_m e^{+2 pi i m a/n})
 template <typename Tr>
-__global__ __launch_bounds__(128) void k_dft_c2r(const DftArgs a)
+__global__ __launch_bounds__(128) void k_dft_c2r_direct(const DftArgs a)
 {
     typedef typename V2<Tr>::t C2;
     extern __shared__ unsigned char smem_raw[];
@@ -497,7 +857,7 @@ __global__ __launch_bounds__(128) void k_dft_c2r(const DftArgs a)
         Z[p] = mk2<Tr>(sc * (z1.x - z2.y), sc * (z1.y + z2.x));   // z1 + i z2
     }
     __syncthreads();
-    pfa_stages<Tr>(Z, Y, w1, w2, n1, n2, (Tr)1);
+    pfa_stages_direct<Tr>(Z, Y, w1, w2, n1, n2, (Tr)1);
     Tr *o1 = reinterpret_cast<Tr *>(a.out) + r1 * a.ostride, *o2 = reinterpret_cast<Tr *>(a.out) + r2 * a.ostride;
     for (int p = tid; p < n; p += blockDim.x) {
         const int aa = a.pout[p];
@@ -509,7 +869,7 @@ __global__ __launch_bounds__(128) void k_dft_c2r(const DftArgs a)
 // r2c: two real rows x1, x2 of length n -> X_m = scale * sum_a x(a) e^{-2 pi i m a/n}, m = 0..Lh-1.
 // Tin: element type of the input rows (the mixed path reads FP64 maps into FP32 arithmetic).
 template <typename Tr, typename Tin>
-__global__ __launch_bounds__(128) void k_dft_r2c(const DftArgs a)
+__global__ __launch_bounds__(128) void k_dft_r2c_direct(const DftArgs a)
 {
     typedef typename V2<Tr>::t C2;
     extern __shared__ unsigned char smem_raw[];
@@ -527,13 +887,13 @@ __global__ __launch_bounds__(128) void k_dft_r2c(const DftArgs a)
         Z[p] = mk2<Tr>((Tr)x1[mm], has2 ? (Tr)x2[mm] : (Tr)0);
     }
     __syncthreads();
-    pfa_stages<Tr>(Z, Y, w1, w2, n1, n2, (Tr)-1);
+    pfa_stages_direct<Tr>(Z, Y, w1, w2, n1, n2, (Tr)-1);
     C2 *O1 = reinterpret_cast<C2 *>(a.out) + r1 * a.ostride;
     C2 *O2 = reinterpret_cast<C2 *>(a.out) + r2 * a.ostride;
     const Tr h = (Tr)(0.5 * a.scale);
     for (int mm = tid; mm < Lh; mm += blockDim.x) {
-        const C2 X = Z[a.pinv[mm]];
-        const C2 Xc = Z[a.pinv[mm == 0 ? 0 : n - mm]];
+        const C2 X = Z[a.outpos[mm]];
+        const C2 Xc = Z[a.outpos[mm == 0 ? 0 : n - mm]];
         O1[mm] = mk2<Tr>(h * (X.x + Xc.x), h * (X.y - Xc.y));
         if (has2) O2[mm] = mk2<Tr>(h * (X.y + Xc.y), -h * (X.x - Xc.x));
     }
@@ -681,6 +1041,20 @@ __global__ void k_pack_sigma(const Tr *in, Tr *out, int B, int nn, int M, int L,
     }
 }
 
+// out[b][p][m][l] = phi[p][l] in[b][p][m][l] (complex), rows of L x L harmonic
+// coefficients per radial index p (ball scaling filter, applied elementwise).
+__global__ void k_scale_pl(const double *in, double *out, const double *phi, int P, int L, size_t total)
+{
+    const size_t LL = (size_t)L * L;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const int l = (int)(i % L);
+        const int p = (int)((i / LL) % P);
+        const double f = phi[(size_t)p * L + l];
+        out[2 * i] = f * in[2 * i];
+        out[2 * i + 1] = f * in[2 * i + 1];
+    }
+}
+
 __global__ void k_convert_f64_f32(const double *in, float *out, size_t n)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -761,6 +1135,11 @@ void launch_lsum(const LsumArgs &a, int NS, int B, hipStream_t st)
             default: launch_lsum_t<8, 2>(a, B, st); break;
         }
     }
+    if (a.npol > 0 && a.mcount > 0) {
+        dim3 grid(a.mcount, a.nn, B);
+        if (NS == 1) hipLaunchKernelGGL(k_lsum_polar<1>, grid, dim3(64), 0, st, a);
+        else hipLaunchKernelGGL(k_lsum_polar<2>, grid, dim3(64), 0, st, a);
+    }
 }
 
 template <int T, int NS>
@@ -787,42 +1166,86 @@ void launch_tsum(const TsumArgs &a, int NS, int B, hipStream_t st)
         else if (T <= 8) launch_tsum_t<8, 2>(a, B, st);
         else launch_tsum_t<16, 2>(a, B, st);
     }
+    if (a.npol > 0 && a.mcount > 0) {
+        dim3 grid(a.mcount, a.nn, B);
+        if (NS == 1) hipLaunchKernelGGL(k_tsum_polar<1>, grid, dim3(64), 0, st, a);
+        else hipLaunchKernelGGL(k_tsum_polar<2>, grid, dim3(64), 0, st, a);
+    }
 }
 
-void launch_gemm(const double *A, const double *Bm, double *C, int M, int N, int K, hipStream_t st)
+void launch_scale_pl(const double *in, double *out, const double *phi, int P, int L, size_t total, hipStream_t st)
+{
+    if (total == 0) return;
+    const size_t blocks = std::min<size_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_scale_pl, dim3((unsigned)blocks), dim3(256), 0, st, in, out, phi, P, L, total);
+}
+
+void launch_gemm(const double *A, const double *Bm, double *C, int M, int N, int K, hipStream_t st, bool accum)
 {
     if (M <= 0 || N <= 0) return;
     dim3 grid((N + 127) / 128, (M + 127) / 128);
-    hipLaunchKernelGGL(k_gemm<double>, grid, dim3(256), 0, st, A, Bm, C, M, N, K);
+    hipLaunchKernelGGL(k_gemm<double>, grid, dim3(256), 0, st, A, Bm, C, M, N, K, accum ? 1 : 0);
 }
 
 void launch_gemm_f32(const float *A, const float *Bm, float *C, int M, int N, int K, hipStream_t st)
 {
     if (M <= 0 || N <= 0) return;
     dim3 grid((N + 127) / 128, (M + 127) / 128);
-    hipLaunchKernelGGL(k_gemm<float>, grid, dim3(256), 0, st, A, Bm, C, M, N, K);
+    hipLaunchKernelGGL(k_gemm<float>, grid, dim3(256), 0, st, A, Bm, C, M, N, K, 0);
 }
 
-void launch_dft_c2r(const DftArgs &a, hipStream_t st, bool f32)
+// Row pairs per block and threads per block for a DFT launch.  In-place stages
+// when every thread holds at most one task per stage (up to 4 row pairs, 32 KB of
+// rows per block); otherwise one row pair, 256 threads and a second buffer.
+template <typename Tr>
+static void dft_shape(DftArgs &a, int &threads, size_t &lds)
 {
-    if (a.nrows <= 0) return;
-    dim3 grid((a.nrows + 1) / 2);
-    if (f32)
-        hipLaunchKernelGGL(k_dft_c2r<float>, grid, dim3(128), sizeof(float2) * 2 * (size_t)a.n, st, a);
-    else
-        hipLaunchKernelGGL(k_dft_c2r<double>, grid, dim3(128), sizeof(double2) * 2 * (size_t)a.n, st, a);
+    const size_t elem = 2 * sizeof(Tr);
+    const int t = std::max(dft_tasks<Tr>(a.n1, a.n2), dft_tasks<Tr>(a.n2, a.n1));
+    int R = 1;
+    if (t <= 256) {
+        while (R < 4 && (R + 1) * t <= 256 && (size_t)(R + 1) * a.n * elem <= 32768) ++R;
+        threads = std::max(64, (R * t + 63) / 64 * 64);
+        a.inplace = 1;
+    } else {
+        threads = 256;
+        a.inplace = 0;
+    }
+    a.rpb = R;
+    lds = ((size_t)R * a.n * (a.inplace ? 1 : 2) + a.n1 + a.n2) * elem;
 }
 
-void launch_dft_r2c(const DftArgs &a, hipStream_t st, bool f32, bool in64)
+void launch_dft_c2r(DftArgs a, hipStream_t st, bool f32)
 {
     if (a.nrows <= 0) return;
-    dim3 grid((a.nrows + 1) / 2);
-    if (!f32)
-        hipLaunchKernelGGL((k_dft_r2c<double, double>), grid, dim3(128), sizeof(double2) * 2 * (size_t)a.n, st, a);
-    else if (in64)
-        hipLaunchKernelGGL((k_dft_r2c<float, double>), grid, dim3(128), sizeof(float2) * 2 * (size_t)a.n, st, a);
-    else
-        hipLaunchKernelGGL((k_dft_r2c<float, float>), grid, dim3(128), sizeof(float2) * 2 * (size_t)a.n, st, a);
+    if (f32) {
+        hipLaunchKernelGGL(k_dft_c2r_direct<float>, dim3((a.nrows + 1) / 2), dim3(128),
+                           sizeof(float2) * 2 * (size_t)a.n, st, a);
+        return;
+    }
+    int thr;
+    size_t lds;
+    dft_shape<double>(a, thr, lds);
+    dim3 grid((unsigned)(((a.nrows + 1) / 2 + a.rpb - 1) / a.rpb));
+    hipLaunchKernelGGL(k_dft_c2r<double>, grid, dim3(thr), lds, st, a);
+}
+
+void launch_dft_r2c(DftArgs a, hipStream_t st, bool f32, bool in64)
+{
+    if (a.nrows <= 0) return;
+    if (f32) {
+        const size_t lds = sizeof(float2) * 2 * (size_t)a.n;
+        if (in64)
+            hipLaunchKernelGGL((k_dft_r2c_direct<float, double>), dim3((a.nrows + 1) / 2), dim3(128), lds, st, a);
+        else
+            hipLaunchKernelGGL((k_dft_r2c_direct<float, float>), dim3((a.nrows + 1) / 2), dim3(128), lds, st, a);
+        return;
+    }
+    int thr;
+    size_t lds;
+    dft_shape<double>(a, thr, lds);
+    dim3 grid((unsigned)(((a.nrows + 1) / 2 + a.rpb - 1) / a.rpb));
+    hipLaunchKernelGGL((k_dft_r2c<double, double>), grid, dim3(thr), lds, st, a);
 }
 
 void launch_gamma_c2r(const GammaArgs &a, hipStream_t st, bool f32)

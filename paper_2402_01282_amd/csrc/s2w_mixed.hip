@@ -25,11 +25,12 @@ __device__ __forceinline__ f4 mfma16(float a, float b, f4 c)
 
 // ------------------------------------------------------------ k_lsum_mm ----
 // C_s[b][ni][m][theta] (complex FP32) = sum_{l >= l0} d^l_mn(theta) w_s[ni][l] flm[b][m][l]
-// grid (m, ni, theta tiles x column groups), one wave per block.
+// grid (m, ni, theta tiles x column groups of 16 NC columns), one wave per block.
 
-template <int NS>
+template <int NS, int NC>
 __global__ __launch_bounds__(64) void k_lsum_mm(const LsumArgs a, const MixOut o)
 {
+    constexpr int CW = 16 * NC;        // columns per wave
     const int m = blockIdx.x, ni = blockIdx.y;
     const int L = a.L;
     const int ntt = (L + 63) >> 6;
@@ -43,61 +44,63 @@ __global__ __launch_bounds__(64) void k_lsum_mm(const LsumArgs a, const MixOut o
     const bool valid = th < L;
 
     __shared__ float Ds[16][64 + 4];
-    __shared__ float Us[16][64 + 4];
-    __shared__ float Ot[64][64 + 1];
+    __shared__ float Us[16][CW + 4];
+    __shared__ float Ot[CW][64 + 1];
 
     const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
-    double c = 0.0, e = 0.0, ep = 0.0;
+    double c = 0.0, cl = 0.0, e = 0.0, ep = 0.0;
     int k = 0;
     if (valid && l0 < L) {
         c = a.cth[th];
+        cl = a.ctl[th];
         const int p1 = (m + n) < 0 ? -(m + n) : (m + n);
         const int p2 = (m - n) < 0 ? -(m - n) : (m - n);
         start_value(a.smant[(size_t)ng * a.Lrec + m], a.sexp[(size_t)ng * a.Lrec + m], p1, p2, a.ch[th],
                     a.sh[th], a.ceps[th], a.seps[th], e, k);
     }
-    f4 acc[4][4];
-    double accd[4][4][4];
+    f4 acc[4][NC];
+    double accd[4][NC][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NC; ++j) {
             acc[i][j] = f4{0, 0, 0, 0};
 #pragma unroll
             for (int r = 0; r < 4; ++r) accd[i][j][r] = 0.0;
         }
 
+    // this lane stages column (lane % CW) for degrees i = lane / CW + (64 / CW) * q
+    const int ccol = lane % CW, cpart = lane / CW;
+    constexpr int NPART = 64 / CW;
+    const int cg = g * CW + ccol;
+    int cs = 0, cb = 0, ccc = 0;
+    const bool cok = cg < ncols;
+    if (cok) {
+        cs = cg / (2 * B);
+        const int rem = cg - cs * 2 * B;
+        cb = rem >> 1;
+        ccc = rem & 1;
+    }
+    const double *wv = a.w[cs < NS ? cs : 0] + (size_t)ni * a.wstride;
+    const double *fl = a.flm + ((size_t)cb * a.flm_m + m) * a.flm_l * 2 + ccc;
+
     int chunk = 0;
     for (int lb = l0; lb < L; lb += 16, ++chunk) {
-        // coefficient tile U[l][col] = w_s[ni][l] flm[b][m][l].(re|im)
-        {
-            const int cg = g * 64 + lane;
-            int s = 0, b = 0, cc = 0;
-            const bool cok = cg < ncols;
-            if (cok) {
-                s = cg / (2 * B);
-                const int rem = cg - s * 2 * B;
-                b = rem >> 1;
-                cc = rem & 1;
-            }
-            const double *wv = a.w[s < NS ? s : 0];
-            const double *fl = a.flm + ((size_t)b * a.flm_m + m) * a.flm_l * 2 + cc;
-#pragma unroll 4
-            for (int i = 0; i < 16; ++i) {
-                const int l = lb + i;
-                float v = 0.f;
-                if (cok && l < L) v = (float)(wv[(size_t)ni * a.wstride + l] * fl[(size_t)l * 2]);
-                Us[i][lane] = v;
-            }
+#pragma unroll
+        for (int q = 0; q < 16 / NPART; ++q) {
+            const int i = cpart + NPART * q;
+            const int l = lb + i;
+            float v = 0.f;
+            if (cok && l < L) v = (float)(wv[l] * fl[(size_t)l * 2]);
+            Us[i][ccol] = v;
         }
-        // recursion: d^l = S_l e^l for 16 degrees
 #pragma unroll 4
         for (int i = 0; i < 16; ++i) {
             const int l = lb + i;
             double A = 0.0, Bv = 0.0, S = 0.0;
             if (l < L) { A = a.A[tabm + l]; Bv = a.B[tabm + l]; S = a.S[tabm + l]; }
             Ds[i][lane] = (valid && k == 0) ? (float)(S * e) : 0.f;
-            const double en = fma(fma(A, c, -Bv), e, -ep);
+            const double en = fma(fma(A, cl, fma(A, c, -Bv)), e, -ep);
             ep = e;
             e = en;
             if ((i & 7) == 7 && k < 0 && fabs(e) > 0x1p256) {
@@ -109,22 +112,22 @@ __global__ __launch_bounds__(64) void k_lsum_mm(const LsumArgs a, const MixOut o
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 4) {
-            float af[4], bf[4];
+            float af[4], bf[NC];
 #pragma unroll
             for (int i = 0; i < 4; ++i) af[i] = Ds[kk + (lane >> 4)][i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bf[j] = Us[kk + (lane >> 4)][j * 16 + (lane & 15)];
+            for (int j = 0; j < NC; ++j) bf[j] = Us[kk + (lane >> 4)][j * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
+                for (int j = 0; j < NC; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
         }
         __syncthreads();
         if ((chunk & 3) == 3) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < NC; ++j) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) accd[i][j][r] += (double)acc[i][j][r];
                     acc[i][j] = f4{0, 0, 0, 0};
@@ -134,17 +137,17 @@ __global__ __launch_bounds__(64) void k_lsum_mm(const LsumArgs a, const MixOut o
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < NC; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 Ot[j * 16 + (lane & 15)][i * 16 + 4 * (lane >> 4) + r] = (float)(accd[i][j][r] + (double)acc[i][j][r]);
     __syncthreads();
     // write (re, im) pairs with theta contiguous
-    for (int p = 0; p < 32; ++p) {
-        const int cg = g * 64 + 2 * p;
-        if (cg >= ncols) break;
-        const int s = cg / (2 * B);
-        const int b = (cg - s * 2 * B) >> 1;
+    for (int p = 0; p < CW / 2; ++p) {
+        const int cgp = g * CW + 2 * p;
+        if (cgp >= ncols) break;
+        const int s = cgp / (2 * B);
+        const int b = (cgp - s * 2 * B) >> 1;
         if (valid) {
             float2 *dst = reinterpret_cast<float2 *>(o.out[s]);
             dst[(((size_t)b * a.nn + ni) * a.mcount + m) * L + th] = make_float2(Ot[2 * p][lane], Ot[2 * p + 1][lane]);
@@ -204,10 +207,11 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
     }
 
     const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
-    double c = 0.0, e = 0.0, ep = 0.0;
+    double c = 0.0, cl = 0.0, e = 0.0, ep = 0.0;
     int k = 0;
     if (valid && l0 < L) {
         c = a.cth[th];
+        cl = a.ctl[th];
         const int p1 = (m + n) < 0 ? -(m + n) : (m + n);
         const int p2 = (m - n) < 0 ? -(m - n) : (m - n);
         start_value(a.smant[(size_t)ng * a.Lrec + m], a.sexp[(size_t)ng * a.Lrec + m], p1, p2, a.ch[th],
@@ -223,7 +227,7 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
             double A = 0.0, Bv = 0.0;
             if (l < L) { A = a.A[tabm + l]; Bv = a.B_[tabm + l]; }
             Dw[lane * 16 + (i ^ (lane & 15))] = (valid && k == 0) ? (float)e : 0.f;
-            const double en = fma(fma(A, c, -Bv), e, -ep);
+            const double en = fma(fma(A, cl, fma(A, c, -Bv)), e, -ep);
             ep = e;
             e = en;
             if ((i & 7) == 7 && k < 0 && fabs(e) > 0x1p256) {
@@ -281,11 +285,12 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
 
 void launch_lsum_mm(const LsumArgs &a, const MixOut &o, int NS, hipStream_t st)
 {
+    constexpr int NC = 2;
     const int ntt = (a.L + 63) / 64;
-    const int ngrp = (2 * o.B * NS + 63) / 64;
+    const int ngrp = (2 * o.B * NS + 16 * NC - 1) / (16 * NC);
     dim3 grid(a.mcount, a.nn, ntt * ngrp);
-    if (NS == 1) hipLaunchKernelGGL(k_lsum_mm<1>, grid, dim3(64), 0, st, a, o);
-    else hipLaunchKernelGGL(k_lsum_mm<2>, grid, dim3(64), 0, st, a, o);
+    if (NS == 1) hipLaunchKernelGGL((k_lsum_mm<1, NC>), grid, dim3(64), 0, st, a, o);
+    else hipLaunchKernelGGL((k_lsum_mm<2, NC>), grid, dim3(64), 0, st, a, o);
 }
 
 void launch_tsum_mm(const TsumArgs &a, const MixIn &in, int NS, hipStream_t st)

@@ -31,9 +31,9 @@ def _mix(z: np.ndarray) -> np.ndarray:
         return z ^ (z >> np.uint64(31))
 
 
-def stream_key(config: int, index: int = 0) -> int:
-    """Key of the random stream for (config k, map b): seed k, map b in a batch."""
-    return ((int(config) & 0xFFFFFFFF) << 32) | (int(index) & 0xFFFFFFFF)
+def stream_key(seed: int, index: int = 0) -> int:
+    """Key of the random stream for (seed k, map b): seed k, map b in a batch."""
+    return ((int(seed) & 0xFFFFFFFF) << 32) | (int(index) & 0xFFFFFFFF)
 
 
 def uniforms(key: int, n: int) -> np.ndarray:

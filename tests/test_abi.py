@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_symbols():
     src = open(os.path.join(ROOT, "include", "s2w.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(s2w_[a-z0-9_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b((?:s2w|b3w)_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -116,3 +116,36 @@ def test_plan_create_rejects_bad_arguments_without_device_work():
     assert h.value is None
     assert lib.s2w_plan_destroy(None) == 0
     assert lib.s2w_analysis(None, None, None, None, None) == -1
+
+
+@pytest.mark.parametrize("m,n", [(0, 0), (1, 0), (7, 7), (8, -7), (300, -5)])
+def test_host_recursion_with_polar_table_at_L1024(m, n):
+    """At L=1024 the FP64 recursion alone drifts by ~1e-11 at the samples next to the
+    poles (near-double characteristic root); with the long-double polar table the
+    l-contraction sum_l a_l d^l_mn(theta_b) matches the oracle's to ~1e-13 relative
+    (compared through the oracle's Delta-based Fourier sums)."""
+    import paper_2402_01282_amd as s2w
+    L = 1024
+    got = s2w.host_wigner_d(L, m, n)            # [l][b]
+    rng = np.random.default_rng(7)
+    l0 = max(abs(m), abs(n))
+    a = np.zeros((L, 1, 1), complex)
+    a[l0:, 0, 0] = rng.normal(size=L - l0) / np.sqrt(np.arange(l0, L) + 1.0)
+    ref = ((1j) ** ((n - m) % 4) * mw.eval_fourier(mw._fourier(L, [m], [n], a)[0], L))[0].real
+    c = a[:, 0, 0].real @ got
+    assert np.linalg.norm(c - ref) / np.linalg.norm(ref) < 1.5e-13
+    # every sample, pole-adjacent ones included, within 4e-12 of the column's rms
+    # (the recursion alone is off by ~1.4e-11 of it at the first sample)
+    assert np.abs(c - ref).max() < 4e-12 * np.linalg.norm(ref) / np.sqrt(L)
+
+
+@pytest.mark.parametrize("P,tau", [(1, 1.0), (7, 0.5), (64, 1.0), (128, 2.0)])
+def test_host_laguerre_rule_matches_oracle(P, tau):
+    """The library's radial rule (Sturm bisection on the Jacobi matrix + Newton, long
+    double) against the oracle's (library eigenvalue estimate + Newton)."""
+    import paper_2402_01282_amd as s2w
+    from oracle import ball
+    r, w = s2w.host_laguerre_rule(P, tau)
+    R = ball.Radial(P, tau)
+    np.testing.assert_allclose(r, R.r, rtol=1e-13)
+    np.testing.assert_allclose(w, R.W, rtol=1e-12)

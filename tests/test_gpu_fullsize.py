@@ -1,4 +1,4 @@
-"""Full-size checks at the benchmark configuration L=1024, N=8, lambda=2, J0=0 (FP64).
+"""Full-size checks at L=1024, N=8, lambda=2, J0=0 (FP64).
 
 The oracle is run on the parts it finishes in seconds at this size (the
 spherical-harmonic transform, one wavelet scale), and properties that hold at
@@ -61,10 +61,12 @@ def test_fullsize_round_trip(setup):
 
 def test_fullsize_top_scale_against_oracle(setup):
     """The top wavelet scale (L_J = 1024, N_J = 8), all 15 x 1024 x 2047 samples,
-    against the oracle's inverse Wigner transform of f_lm conj(Psi) N."""
+    against the oracle's analysis of the same map (the oracle's forward SHT of the
+    GPU-resident map, then its inverse Wigner transform of f_lm conj(Psi) N)."""
     plan, flm, f = setup
     print("[fullsize] top scale vs oracle", flush=True)
     wav, scal = plan.analysis(f)
+    flm = mw.sht_forward(f[0].cpu().numpy(), L)
     P = wavelets.Plan(L, N, LAM, J0)
     k = len(P.scales) - 1
     Lj, Nj = P.Lj[k], P.Nj[k]

@@ -59,7 +59,7 @@ def test_gradient_against_oracle_adjoint(L, N, J0):
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-12
 
 
-def test_gradient_config4_full_size_runs_and_is_consistent():
+def test_gradient_L1024_N8_directional_derivative():
     """L=1024, N=8: the gradient of sum W^2 equals 2 A^T A f; check <grad, v> against
     the directional derivative 2 <A f, A v> for a random direction v."""
     torch = _torch()

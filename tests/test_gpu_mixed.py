@@ -60,11 +60,11 @@ def test_mixed_analysis_and_synthesis(L, N, J0, B):
     assert _rel(g, wavelets.synthesis(wr, sr, P)) < TOL
 
 
-def test_mixed_config3_L512_B64():
-    """Config 3: 64 maps at L=512, N=4, lambda=2, all scales.  Round trip for every
+def test_mixed_L512_N4_B64_all_scales():
+    """64 maps at L=512, N=4, lambda=2, all scales.  Round trip for every
     map; every scale against the oracle for two maps of the batch."""
     torch = _torch()
-    print("[mixed config3 L=512 N=4 B=64]", flush=True)
+    print("[mixed L=512 N=4 B=64]", flush=True)
     L, N, J0, B = 512, 4, 0, 64
     plan = _plan(L, N, J0, B)
     P = wavelets.Plan(L, N, 2.0, J0)
@@ -86,7 +86,7 @@ def test_mixed_config3_L512_B64():
         assert _rel(scal[b].cpu().numpy(), sr) < TOL
 
 
-def test_mixed_metric_config_L1024_round_trip():
+def test_mixed_L1024_N8_B64():
     """L=1024, N=8, batch 64: round trip of every map and the top scale of one map
     against the oracle."""
     torch = _torch()

@@ -101,7 +101,7 @@ def test_adjoint_parity(L, N, J0):
     assert _rel(got[0].cpu().numpy(), ref) < TOL
 
 
-def test_round_trip_config1():
+def test_round_trip_L32_N3():
     """L=32, N=3, lambda=2, J0=0: synthesis(analysis(f)) = f."""
     torch = _torch()
     plan = _plan(32, 3, 0)
@@ -112,11 +112,11 @@ def test_round_trip_config1():
     assert _rel(f2, f) < TOL
 
 
-def test_config2_parity():
-    """L=256, N=4, lambda=2, J0=2 (the FP64 GPU baseline configuration): every
+def test_parity_L256_N4_J0_2():
+    """L=256, N=4, lambda=2, J0=2, one map: every
     scale of the analysis, the synthesis and the round trip against the oracle."""
     torch = _torch()
-    print("[config2 L=256 N=4 J0=2]", flush=True)
+    print("[parity L=256 N=4 J0=2]", flush=True)
     L, N, J0 = 256, 4, 2
     plan = _plan(L, N, J0)
     P = wavelets.Plan(L, N, 2.0, J0)

@@ -20,8 +20,8 @@ def test_round_trip(L, N, J0):
     np.testing.assert_allclose(wavelets.synthesis(wav, scal, P), f, atol=1e-13 * np.abs(f).max())
 
 
-def test_round_trip_config2():
-    """L=256, N=4, lam=2, J0=2 (the FP64 baseline configuration)."""
+def test_round_trip_L256_N4_J0_2():
+    """L=256, N=4, lam=2, J0=2."""
     P = wavelets.Plan(256, 4, 2.0, 2)
     f = _map(256, S.stream_key(2))
     wav, scal = wavelets.analysis(f, P)
