@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay each transform as a HIP graph (no per-kernel timing)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the plan's tile-shape autotuning")
     return ap.parse_args()
 
 
@@ -100,7 +102,9 @@ def main():
     B = args.batch if args.batch is not None else (64 if mixed else 1)
     print(f"[bench] L={L} N={N} lambda={lam} J0={J0} batch={B} precision={args.precision}",
           file=sys.stderr, flush=True)
-    plan = s2w.Plan(L, N, lam, J0, batch=B, device=0, precision=s2w.S2W_MIXED if mixed else s2w.S2W_FP64)
+    flags = (0 if args.no_tune else s2w.S2W_PLAN_TUNE) | (s2w.S2W_PLAN_GRAPH if args.graph else 0)
+    plan = s2w.Plan(L, N, lam, J0, batch=B, device=0, precision=s2w.S2W_MIXED if mixed else s2w.S2W_FP64,
+                    flags=flags)
     # synthetic Gaussian random fields, synthesised on the GPU (FP64 inverse SHT, one map per call)
     synth = s2w.Plan(L, 1, lam, 0, batch=1, device=0)
     f = torch.empty(plan.map_shape, dtype=torch.float64, device="cuda")
@@ -121,7 +125,8 @@ def main():
         step()
     torch.cuda.synchronize()
     print("[bench] warmup done", file=sys.stderr, flush=True)
-    if not args.no_kernel_timing:
+    timing = not (args.no_kernel_timing or args.graph)
+    if timing:
         plan.profile(4096)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -132,7 +137,7 @@ def main():
     print(f"[bench] timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
     kern = {}
     dropped = 0
-    if not args.no_kernel_timing:
+    if timing:
         kern, dropped = plan.profile_read()
         plan.profile(0)
     err = (torch.linalg.norm(f2 - f) / torch.linalg.norm(f)).item()
@@ -155,7 +160,8 @@ def main():
         "config": {"workload": f"sphere directional wavelets analysis+synthesis, "
                                f"{'mixed FP32/FP64 batched' if mixed else 'FP64'}, L={L}, N={N}, "
                                f"lambda={lam:g}, J0={J0}, batch={B}",
-                   "L": L, "N": N, "lambda": lam, "J0": J0, "batch": B, "form": args.precision},
+                   "L": L, "N": N, "lambda": lam, "J0": J0, "batch": B, "form": args.precision,
+                   "tuned": not args.no_tune, "graph": args.graph},
         "coefficients_per_s": maps_per_s * coeffs,
         "round_trip_rel_err": err,
     }

@@ -56,10 +56,20 @@ typedef enum {
 
 typedef struct s2w_plan_s *s2w_plan;
 
+/* Plan flags (bitwise or). */
+enum {
+    S2W_PLAN_TUNE = 1,      /* time the l-contraction tile shapes on the device at creation and
+                               keep the fastest per grid (creation then synchronises the device) */
+    S2W_PLAN_GRAPH = 2      /* s2w_analysis / s2w_synthesis capture their launches into a HIP graph
+                               on the first call with a given (input, output, output) pointer triple
+                               and replay it afterwards (up to 16 triples per plan; kernel timing is
+                               not recorded for graph replays) */
+};
+
 /* Create a plan for band limit L >= 2, azimuthal band limit 1 <= N <= L, dilation
  * lambda > 1, lowest wavelet scale 0 <= J0 <= J, batch >= 1 maps per call, on HIP
- * device `device`.  flags must be 0.  Computes filters (Appendix A), the exact MW
- * theta-quadrature matrices, recursion tables and allocates all workspace. */
+ * device `device`, with flags from S2W_PLAN_*.  Computes filters (Appendix A), the
+ * exact MW theta-quadrature matrices, recursion tables and allocates all workspace. */
 s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, int batch,
                            s2w_precision precision, int device, unsigned flags);
 
@@ -82,13 +92,11 @@ s2w_status s2w_synthesis(s2w_plan plan, const void *wav, const double *scal, dou
 
 /* Transpose of the analysis map under the real inner product of the sample arrays
  * (the gradient of a loss with respect to f, given its gradient with respect to the
- * coefficients).  It is not the synthesis: MW sampling oversamples, so A^T A != I. */
+ * coefficients).  It is not the synthesis: MW sampling oversamples, so A^T A != I.
+ * gwav has the plan's coefficient type (FP32 for S2W_MIXED plans); the adjoint is
+ * evaluated in FP64 with the Wigner d recomputed. */
 s2w_status s2w_analysis_adjoint(s2w_plan plan, const void *gwav, const double *gscal, double *gf,
                                 void *stream);
-
-/* Transpose of the synthesis map (the gradient through a synthesis). */
-s2w_status s2w_synthesis_adjoint(s2w_plan plan, const double *gf, void *gwav, double *gscal,
-                                 void *stream);
 
 /* Spin-0 spherical-harmonic transforms on the plan's grid (Section 2.1,
  * eq:fswsh / eq:iswsh; the S^2 case of the Wigner transforms).  flm is complex
@@ -137,8 +145,8 @@ s2w_status s2w_plan_profile_read(s2w_plan plan, int max, char *names, double *to
 typedef struct b3w_plan_s *b3w_plan;
 
 /* Create a ball plan: L >= 2, 1 <= N <= L, P >= 1, lambda > 1, nu > 1, 0 <= J0 <= J,
- * 0 <= J0p <= J', tau > 0, batch >= 1.  Errors: S2W_EINVAL, S2W_EUNSUPPORTED (N > 8),
- * S2W_ENOMEM, S2W_EHIP. */
+ * 0 <= J0p <= J', tau > 0, batch >= 1, flags 0 or S2W_PLAN_TUNE.  Errors: S2W_EINVAL,
+ * S2W_EUNSUPPORTED (N > 8), S2W_ENOMEM, S2W_EHIP. */
 s2w_status b3w_plan_create(b3w_plan *out, int L, int N, int P, double lambda, double nu, int J0,
                            int J0p, double tau, int batch, s2w_precision precision, int device,
                            unsigned flags);

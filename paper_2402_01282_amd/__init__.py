@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libs2w.so")
 
 S2W_FP64 = 0
 S2W_MIXED = 1
+S2W_PLAN_TUNE = 1
+S2W_PLAN_GRAPH = 2
 
 _STATUS = {0: "S2W_OK", -1: "S2W_EINVAL", -2: "S2W_ENOMEM", -3: "S2W_EHIP",
            -4: "S2W_EUNSUPPORTED", -5: "S2W_ESTATE"}
@@ -46,7 +48,6 @@ def _load():
         "s2w_analysis": [vp, vp, vp, vp, vp],
         "s2w_synthesis": [vp, vp, vp, vp, vp],
         "s2w_analysis_adjoint": [vp, vp, vp, vp, vp],
-        "s2w_synthesis_adjoint": [vp, vp, vp, vp, vp],
         "s2w_sht_forward": [vp, vp, vp, vp],
         "s2w_sht_inverse": [vp, vp, vp, vp],
         "s2w_plan_profile": [vp, ctypes.c_int],
@@ -79,7 +80,7 @@ _lib = _load()
 
 # every symbol the header declares (checked by the tests)
 EXPORTS = ["s2w_plan_create", "s2w_plan_destroy", "s2w_plan_layout", "s2w_analysis", "s2w_synthesis",
-           "s2w_analysis_adjoint", "s2w_synthesis_adjoint", "s2w_sht_forward", "s2w_sht_inverse",
+           "s2w_analysis_adjoint", "s2w_sht_forward", "s2w_sht_inverse",
            "s2w_plan_profile", "s2w_plan_profile_read",
            "s2w_last_error", "s2w_host_scales", "s2w_host_filters", "s2w_host_theta_matrix",
            "s2w_host_wigner_d", "s2w_host_laguerre_rule",
@@ -152,14 +153,14 @@ class Plan:
     coefficients are returned as one packed tensor plus per-scale views.
     """
 
-    def __init__(self, L, N, lam=2.0, J0=0, batch=1, precision=S2W_FP64, device=0):
+    def __init__(self, L, N, lam=2.0, J0=0, batch=1, precision=S2W_FP64, device=0, flags=0):
         import torch
         self._torch = torch
         self.L, self.N, self.lam, self.J0, self.batch = L, N, float(lam), J0, batch
         self.precision = precision
         self.device = device
         h = ctypes.c_void_p()
-        _check(_lib.s2w_plan_create(ctypes.byref(h), L, N, float(lam), J0, batch, precision, device, 0))
+        _check(_lib.s2w_plan_create(ctypes.byref(h), L, N, float(lam), J0, batch, precision, device, int(flags)))
         self._h = h
         ns, j0 = ctypes.c_int(), ctypes.c_int()
         Lk = (ctypes.c_int * 70)()
@@ -282,14 +283,15 @@ class BallPlan:
     (radial scale i, angular scale k) of shape [B, P_i, 2N_k-1, L_k, 2L_k-1].
     """
 
-    def __init__(self, L, N, P, lam=2.0, nu=2.0, J0=0, J0p=0, tau=1.0, batch=1, precision=S2W_FP64, device=0):
+    def __init__(self, L, N, P, lam=2.0, nu=2.0, J0=0, J0p=0, tau=1.0, batch=1, precision=S2W_FP64, device=0,
+                 flags=0):
         import torch
         self._torch = torch
         self.L, self.N, self.P, self.lam, self.nu = L, N, P, float(lam), float(nu)
         self.J0, self.J0p, self.tau, self.batch, self.precision, self.device = J0, J0p, float(tau), batch, precision, device
         h = ctypes.c_void_p()
         _check(_lib.b3w_plan_create(ctypes.byref(h), L, N, P, float(lam), float(nu), J0, J0p, float(tau), batch,
-                                    precision, device, 0))
+                                    precision, device, int(flags)))
         self._h = h
         na, nr = ctypes.c_int(), ctypes.c_int()
         _check(_lib.b3w_plan_layout(h, ctypes.byref(na), ctypes.byref(nr), None, None, None, None, None))

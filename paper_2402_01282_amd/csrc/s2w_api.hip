@@ -77,6 +77,17 @@ struct s2w_plan_s {
     std::vector<std::string> prof_names;
     int64_t prof_dropped = 0;
     int prof_cap = 0;
+    // tuned tile shapes per grid band limit (S2W_PLAN_TUNE)
+    std::map<int, int> tile_lsum, tile_lsum_mm;
+    // graph replay (S2W_PLAN_GRAPH)
+    bool graph = false, capturing = false;
+    hipStream_t cap_stream = nullptr;
+    struct GraphEntry {
+        int kind;
+        const void *a, *b, *c;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
 };
 
 struct b3w_plan_s {
@@ -111,7 +122,7 @@ struct Prof {
     int idx = -1;
     Prof(s2w_plan p_, const char *name, double flop, hipStream_t st_) : p(p_), st(st_)
     {
-        if (p->prof_cap == 0) return;
+        if (p->prof_cap == 0 || p->capturing) return;
         if ((int)p->rec_name.size() >= p->prof_cap) { ++p->prof_dropped; return; }
         int id = -1;
         for (size_t i = 0; i < p->prof_names.size(); ++i)
@@ -277,6 +288,12 @@ LsumArgs lsum_args(s2w_plan p, const DevGrid &g, int mcount, const std::vector<i
     for (int i = 0; i < a.nn; ++i) {
         a.nval[i] = ns[i];
         a.nglob[i] = nglob_index(p, ns[i]);
+    }
+    {
+        auto it = p->tile_lsum.find(g.L);
+        a.tileT = it == p->tile_lsum.end() ? 0 : it->second;
+        auto jt = p->tile_lsum_mm.find(g.L);
+        a.tileNC = jt == p->tile_lsum_mm.end() ? 0 : jt->second;
     }
     a.A = p->A;
     a.B = p->Bt;
@@ -453,6 +470,98 @@ struct BatchScope {
     }
 };
 
+// Graph replay: the launches of one entry point for a given pointer triple are
+// captured once (on the plan's own stream, so that a default caller stream works)
+// into a HIP graph, which is then launched on the caller's stream.
+template <class Body>
+s2w_status run_graph(s2w_plan p, int kind, const void *a, const void *b, const void *c, hipStream_t st,
+                     Body &&body)
+{
+    for (auto &g : p->graphs)
+        if (g.kind == kind && g.a == a && g.b == b && g.c == c) {
+            if (hipGraphLaunch(g.exec, st) != hipSuccess) return fail(S2W_EHIP, "hipGraphLaunch failed");
+            return S2W_OK;
+        }
+    if (p->graphs.size() >= 16) return fail(S2W_EINVAL, "graph cache full (16 pointer triples per plan)");
+    if (!p->cap_stream && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(S2W_EHIP, "stream creation failed");
+    (void)hipGetLastError();
+    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(S2W_EHIP, "hipStreamBeginCapture failed");
+    p->capturing = true;
+    body(p->cap_stream);
+    p->capturing = false;
+    hipGraph_t graph = nullptr;
+    const hipError_t e1 = hipStreamEndCapture(p->cap_stream, &graph);
+    const hipError_t e0 = hipGetLastError();
+    if (e1 != hipSuccess || e0 != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(S2W_EHIP, "graph capture failed");
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) return fail(S2W_EHIP, "hipGraphInstantiate failed");
+    p->graphs.push_back({kind, a, b, c, exec});
+    if (hipGraphLaunch(exec, st) != hipSuccess) return fail(S2W_EHIP, "hipGraphLaunch failed");
+    return S2W_OK;
+}
+
+// S2W_PLAN_TUNE: for every scale group with band limit >= 128, time each tile shape
+// of the l-contraction kernel (theta samples per lane of k_lsum for FP64 plans, MFMA
+// column tiles per wave of k_lsum_mm for mixed plans) on the plan's own shapes and
+// workspace, and keep the fastest.  Runs at plan creation (synchronises).
+void autotune(s2w_plan p)
+{
+    const bool mixed = p->prec == S2W_MIXED;
+    const int B = p->B;
+    (void)hipMemset(p->flm, 0, sizeof(double) * (size_t)B * p->L * p->L * 2);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return;
+    for (auto &grp : p->groups) {
+        const int Lk = grp.L, NS = (int)grp.scales.size();
+        if (Lk < 128 || (mixed ? p->tile_lsum_mm.count(Lk) : p->tile_lsum.count(Lk))) continue;
+        const DevGrid &g = p->grids[Lk];
+        const auto &si = p->S.s[grp.scales[0]];
+        const int nn = (int)si.n.size();
+        LsumArgs la = lsum_args(p, g, Lk, si.n);
+        la.flm = p->flm;
+        la.flm_m = p->L;
+        la.flm_l = p->L;
+        la.wstride = Lk;
+        const size_t cstride = (size_t)B * nn * Lk * Lk * 2;
+        s2w::MixOut mo{};
+        mo.B = B;
+        for (int s = 0; s < NS; ++s) {
+            la.w[s] = p->wpsi[grp.scales[s]];
+            la.out[s] = p->bufA + s * cstride;
+            mo.out[s] = (float *)p->bufA + s * cstride;
+        }
+        const std::vector<int> cands = mixed ? std::vector<int>{1, 2, 4} : std::vector<int>{1, 2, 4, 8};
+        int best = 0;
+        float best_ms = 0.0f;
+        for (int c : cands) {
+            auto launch = [&]() {
+                if (mixed) { la.tileNC = c; s2w::launch_lsum_mm(la, mo, NS, nullptr); }
+                else { la.tileT = c; s2w::launch_lsum(la, NS, B, nullptr); }
+            };
+            launch();
+            (void)hipEventRecord(e0, nullptr);
+            launch();
+            launch();
+            (void)hipEventRecord(e1, nullptr);
+            if (hipEventSynchronize(e1) != hipSuccess) continue;
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (best == 0 || ms < best_ms) { best = c; best_ms = ms; }
+        }
+        if (best) (mixed ? p->tile_lsum_mm : p->tile_lsum)[Lk] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipGetLastError();
+}
+
 s2w_status check_plan(s2w_plan p)
 {
     if (!p) return fail(S2W_EINVAL, "null plan");
@@ -540,7 +649,7 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
     if (!out) return fail(S2W_EINVAL, "null output pointer");
     *out = nullptr;
     if (batch < 1) return fail(S2W_EINVAL, "batch must be >= 1");
-    if (flags != 0) return fail(S2W_EINVAL, "flags must be 0");
+    if (flags & ~(unsigned)(S2W_PLAN_TUNE | S2W_PLAN_GRAPH)) return fail(S2W_EINVAL, "unknown flags");
     if (precision != S2W_FP64 && precision != S2W_MIXED) return fail(S2W_EINVAL, "unknown precision");
     s2w::Scales S;
     std::string err;
@@ -639,6 +748,8 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
         }
         if (!dalloc(p, p->Pphi, (size_t)batch * p->Lphi * p->Lphi * 2)) return oom("workspace");
     }
+    if (flags & S2W_PLAN_TUNE) autotune(p);
+    p->graph = (flags & S2W_PLAN_GRAPH) != 0;
     if (hipDeviceSynchronize() != hipSuccess) {
         free_plan(p);
         delete p;
@@ -654,6 +765,8 @@ s2w_status s2w_plan_destroy(s2w_plan p)
     if (!p->alive) return fail(S2W_ESTATE, "plan destroyed twice");
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
+    for (auto &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     for (auto e : p->ev0) (void)hipEventDestroy(e);
     for (auto e : p->ev1) (void)hipEventDestroy(e);
     free_plan(p);
@@ -801,6 +914,11 @@ s2w_status s2w_analysis(s2w_plan p, const double *f, void *wav_, double *scal, v
     hipStream_t st = (hipStream_t)stream;
     // the forward SHT of the input map runs in FP64 in both forms: it is shared by every
     // scale, and FP32 rounding here would spread as white noise across all degrees
+    if (p->graph && !p->capturing)
+        return run_graph(p, 0, f, wav_, scal, st, [&](hipStream_t cs) {
+            sht_forward_internal(p, f, p->flm, cs);
+            analysis_from_flm(p, p->flm, wav_, scal, cs);
+        });
     sht_forward_internal(p, f, p->flm, st);
     analysis_from_flm(p, p->flm, wav_, scal, st);
     return post_launch("s2w_analysis");
@@ -928,6 +1046,11 @@ s2w_status s2w_synthesis(s2w_plan p, const void *wav_, const double *scal, doubl
     if (s2w_status st = check_plan(p)) return st;
     if (!f || !wav_ || !scal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    if (p->graph && !p->capturing)
+        return run_graph(p, 1, wav_, scal, f, st, [&](hipStream_t cs) {
+            synthesis_to_fhat(p, wav_, scal, p->fhat, cs);
+            sht_inverse_internal(p, p->fhat, f, cs);
+        });
     synthesis_to_fhat(p, wav_, scal, p->fhat, st);
     sht_inverse_internal(p, p->fhat, f, st);
     return post_launch("s2w_synthesis");
@@ -938,8 +1061,10 @@ s2w_status s2w_analysis_adjoint(s2w_plan p, const void *gwav_, const double *gsc
     if (s2w_status st = check_plan(p)) return st;
     if (!gf || !gwav_ || !gscal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
-    if (p->prec == S2W_MIXED) return fail(S2W_EUNSUPPORTED, "the adjoint is provided for S2W_FP64 plans");
-    const double *gwav = (const double *)gwav_;
+    // mixed plans take FP32 cotangents of the wavelet coefficients; the adjoint itself
+    // runs in FP64 (its first stage reads the FP32 rows)
+    const bool mixed = p->prec == S2W_MIXED;
+    const size_t wesz = mixed ? sizeof(float) : sizeof(double);
     const int B = p->B;
     const int npar = (p->N - 1) & 1;
     // wavelet scales: transpose of (c2r, gamma, l-sum)
@@ -953,7 +1078,12 @@ s2w_status s2w_analysis_adjoint(s2w_plan p, const void *gwav_, const double *gsc
         ta.wstride = Lk;
         for (int s = 0; s < NS; ++s) {
             const int k = grp.scales[s];
-            { const DftArgs da_ = dft_args(g, gwav + p->wav_off[k], 2 * Lk - 1, p->bufB, Lk, B * ng * Lk, 1.0); Prof pr_(p, "dft_r2c", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_r2c(da_, st); }
+            {
+                const DftArgs da_ = dft_args(g, (const char *)gwav_ + wesz * p->wav_off[k], 2 * Lk - 1, p->bufB, Lk,
+                                             B * ng * Lk, 1.0);
+                Prof pr_(p, "dft_r2c", dft_flop(da_.n, da_.nrows), st);
+                s2w::launch_dft_r2c(da_, st, false, true, mixed);
+            }
             GammaArgs ga = gamma_args(p, Lk, Lk, Lk, Lk, si.n, ng);
             ga.src = p->bufB;
             ga.dst = p->bufA + s * cstride;
@@ -1099,13 +1229,6 @@ s2w_status s2w_plan_profile_read(s2w_plan p, int max, char *names, double *total
     return S2W_OK;
 }
 
-s2w_status s2w_synthesis_adjoint(s2w_plan p, const double *gf, void *gwav, double *gscal, void *stream)
-{
-    (void)gf; (void)gwav; (void)gscal; (void)stream;
-    if (s2w_status st = check_plan(p)) return st;
-    return fail(S2W_EUNSUPPORTED, "s2w_synthesis_adjoint is not implemented yet");
-}
-
 
 // ------------------------------------------------------------------ ball ---
 
@@ -1154,7 +1277,7 @@ s2w_status b3w_plan_create(b3w_plan *out, int L, int N, int P, double lambda, do
     if (!(nu > 1.0)) return fail(S2W_EINVAL, "nu must be > 1");
     if (!(tau > 0.0)) return fail(S2W_EINVAL, "tau must be > 0");
     if (batch < 1) return fail(S2W_EINVAL, "batch must be >= 1");
-    if (flags != 0) return fail(S2W_EINVAL, "flags must be 0");
+    if (flags & ~(unsigned)S2W_PLAN_TUNE) return fail(S2W_EINVAL, "ball plans accept S2W_PLAN_TUNE only");
     int Jp = 0;
     while (std::pow(nu, (double)Jp) < (double)P) ++Jp;
     if (J0p < 0 || J0p > Jp) return fail(S2W_EINVAL, "J0p must satisfy 0 <= J0p <= J'");
@@ -1163,7 +1286,7 @@ s2w_status b3w_plan_create(b3w_plan *out, int L, int N, int P, double lambda, do
     if (!p) return fail(S2W_ENOMEM, "host allocation failed");
     p->L = L; p->N = N; p->P = P; p->B = batch; p->J0 = J0; p->J0p = J0p; p->Jp = Jp;
     p->lambda = lambda; p->nu = nu; p->tau = tau; p->prec = precision;
-    if (s2w_status st = s2w_plan_create(&p->sp, L, N, lambda, J0, batch * P, precision, device, 0)) {
+    if (s2w_status st = s2w_plan_create(&p->sp, L, N, lambda, J0, batch * P, precision, device, flags)) {
         delete p;
         return st;
     }

@@ -30,6 +30,8 @@ struct LsumArgs {
     const double *w[MAX_NS];     // weights [nn][wstride] (wstride 0: shared by all n)
     int wstride;
     double *out[MAX_NS];         // [B][nn][mcount][L] complex
+    int tileT;                   // theta samples per lane of k_lsum (1, 2, 4, 8; 0: default)
+    int tileNC;                  // 16-column MFMA tiles per wave of k_lsum_mm (1, 2, 4; 0: default)
 };
 
 // sum over theta (reduction across lanes)
@@ -114,7 +116,12 @@ void launch_gemm(const double *A, const double *Bm, double *C, int M, int N, int
 void launch_scale_pl(const double *in, double *out, const double *phi, int P, int L, size_t total, hipStream_t st);
 void launch_gemm_f32(const float *A, const float *Bm, float *C, int M, int N, int K, hipStream_t st);
 void launch_dft_c2r(DftArgs a, hipStream_t st, bool f32 = false);
-void launch_dft_r2c(DftArgs a, hipStream_t st, bool f32 = false, bool in64 = true);
+// f32: FP32 arithmetic (in64: FP64 input rows); otherwise FP64 arithmetic (in32: FP32 input rows)
+void launch_dft_r2c(DftArgs a, hipStream_t st, bool f32 = false, bool in64 = true, bool in32 = false);
+// FP32 DFTs on matrix cores (mixed path); dft_mm_ok tells whether the length is supported
+bool dft_mm_ok(const DftArgs &a);
+void launch_dft_mm_c2r(DftArgs a, hipStream_t st);
+void launch_dft_mm_r2c(DftArgs a, hipStream_t st);
 void launch_gamma_c2r(const GammaArgs &a, hipStream_t st, bool f32 = false);
 void launch_gamma_r2c(const GammaArgs &a, hipStream_t st, bool f32 = false);
 void launch_convert(const void *in, void *out, size_t n, bool to_f32, hipStream_t st);

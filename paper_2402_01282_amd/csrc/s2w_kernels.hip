@@ -414,8 +414,7 @@ __global__ __launch_bounds__(64) void k_tsum_polar(const TsumArgs a)
 
 // ------------------------------------------------------------- k_gemm ------
 // C[M][N] = A[M][K] * Bm[K][N], row-major, on matrix cores (16x16x4 MFMA, FP64 or FP32).
-// Workgroup tile 128 x 128, four waves of 64 x 64 (4 x 4 MFMA tiles), K staged 16 at a
-// time through LDS.  MFMA operand layout (both types): A fragment lane l holds
+// MFMA operand layout (both types): A fragment lane l holds
 // A[l % 16][l / 16], B fragment B[l / 16][l % 16].  Result register j of lane l holds
 // column l % 16 and row 4 (l / 16) + j for FP32 but row l / 16 + 4 j for FP64
 // (checked on the device).
@@ -436,60 +435,147 @@ struct Mfma16<float> {
 };
 
 template <typename Tp>
+struct GemmCfg;
+template <>
+struct GemmCfg<float> {
+    static constexpr int BK = 32, VEC = 4, APAD = 4, BPAD = 16;
+    typedef float4 V;
+};
+template <>
+struct GemmCfg<double> {
+    static constexpr int BK = 16, VEC = 2, APAD = 4, BPAD = 8;
+    typedef double2 V;
+};
+
+// Workgroup tile 128 x 128 (four waves of 64 x 64, 4 x 4 MFMA tiles each), K staged
+// BK at a time through two LDS buffers: the next K slice is fetched from global
+// memory into registers (16-byte vector loads when K and N allow) while the current
+// one feeds the matrix cores.  A is kept [m][k] with row stride BK + 4 and B [k][n]
+// with row stride 128 + BPAD, which makes the fragment reads conflict-free.  Tiles
+// are assigned XCD-aware: consecutive workgroups go to different XCDs (each with its
+// own L2), so workgroup b runs tile (m, n) = (b % 8 + 8 ((b / 8) / nt), (b / 8) % nt),
+// and all column tiles of a 128-row block of A are read on one XCD.
+template <typename Tp>
 __global__ __launch_bounds__(256) void k_gemm(const Tp *__restrict__ A, const Tp *__restrict__ Bm,
-                                              Tp *__restrict__ C, int M, int N, int K, int accum)
+                                              Tp *__restrict__ C, int M, int N, int K, int accum, int mt, int nt,
+                                              int vec)
 {
-    constexpr int BM = 128, BN = 128, BK = 16, PAD = 1;
+    constexpr int BM = 128, BN = 128, BK = GemmCfg<Tp>::BK, VEC = GemmCfg<Tp>::VEC;
+    constexpr int AS = BK + GemmCfg<Tp>::APAD, BS = BN + GemmCfg<Tp>::BPAD;
+    constexpr int AV = BM * BK / VEC / 256, BV = BK * BN / VEC / 256;   // vectors per thread
+    typedef typename GemmCfg<Tp>::V V;
     typedef typename Mfma16<Tp>::v4 v4;
-    __shared__ Tp As[BK][BM + PAD];
-    __shared__ Tp Bs[BK][BN + PAD];
+    extern __shared__ __align__(16) unsigned char gemm_smem[];
+    Tp *As = reinterpret_cast<Tp *>(gemm_smem);          // [2][BM][AS]
+    Tp *Bs = As + 2 * BM * AS;                            // [2][BK][BS]
+    const int bid = blockIdx.x, kx = bid >> 3;
+    const int mtile = (bid & 7) + 8 * (kx / nt), ntile = kx % nt;
+    if (mtile >= mt) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = w >> 1, wc = w & 1;
-    const int row0 = blockIdx.y * BM, col0 = blockIdx.x * BN;
+    const int row0 = mtile * BM, col0 = ntile * BN;
+    V ra[AV], rb[BV];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < AV; ++r) {
+            const int f = tid + 256 * r;
+            const int am = f / (BK / VEC), aq = f % (BK / VEC);
+            const int gr = row0 + am, gk = k0 + aq * VEC;
+            Tp t[VEC];
+            if (vec && gr < M && gk < K) {
+                const V x = *reinterpret_cast<const V *>(A + (size_t)gr * K + gk);
+                __builtin_memcpy(t, &x, sizeof(V));
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) t[e] = (gr < M && gk + e < K) ? A[(size_t)gr * K + gk + e] : Tp(0);
+            }
+            __builtin_memcpy(&ra[r], t, sizeof(V));
+        }
+#pragma unroll
+        for (int r = 0; r < BV; ++r) {
+            const int f = tid + 256 * r;
+            const int bk = f / (BN / VEC), bq = f % (BN / VEC);
+            const int gk = k0 + bk, gc = col0 + bq * VEC;
+            Tp t[VEC];
+            if (vec && gk < K && gc < N) {
+                const V x = *reinterpret_cast<const V *>(Bm + (size_t)gk * N + gc);
+                __builtin_memcpy(t, &x, sizeof(V));
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) t[e] = (gk < K && gc + e < N) ? Bm[(size_t)gk * N + gc + e] : Tp(0);
+            }
+            __builtin_memcpy(&rb[r], t, sizeof(V));
+        }
+    };
+    auto sstore = [&](int buf) {
+        Tp *a = As + buf * BM * AS;
+        Tp *b = Bs + buf * BK * BS;
+#pragma unroll
+        for (int r = 0; r < AV; ++r) {
+            const int f = tid + 256 * r;
+            const int am = f / (BK / VEC), aq = f % (BK / VEC);
+            *reinterpret_cast<V *>(a + am * AS + aq * VEC) = ra[r];
+        }
+#pragma unroll
+        for (int r = 0; r < BV; ++r) {
+            const int f = tid + 256 * r;
+            const int bk = f / (BN / VEC), bq = f % (BN / VEC);
+            *reinterpret_cast<V *>(b + bk * BS + bq * VEC) = rb[r];
+        }
+    };
     v4 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = v4{0, 0, 0, 0};
-    for (int k0 = 0; k0 < K; k0 += BK) {
-#pragma unroll
-        for (int r = 0; r < (BM * BK) / 256; ++r) {
-            const int idx = tid + 256 * r;
-            const int ar = idx / BK, ak = idx % BK;
-            const int gr = row0 + ar, gk = k0 + ak;
-            As[ak][ar] = (gr < M && gk < K) ? A[(size_t)gr * K + gk] : Tp(0);
-            const int bk = idx / BN, bc = idx % BN;
-            const int gk2 = k0 + bk, gc = col0 + bc;
-            Bs[bk][bc] = (gk2 < K && gc < N) ? Bm[(size_t)gk2 * N + gc] : Tp(0);
-        }
-        __syncthreads();
+    const int nk = (K + BK - 1) / BK;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int t = 0; t < nk; ++t) {
+        const int cur = t & 1;
+        if (t + 1 < nk) gload((t + 1) * BK);
+        const Tp *a = As + cur * BM * AS;
+        const Tp *b = Bs + cur * BK * BS;
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             Tp af[4], bf[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) af[i] = As[kk + (lane >> 4)][wr * 64 + i * 16 + (lane & 15)];
+            for (int i = 0; i < 4; ++i) af[i] = a[(wr * 64 + i * 16 + (lane & 15)) * AS + kk + (lane >> 4)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bf[j] = Bs[kk + (lane >> 4)][wc * 64 + j * 16 + (lane & 15)];
+            for (int j = 0; j < 4; ++j) bf[j] = b[(kk + (lane >> 4)) * BS + wc * 64 + j * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) acc[i][j] = Mfma16<Tp>::op(af[i], bf[j], acc[i][j]);
         }
+        if (t + 1 < nk) sstore(cur ^ 1);
         __syncthreads();
     }
+    // accumulate into C only when asked (a uniform branch: the plain store never reads C)
+    if (accum) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int gr = row0 + wr * 64 + i * 16 + Mfma16<Tp>::row(lane, r);
-                const int gc = col0 + wc * 64 + j * 16 + (lane & 15);
-                if (gr < M && gc < N) {
-                    Tp *c = C + (size_t)gr * N + gc;
-                    *c = accum ? *c + acc[i][j][r] : acc[i][j][r];
+                for (int r = 0; r < 4; ++r) {
+                    const int gr = row0 + wr * 64 + i * 16 + Mfma16<Tp>::row(lane, r);
+                    const int gc = col0 + wc * 64 + j * 16 + (lane & 15);
+                    if (gr < M && gc < N) C[(size_t)gr * N + gc] += acc[i][j][r];
                 }
-            }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gr = row0 + wr * 64 + i * 16 + Mfma16<Tp>::row(lane, r);
+                    const int gc = col0 + wc * 64 + j * 16 + (lane & 15);
+                    if (gr < M && gc < N) C[(size_t)gr * N + gc] = acc[i][j][r];
+                }
+    }
 }
 
 // -------------------------------------------------------------- DFTs -------
@@ -1119,7 +1205,8 @@ static void launch_lsum_t(const LsumArgs &a, int B, hipStream_t st)
 
 void launch_lsum(const LsumArgs &a, int NS, int B, hipStream_t st)
 {
-    const int T = a.L > 512 ? 8 : (a.L > 256 ? 8 : (a.L > 128 ? 4 : (a.L > 64 ? 2 : 1)));
+    int T = a.L > 512 ? 8 : (a.L > 256 ? 8 : (a.L > 128 ? 4 : (a.L > 64 ? 2 : 1)));
+    if (a.tileT == 1 || a.tileT == 2 || a.tileT == 4 || a.tileT == 8) T = a.tileT;
     if (NS == 1) {
         switch (T) {
             case 1: launch_lsum_t<1, 1>(a, B, st); break;
@@ -1180,18 +1267,27 @@ void launch_scale_pl(const double *in, double *out, const double *phi, int P, in
     hipLaunchKernelGGL(k_scale_pl, dim3((unsigned)blocks), dim3(256), 0, st, in, out, phi, P, L, total);
 }
 
-void launch_gemm(const double *A, const double *Bm, double *C, int M, int N, int K, hipStream_t st, bool accum)
+template <typename Tp>
+static void launch_gemm_t(const Tp *A, const Tp *Bm, Tp *C, int M, int N, int K, hipStream_t st, bool accum)
 {
     if (M <= 0 || N <= 0) return;
-    dim3 grid((N + 127) / 128, (M + 127) / 128);
-    hipLaunchKernelGGL(k_gemm<double>, grid, dim3(256), 0, st, A, Bm, C, M, N, K, accum ? 1 : 0);
+    constexpr int VEC = GemmCfg<Tp>::VEC, BK = GemmCfg<Tp>::BK;
+    const int mt = (M + 127) / 128, nt = (N + 127) / 128;
+    const bool vec = (K % VEC == 0) && (N % VEC == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)Bm % 16 == 0);
+    const size_t lds = sizeof(Tp) * 2 * ((size_t)128 * (BK + GemmCfg<Tp>::APAD) + (size_t)BK * (128 + GemmCfg<Tp>::BPAD));
+    const unsigned blocks = 8u * (unsigned)nt * (unsigned)((mt + 7) / 8);
+    hipLaunchKernelGGL(k_gemm<Tp>, dim3(blocks), dim3(256), lds, st, A, Bm, C, M, N, K, accum ? 1 : 0, mt, nt,
+                       vec ? 1 : 0);
+}
+
+void launch_gemm(const double *A, const double *Bm, double *C, int M, int N, int K, hipStream_t st, bool accum)
+{
+    launch_gemm_t<double>(A, Bm, C, M, N, K, st, accum);
 }
 
 void launch_gemm_f32(const float *A, const float *Bm, float *C, int M, int N, int K, hipStream_t st)
 {
-    if (M <= 0 || N <= 0) return;
-    dim3 grid((N + 127) / 128, (M + 127) / 128);
-    hipLaunchKernelGGL(k_gemm<float>, grid, dim3(256), 0, st, A, Bm, C, M, N, K, 0);
+    launch_gemm_t<float>(A, Bm, C, M, N, K, st, false);
 }
 
 // Row pairs per block and threads per block for a DFT launch.  In-place stages
@@ -1219,6 +1315,10 @@ void launch_dft_c2r(DftArgs a, hipStream_t st, bool f32)
 {
     if (a.nrows <= 0) return;
     if (f32) {
+        if (dft_mm_ok(a)) {
+            launch_dft_mm_c2r(a, st);
+            return;
+        }
         hipLaunchKernelGGL(k_dft_c2r_direct<float>, dim3((a.nrows + 1) / 2), dim3(128),
                            sizeof(float2) * 2 * (size_t)a.n, st, a);
         return;
@@ -1230,10 +1330,14 @@ void launch_dft_c2r(DftArgs a, hipStream_t st, bool f32)
     hipLaunchKernelGGL(k_dft_c2r<double>, grid, dim3(thr), lds, st, a);
 }
 
-void launch_dft_r2c(DftArgs a, hipStream_t st, bool f32, bool in64)
+void launch_dft_r2c(DftArgs a, hipStream_t st, bool f32, bool in64, bool in32)
 {
     if (a.nrows <= 0) return;
     if (f32) {
+        if (!in64 && dft_mm_ok(a)) {
+            launch_dft_mm_r2c(a, st);
+            return;
+        }
         const size_t lds = sizeof(float2) * 2 * (size_t)a.n;
         if (in64)
             hipLaunchKernelGGL((k_dft_r2c_direct<float, double>), dim3((a.nrows + 1) / 2), dim3(128), lds, st, a);
@@ -1245,7 +1349,10 @@ void launch_dft_r2c(DftArgs a, hipStream_t st, bool f32, bool in64)
     size_t lds;
     dft_shape<double>(a, thr, lds);
     dim3 grid((unsigned)(((a.nrows + 1) / 2 + a.rpb - 1) / a.rpb));
-    hipLaunchKernelGGL((k_dft_r2c<double, double>), grid, dim3(thr), lds, st, a);
+    if (in32)
+        hipLaunchKernelGGL((k_dft_r2c<double, float>), grid, dim3(thr), lds, st, a);
+    else
+        hipLaunchKernelGGL((k_dft_r2c<double, double>), grid, dim3(thr), lds, st, a);
 }
 
 void launch_gamma_c2r(const GammaArgs &a, hipStream_t st, bool f32)

@@ -283,14 +283,21 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
 
 // ------------------------------------------------------------- launchers ---
 
-void launch_lsum_mm(const LsumArgs &a, const MixOut &o, int NS, hipStream_t st)
+template <int NC>
+static void launch_lsum_mm_t(const LsumArgs &a, const MixOut &o, int NS, hipStream_t st)
 {
-    constexpr int NC = 2;
     const int ntt = (a.L + 63) / 64;
     const int ngrp = (2 * o.B * NS + 16 * NC - 1) / (16 * NC);
     dim3 grid(a.mcount, a.nn, ntt * ngrp);
     if (NS == 1) hipLaunchKernelGGL((k_lsum_mm<1, NC>), grid, dim3(64), 0, st, a, o);
     else hipLaunchKernelGGL((k_lsum_mm<2, NC>), grid, dim3(64), 0, st, a, o);
+}
+
+void launch_lsum_mm(const LsumArgs &a, const MixOut &o, int NS, hipStream_t st)
+{
+    if (a.tileNC == 1) launch_lsum_mm_t<1>(a, o, NS, st);
+    else if (a.tileNC == 4) launch_lsum_mm_t<4>(a, o, NS, st);
+    else launch_lsum_mm_t<2>(a, o, NS, st);
 }
 
 void launch_tsum_mm(const TsumArgs &a, const MixIn &in, int NS, hipStream_t st)
@@ -301,6 +308,208 @@ void launch_tsum_mm(const TsumArgs &a, const MixIn &in, int NS, hipStream_t st)
     const size_t smem = sizeof(float) * 1024 * (size_t)NW;
     if (NS == 1) hipLaunchKernelGGL(k_tsum_mm<1>, grid, dim3(64 * NW), smem, st, a, in);
     else hipLaunchKernelGGL(k_tsum_mm<2>, grid, dim3(64 * NW), smem, st, a, in);
+}
+
+// ------------------------------------------------------------ k_dft_mm -----
+// FP32 odd-length DFTs of the mixed path on matrix cores.  Same prime-factor
+// order and index tables as the FP64 kernels (input index (m1 n2 + m2 n1) mod n
+// at LDS position m1 n2 + m2; output frequency (a1 e1 + a2 e2) mod n at a1 n2 + a2),
+// R row pairs per block, two real rows per complex row.  Each length-p stage
+// pairs k with p-k (u_k = x_k + x_{p-k}, u_0 = x_0, v_k = x_k - x_{p-k}) and
+// forms, as dense products on 16x16x4 FP32 MFMA,
+//   A = C u,  B = S v,  C[j][k] = cos(2 pi jk/p),  S[j][k] = sin(2 pi jk/p),  0 <= j, k <= h,
+// then X_j = A_j + i sgn B_j and X_{p-j} = A_j - i sgn B_j (h = (p-1)/2).  A column
+// of the products is the real or imaginary part of one sequence (slot, sequence):
+// a 16-column tile holds 8 whole sequences, and the wave that reads a tile is the
+// one that overwrites it, so each stage works in place.  C and S stay in
+// registers as MFMA A operands (p <= 95); the u, v operands come from LDS.
+
+constexpr int DMM_MT = 3;     // 16-row tiles of j (h + 1 <= 48)
+constexpr int DMM_KS = 12;    // 4-deep steps of k
+
+__device__ __attribute__((always_inline)) inline void dft_mm_stage(float2 *Z, const float2 *tw, int n, int R, int p,
+                                                                   int q, int sj, int sc, float sgn)
+{
+    if (p == 1) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int h = (p - 1) / 2, mt = (h + 16) / 16, ks = (h + 4) / 4;
+    float fc[DMM_MT][DMM_KS], fs[DMM_MT][DMM_KS];
+    // fragments: lane holds C[16 i + lane % 16][4 s + lane / 16]
+#pragma unroll
+    for (int i = 0; i < DMM_MT; ++i)
+#pragma unroll
+        for (int s = 0; s < DMM_KS; ++s) {
+            const int j = 16 * i + (lane & 15), k = 4 * s + (lane >> 4);
+            float cv = 0.f, sv = 0.f;
+            if (i < mt && s < ks && j <= h && k <= h) {
+                const float2 t = tw[(j * k) % p];
+                cv = t.x;
+                sv = t.y;
+            }
+            fc[i][s] = cv;
+            fs[i][s] = sv;
+        }
+    float *Zf = reinterpret_cast<float *>(Z);
+    const int ncol = 2 * R * q, ntile = (ncol + 15) / 16;
+    for (int tile = w; tile < ntile; tile += nw) {
+        const int col = 16 * tile + (lane & 15);
+        const bool cok = col < ncol;
+        const int s = cok ? col / (2 * q) : 0;
+        const int rem = col - s * 2 * q;
+        const int c = rem >> 1, ri = rem & 1;
+        const int base = s * n + c * sc;      // complex index of element k = 0
+        f4 accA[DMM_MT], accB[DMM_MT];
+#pragma unroll
+        for (int i = 0; i < DMM_MT; ++i) {
+            accA[i] = f4{0.f, 0.f, 0.f, 0.f};
+            accB[i] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int st = 0; st < DMM_KS; ++st) {
+            if (st >= ks) continue;
+            const int k = 4 * st + (lane >> 4);
+            float u = 0.f, v = 0.f;
+            if (cok && k <= h) {
+                const float x1 = Zf[2 * (base + k * sj) + ri];
+                if (k == 0) {
+                    u = x1;
+                } else {
+                    const float x2 = Zf[2 * (base + (p - k) * sj) + ri];
+                    u = x1 + x2;
+                    v = x1 - x2;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < DMM_MT; ++i) {
+                if (i >= mt) continue;
+                accA[i] = mfma16(fc[i][st], u, accA[i]);
+                accB[i] = mfma16(fs[i][st], v, accB[i]);
+            }
+        }
+        // combine real and imaginary columns (adjacent lanes) and write in place
+#pragma unroll
+        for (int i = 0; i < DMM_MT; ++i) {
+            if (i >= mt) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float a = accA[i][r], b = accB[i][r];
+                const float ao = __shfl_xor(a, 1, 64), bo = __shfl_xor(b, 1, 64);
+                const int j = 16 * i + 4 * (lane >> 4) + r;
+                if (cok && ri == 0 && j <= h) {
+                    // this lane: A.re = a, B.re = b; partner: A.im = ao, B.im = bo
+                    Z[base + j * sj] = make_float2(a - sgn * bo, ao + sgn * b);
+                    if (j > 0) Z[base + (p - j) * sj] = make_float2(a + sgn * bo, ao - sgn * b);
+                }
+            }
+        }
+    }
+}
+
+// c2r (DIR = +1): Hermitian rows E (m < Lh, complex FP32) -> real rows of length n.
+// r2c (DIR = -1): real rows (Tin) -> X_m = scale sum_a x(a) e^{-2 pi i m a/n}, m < Lh.
+template <int DIR, typename Tin>
+__global__ __launch_bounds__(256) void k_dft_mm(const DftArgs a)
+{
+    extern __shared__ __align__(16) unsigned char dmm_smem[];
+    float2 *tw1 = reinterpret_cast<float2 *>(dmm_smem), *tw2 = tw1 + a.n1, *Z = tw2 + a.n2;
+    const int n = a.n, Lh = (n + 1) / 2, R = a.rpb;
+    const double2 *w1 = reinterpret_cast<const double2 *>(a.w1), *w2 = reinterpret_cast<const double2 *>(a.w2);
+    for (int i = threadIdx.x; i < a.n1 + a.n2; i += blockDim.x) {
+        const double2 t = i < a.n1 ? w1[i] : w2[i - a.n1];
+        tw1[i] = make_float2((float)t.x, (float)t.y);
+    }
+    const long pair0 = (long)blockIdx.x * R;
+    if (DIR > 0) {
+        const float sc = (float)a.scale;
+        for (int idx = threadIdx.x; idx < R * Lh; idx += blockDim.x) {
+            const int s = idx / Lh, mm = idx - s * Lh;
+            const long r1 = 2 * (pair0 + s);
+            float2 *Zs = Z + (size_t)s * n;
+            float2 z1 = make_float2(0.f, 0.f), z2 = make_float2(0.f, 0.f);
+            if (r1 < a.nrows) {
+                z1 = reinterpret_cast<const float2 *>(a.in)[r1 * a.istride + mm];
+                if (r1 + 1 < a.nrows) z2 = reinterpret_cast<const float2 *>(a.in)[(r1 + 1) * a.istride + mm];
+            }
+            if (mm == 0) {
+                Zs[a.inpos[0]] = make_float2(sc * z1.x, sc * z2.x);
+            } else {
+                Zs[a.inpos[mm]] = make_float2(sc * (z1.x - z2.y), sc * (z1.y + z2.x));
+                Zs[a.inpos[n - mm]] = make_float2(sc * (z1.x + z2.y), sc * (z2.x - z1.y));
+            }
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < R * n; idx += blockDim.x) {
+            const int s = idx / n, mm = idx - s * n;
+            const long r1 = 2 * (pair0 + s);
+            float x1 = 0.f, x2 = 0.f;
+            if (r1 < a.nrows) {
+                const Tin *x = reinterpret_cast<const Tin *>(a.in);
+                x1 = (float)x[r1 * a.istride + mm];
+                if (r1 + 1 < a.nrows) x2 = (float)x[(r1 + 1) * a.istride + mm];
+            }
+            Z[(size_t)s * n + a.inpos[mm]] = make_float2(x1, x2);
+        }
+    }
+    __syncthreads();
+    const float sgn = DIR > 0 ? 1.f : -1.f;
+    dft_mm_stage(Z, tw1, n, R, a.n1, a.n2, a.n2, 1, sgn);
+    __syncthreads();
+    dft_mm_stage(Z, tw2, n, R, a.n2, a.n1, 1, a.n2, sgn);
+    __syncthreads();
+    if (DIR > 0) {
+        for (int idx = threadIdx.x; idx < R * n; idx += blockDim.x) {
+            const int s = idx / n, aa = idx - s * n;
+            const long r1 = 2 * (pair0 + s);
+            if (r1 >= a.nrows) continue;
+            const float2 z = Z[(size_t)s * n + a.outpos[aa]];
+            reinterpret_cast<float *>(a.out)[r1 * a.ostride + aa] = z.x;
+            if (r1 + 1 < a.nrows) reinterpret_cast<float *>(a.out)[(r1 + 1) * a.ostride + aa] = z.y;
+        }
+    } else {
+        const float hs = (float)(0.5 * a.scale);
+        for (int idx = threadIdx.x; idx < R * Lh; idx += blockDim.x) {
+            const int s = idx / Lh, mm = idx - s * Lh;
+            const long r1 = 2 * (pair0 + s);
+            if (r1 >= a.nrows) continue;
+            const float2 *Zs = Z + (size_t)s * n;
+            const float2 X = Zs[a.outpos[mm]];
+            const float2 Xc = Zs[a.outpos[mm == 0 ? 0 : n - mm]];
+            float2 *O = reinterpret_cast<float2 *>(a.out);
+            O[r1 * a.ostride + mm] = make_float2(hs * (X.x + Xc.x), hs * (X.y - Xc.y));
+            if (r1 + 1 < a.nrows) O[(r1 + 1) * a.ostride + mm] = make_float2(hs * (X.y + Xc.y), -hs * (X.x - Xc.x));
+        }
+    }
+}
+
+// Matrix-core DFT usable for this length: both prime-factor lengths within the
+// register-resident C and S (p <= 95).
+bool dft_mm_ok(const DftArgs &a) { return a.n1 <= 95 && a.n2 <= 95 && a.n >= 15; }
+
+static void dft_mm_shape(DftArgs &a, size_t &lds, int &blocks)
+{
+    int R = 1;
+    while (R < 8 && (size_t)(2 * R) * a.n * sizeof(float2) <= 65536) R *= 2;
+    a.rpb = R;
+    lds = ((size_t)R * a.n + a.n1 + a.n2) * sizeof(float2);
+    blocks = (int)(((a.nrows + 1) / 2 + R - 1) / R);
+}
+
+void launch_dft_mm_c2r(DftArgs a, hipStream_t st)
+{
+    if (a.nrows <= 0) return;
+    size_t lds;
+    int blocks;
+    dft_mm_shape(a, lds, blocks);
+    hipLaunchKernelGGL((k_dft_mm<1, float>), dim3(blocks), dim3(256), lds, st, a);
+}
+
+void launch_dft_mm_r2c(DftArgs a, hipStream_t st)
+{
+    if (a.nrows <= 0) return;
+    size_t lds;
+    int blocks;
+    dft_mm_shape(a, lds, blocks);
+    hipLaunchKernelGGL((k_dft_mm<-1, float>), dim3(blocks), dim3(256), lds, st, a);
 }
 
 }  // namespace s2w
