@@ -6,9 +6,13 @@ paper's protocol of Section 4.4 without its harmonic-space bookends).  Inputs
 are synthetic Gaussian random fields (C_l = 1/(l+1)^2) synthesised on the GPU
 and resident in HBM before timing starts.
 
-Prints one JSON line.  `roofline` reports the dominant kernel: algorithmic
-work per launch (counted by the library from each launch's parameters) over
-its average duration measured with HIP events on the stream it runs on.
+Prints one JSON line.  By default the headline value is the mixed-precision
+batched form (64 maps per call) and `fp64_form` carries the plain FP64 form
+(one map per call) measured in the same run.  `roofline` reports the dominant
+kernel: algorithmic work per launch (counted by the library from each launch's
+parameters) over its average duration measured with HIP events on the stream
+it runs on; `traffic` is the HBM bytes per launch from a committed PMC summary
+(profiles/traffic.json) when it was taken on the current sources, else null.
 `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
 workload on this host.
 """
@@ -41,20 +45,25 @@ def parse():
     ap.add_argument("--N", type=int, default=8)
     ap.add_argument("--lam", type=float, default=2.0)
     ap.add_argument("--J0", type=int, default=0)
-    ap.add_argument("--batch", type=int, default=None, help="maps per call (default 1 for fp64, 64 for mixed)")
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--batch", type=int, default=None, help="maps per call (default 64 for mixed, 1 for fp64)")
+    ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both",
+                    help="both: the mixed batched form (the headline value) and the FP64 form beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay each transform as a HIP graph (no per-kernel timing)")
     ap.add_argument("--no-tune", action="store_true", help="skip the plan's tile-shape autotuning")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for scaling HBM traffic counters)")
     return ap.parse_args()
 
 
 def cpu_baseline(L, N, lam, J0):
     """Time the oracle on a bounded sample of the workload: the spherical-harmonic
-    transform pair at full size plus the analysis and synthesis of the TOP wavelet
-    scale (the largest single piece), scaled to one full round trip by the oracle's
-    own cost model sum_j L_j^3 N_j over the scales."""
+    transform pair at full size plus the analysis and synthesis of one wavelet scale,
+    scaled to one full round trip by the oracle's own cost model sum_j L_j^3 N_j over
+    the scales.  The scale is the largest with L_j <= L/2, or the top scale when that
+    one is projected to take under 30 s on this host; it is repeated until the sample
+    holds at least 10 s of CPU work."""
     import numpy as np
 
     import synthetic
@@ -68,40 +77,77 @@ def cpu_baseline(L, N, lam, J0):
     f = np.real(mw.sht_inverse(flm, L))
     flm2 = mw.sht_forward(f, L)
     t_sht = time.perf_counter() - t0
-    k = len(P.scales) - 1
-    Lj, Nj = P.Lj[k], P.Nj[k]
-    fl = flm2[:Lj, L - Lj:L + Lj - 1]
-    lj = np.arange(Lj)
-    what = (8 * np.pi ** 2 / (2 * lj + 1))[None, :, None] * fl[None] * np.conj(P.psi(k)).T[:, :, None]
-    t0 = time.perf_counter()
-    w = mw.wigner_inverse(what, Lj, Nj)
-    _ = mw.wigner_forward(np.real(w), Lj, Nj)
-    t_top = time.perf_counter() - t0
     cost = [P.Lj[i] ** 3 * P.Nj[i] for i in range(len(P.scales))]
-    t_round = t_sht + t_top * sum(cost) / cost[k]
+
+    def scale_round_trip(k):
+        Lj, Nj = P.Lj[k], P.Nj[k]
+        fl = flm2[:Lj, L - Lj:L + Lj - 1]
+        lj = np.arange(Lj)
+        what = (8 * np.pi ** 2 / (2 * lj + 1))[None, :, None] * fl[None] * np.conj(P.psi(k)).T[:, :, None]
+        t = time.perf_counter()
+        w = mw.wigner_inverse(what, Lj, Nj)
+        _ = mw.wigner_forward(np.real(w), Lj, Nj)
+        return time.perf_counter() - t
+
+    ks = [i for i in range(len(P.scales)) if P.Lj[i] <= max(L // 2, 1)]
+    k = ks[-1] if ks else len(P.scales) - 1
+    t_s = scale_round_trip(k)
+    top = len(P.scales) - 1
+    if k != top and t_s * cost[top] / cost[k] < 30.0:
+        k = top
+        t_s = scale_round_trip(k)
+    # repeat the scale until the sample holds at least 10 s of CPU work; use the mean
+    reps = [t_s]
+    while t_sht + sum(reps) < 10.0:
+        reps.append(scale_round_trip(k))
+    t_s = sum(reps) / len(reps)
+    t_round = t_sht + t_s * sum(cost) / cost[k]
     return {"value": 1.0 / t_round, "unit": "maps/s", "cores": threads, "kind": "oracle",
-            "sample": (f"oracle SHT pair at L={L} plus analysis+synthesis of the top scale "
-                       f"(L_j={Lj}, N_j={Nj}) in {t_sht + t_top:.1f} s, scaled to the full round trip by "
-                       f"sum_j L_j^3 N_j / (L_J^3 N_J) = {sum(cost) / cost[k]:.3f}")}
+            "sample": (f"oracle SHT pair at L={L} ({t_sht:.1f} s) plus analysis+synthesis of the scale "
+                       f"L_j={P.Lj[k]}, N_j={P.Nj[k]} ({len(reps)} x {t_s:.1f} s), scaled to the full round "
+                       f"trip by sum_j L_j^3 N_j / (L_j^3 N_j) = {sum(cost) / cost[k]:.2f}")}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "sharding across GPUs is not built", file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
+def source_hash():
+    """sha256 of the library sources (kernels, host code, ABI header)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2402_01282_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".h", ".cpp")))
+    files.append(os.path.join(ROOT, "include", "s2w.h"))
+    for fn in files:
+        h.update(os.path.basename(fn).encode())
+        h.update(open(fn, "rb").read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed PMC summary, if it was taken
+    on the current sources and the same workload (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except ValueError:
+        return None
+    if rec.get("source_sha256") != source_hash():
+        return None
+    ent = rec.get("kernels", {}).get(kernel)
+    if not ent or ent.get("workload") != workload:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def run_form(args, precision, B):
     import torch
 
     import paper_2402_01282_amd as s2w
     import synthetic
 
     L, N, lam, J0 = args.L, args.N, args.lam, args.J0
-    mixed = args.precision == "mixed"
-    B = args.batch if args.batch is not None else (64 if mixed else 1)
-    print(f"[bench] L={L} N={N} lambda={lam} J0={J0} batch={B} precision={args.precision}",
-          file=sys.stderr, flush=True)
+    mixed = precision == "mixed"
+    print(f"[bench] L={L} N={N} lambda={lam} J0={J0} batch={B} precision={precision}", file=sys.stderr, flush=True)
     flags = (0 if args.no_tune else s2w.S2W_PLAN_TUNE) | (s2w.S2W_PLAN_GRAPH if args.graph else 0)
     plan = s2w.Plan(L, N, lam, J0, batch=B, device=0, precision=s2w.S2W_MIXED if mixed else s2w.S2W_FP64,
                     flags=flags)
@@ -130,41 +176,22 @@ def main():
         plan.profile(4096)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    print(f"[bench] timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
-    kern = {}
-    dropped = 0
+    print(f"[bench] {precision}: timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    kern, dropped = {}, 0
     if timing:
         kern, dropped = plan.profile_read()
         plan.profile(0)
     err = (torch.linalg.norm(f2 - f) / torch.linalg.norm(f)).item()
-
     maps_per_s = B * args.steps / dt
-    coeffs = plan.wav_offset[-1] // B
-    out = {
-        "metric": "analysis+synthesis maps/s at L=1024,N=8: FP64 vs mixed-batched @ <=1e-6 rel err",
-        "value": maps_per_s,
-        "unit": "maps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * dt / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64" if mixed else "f64",
-        "data": "synthetic Gaussian random fields, C_l = 1/(l+1)^2, synthesised on the GPU",
-        "config": {"workload": f"sphere directional wavelets analysis+synthesis, "
-                               f"{'mixed FP32/FP64 batched' if mixed else 'FP64'}, L={L}, N={N}, "
-                               f"lambda={lam:g}, J0={J0}, batch={B}",
-                   "L": L, "N": N, "lambda": lam, "J0": J0, "batch": B, "form": args.precision,
-                   "tuned": not args.no_tune, "graph": args.graph},
-        "coefficients_per_s": maps_per_s * coeffs,
-        "round_trip_rel_err": err,
-    }
+    workload = (f"sphere directional wavelets analysis+synthesis, "
+                f"{'mixed FP32/FP64 batched' if mixed else 'FP64'}, L={L}, N={N}, lambda={lam:g}, J0={J0}, batch={B}")
+    out = {"value": maps_per_s, "ms_per_step": 1e3 * dt / args.steps,
+           "dtype": "f32+f64" if mixed else "f64", "workload": workload, "batch": B,
+           "coefficients_per_s": maps_per_s * (plan.wav_offset[-1] // B), "round_trip_rel_err": err}
     if kern:
         tot = sum(v[0] for v in kern.values())
         name, (ms, cnt, flop) = max(kern.items(), key=lambda kv: kv[1][0])
@@ -174,7 +201,8 @@ def main():
         else:
             peak, bound = PEAKS["fp64_valu"], "alu"
         out["roofline"] = {"bound": bound, "kernel": name, "achieved": achieved / 1e12, "peak": peak / 1e12,
-                           "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                           "unit": "TFLOP/s", "frac": achieved / peak,
+                           "traffic": recorded_traffic(name, workload),
                            "avg_launch_ms": ms / max(cnt, 1), "launches": cnt,
                            "algorithmic_flop_per_launch": flop / max(cnt, 1)}
         out["kernel_breakdown_ms_per_step"] = {k: v[0] / args.steps for k, v in
@@ -182,9 +210,62 @@ def main():
         out["kernel_time_fraction_of_step"] = tot / (1e3 * dt)
         if dropped:
             out["kernel_timing_dropped_launches"] = dropped
+    del plan, wav, scal, f, f2
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "sharding across GPUs is not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    forms = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
+    res = {}
+    for form in forms:
+        B = args.batch if args.batch is not None else (64 if form == "mixed" else 1)
+        res[form] = run_form(args, form, B)
+    head = res[forms[0]]
+    out = {
+        "metric": "analysis+synthesis maps/s at L=1024,N=8: FP64 vs mixed-batched @ <=1e-6 rel err",
+        "value": head["value"],
+        "unit": "maps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head["dtype"],
+        "data": "synthetic Gaussian random fields, C_l = 1/(l+1)^2, synthesised on the GPU",
+        "config": {"workload": head["workload"], "L": args.L, "N": args.N, "lambda": args.lam, "J0": args.J0,
+                   "batch": head["batch"], "form": forms[0], "tuned": not args.no_tune, "graph": args.graph},
+        "coefficients_per_s": head["coefficients_per_s"],
+        "round_trip_rel_err": head["round_trip_rel_err"],
+    }
+    for k in ("roofline", "kernel_breakdown_ms_per_step", "kernel_time_fraction_of_step",
+              "kernel_timing_dropped_launches"):
+        if k in head:
+            out[k] = head[k]
+    if "fp64" in res and forms[0] != "fp64":
+        out["fp64_form"] = res["fp64"]
+        out["speedup_vs_fp64_form"] = head["value"] / res["fp64"]["value"]
+    if args.copy_calibration:
+        # a plain copy of known size, for scaling the HBM traffic counters of a profiled run
+        n = 1 << 27
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": 8 * n, "written": 8 * n}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(L, N, lam, J0)
+        out["cpu_baseline"] = cpu_baseline(args.L, args.N, args.lam, args.J0)
     print(json.dumps(out), flush=True)
 
 

@@ -164,19 +164,23 @@ __global__ __launch_bounds__(64) void k_lsum(const LsumArgs a)
 // h_s rows (re, im) come from the sigma-grouped layout [sig][b][m'][ni][c][theta].
 
 template <int T, int NS>
-__global__ __launch_bounds__(64) void k_tsum(const TsumArgs a)
+__global__ __launch_bounds__(256) void k_tsum(const TsumArgs a)
 {
-    constexpr int LB = 32 / NS;          // l-steps per reduction block: 2*NS*LB = 64 entries
+    constexpr int LB = 16 / NS;          // l-steps per reduction block: 2*NS*LB = 32 entries
     constexpr int K = 2 * NS * LB;
+    constexpr int MAXW = 4;
     const int m = blockIdx.x, ni = blockIdx.y;
     const int b = blockIdx.z;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int n = a.nval[ni], ng = a.nglob[ni];
     const int an = n < 0 ? -n : n;
     const int l0 = m > an ? m : an;
     const int lmax = a.L;
 
-    __shared__ double red[64][K + 1];
+    // wave w owns theta = 64 (w T + t) + lane, t < T; each wave reduces its lanes
+    // through red[w], then wave 0 adds the waves' partials in a fixed order
+    __shared__ double red[MAXW][64][K + 1];
+    __shared__ double part[MAXW][K];
     __shared__ double2 sAB[LB];
 
     // input rows
@@ -195,7 +199,7 @@ __global__ __launch_bounds__(64) void k_tsum(const TsumArgs a)
     bool asleep_any = false;
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-        const int th = t * 64 + lane;
+        const int th = (w * T + t) * 64 + lane;
         e[t] = 0.0;
         ep[t] = 0.0;
         k[t] = 0;
@@ -221,11 +225,11 @@ __global__ __launch_bounds__(64) void k_tsum(const TsumArgs a)
 
     for (int lb = l0; lb < lmax; lb += LB) {
         __syncthreads();
-        if (lane < LB) {
-            const int l = lb + lane;
+        if (threadIdx.x < LB) {
+            const int l = lb + threadIdx.x;
             double A = 0.0, Bv = 0.0;
             if (l < lmax) { A = a.A[tabm + l]; Bv = a.B_[tabm + l]; }
-            sAB[lane] = make_double2(A, Bv);
+            sAB[threadIdx.x] = make_double2(A, Bv);
         }
         __syncthreads();
         for (int i = 0; i < LB; ++i) {
@@ -246,8 +250,8 @@ __global__ __launch_bounds__(64) void k_tsum(const TsumArgs a)
             }
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                red[lane][(s * LB + i) * 2 + 0] = pr[s];
-                red[lane][(s * LB + i) * 2 + 1] = pi[s];
+                red[w][lane][(s * LB + i) * 2 + 0] = pr[s];
+                red[w][lane][(s * LB + i) * 2 + 1] = pi[s];
             }
             if (anyAsleep && ((i & 7) == 7)) {
                 bool any = false;
@@ -258,7 +262,7 @@ __global__ __launch_bounds__(64) void k_tsum(const TsumArgs a)
                             e[t] *= 0x1p-512;
                             ep[t] *= 0x1p-512;
                             k[t] += 1;
-                            const int th = t * 64 + lane;
+                            const int th = (w * T + t) * 64 + lane;
                             if (k[t] == 0 && !is_polar(th, a.L, a.npol)) {
 #pragma unroll
                                 for (int s = 0; s < NS; ++s) {
@@ -274,25 +278,31 @@ __global__ __launch_bounds__(64) void k_tsum(const TsumArgs a)
             }
         }
         __syncthreads();
-        // lane j sums entry j over the 64 source lanes
-        {
-            const int j = lane;
+        // lane j < K of each wave sums entry j over the wave's 64 lanes
+        if (lane < K) {
             double v = 0.0;
 #pragma unroll 8
-            for (int src = 0; src < 64; ++src) v += red[src][j];
+            for (int src = 0; src < 64; ++src) v += red[w][src][lane];
+            part[w][lane] = v;
+        }
+        __syncthreads();
+        if (w == 0 && lane < K) {
+            const int j = lane;
+            double v = 0.0;
+            for (int ww = 0; ww < nw; ++ww) v += part[ww][j];
             const int s = j / (2 * LB);
             const int i = (j / 2) % LB;
             const int cc = j & 1;
             const int l = lb + i;
             if (l < lmax) {
                 const double S = a.S[tabm + l];
-                const double w = a.w[s][(size_t)ni * a.wstride + l];
-                a.out[s][((((size_t)b * a.mcount + m) * a.nn + ni) * a.L + l) * 2 + cc] = v * S * w;
+                const double wgt = a.w[s][(size_t)ni * a.wstride + l];
+                a.out[s][((((size_t)b * a.mcount + m) * a.nn + ni) * a.L + l) * 2 + cc] = v * S * wgt;
             }
         }
     }
     // zero the l < l0 part of the output rows
-    for (int l = lane; l < l0 && l < lmax; l += 64) {
+    for (int l = threadIdx.x; l < l0 && l < lmax; l += blockDim.x) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             double *o = a.out[s] + ((((size_t)b * a.mcount + m) * a.nn + ni) * a.L + l) * 2;
@@ -1230,28 +1240,26 @@ void launch_lsum(const LsumArgs &a, int NS, int B, hipStream_t st)
 }
 
 template <int T, int NS>
-static void launch_tsum_t(const TsumArgs &a, int B, hipStream_t st)
+static void launch_tsum_t(const TsumArgs &a, int B, int nw, hipStream_t st)
 {
     dim3 grid(a.mcount, a.nn, B);
-    hipLaunchKernelGGL((k_tsum<T, NS>), grid, dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_tsum<T, NS>), grid, dim3(64 * nw), 0, st, a);
 }
 
 void launch_tsum(const TsumArgs &a, int NS, int B, hipStream_t st)
 {
-    // one wave covers all theta: T = ceil(L / 64)
-    const int T = (a.L + 63) / 64;
+    // T theta samples per lane (at most 4, keeping the lane state in registers) and
+    // up to 4 waves per block: T = ceil(L / (64 nw)) with nw = ceil(L / 256)
+    const int nw = std::min(4, std::max(1, (a.L + 255) / 256));
+    const int T = (a.L + 64 * nw - 1) / (64 * nw);
     if (NS == 1) {
-        if (T <= 1) launch_tsum_t<1, 1>(a, B, st);
-        else if (T <= 2) launch_tsum_t<2, 1>(a, B, st);
-        else if (T <= 4) launch_tsum_t<4, 1>(a, B, st);
-        else if (T <= 8) launch_tsum_t<8, 1>(a, B, st);
-        else launch_tsum_t<16, 1>(a, B, st);
+        if (T <= 1) launch_tsum_t<1, 1>(a, B, nw, st);
+        else if (T <= 2) launch_tsum_t<2, 1>(a, B, nw, st);
+        else launch_tsum_t<4, 1>(a, B, nw, st);
     } else {
-        if (T <= 1) launch_tsum_t<1, 2>(a, B, st);
-        else if (T <= 2) launch_tsum_t<2, 2>(a, B, st);
-        else if (T <= 4) launch_tsum_t<4, 2>(a, B, st);
-        else if (T <= 8) launch_tsum_t<8, 2>(a, B, st);
-        else launch_tsum_t<16, 2>(a, B, st);
+        if (T <= 1) launch_tsum_t<1, 2>(a, B, nw, st);
+        else if (T <= 2) launch_tsum_t<2, 2>(a, B, nw, st);
+        else launch_tsum_t<4, 2>(a, B, nw, st);
     }
     if (a.npol > 0 && a.mcount > 0) {
         dim3 grid(a.mcount, a.nn, B);

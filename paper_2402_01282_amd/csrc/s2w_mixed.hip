@@ -25,16 +25,22 @@ __device__ __forceinline__ f4 mfma16(float a, float b, f4 c)
 
 // ------------------------------------------------------------ k_lsum_mm ----
 // C_s[b][ni][m][theta] (complex FP32) = sum_{l >= l0} d^l_mn(theta) w_s[ni][l] flm[b][m][l]
-// grid (m, ni, theta tiles x column groups of 16 NC columns), one wave per block.
+// one wave per block: a 64-theta tile of one (m, n, column group of 16 NC columns).
 
 template <int NS, int NC>
 __global__ __launch_bounds__(64) void k_lsum_mm(const LsumArgs a, const MixOut o)
 {
     constexpr int CW = 16 * NC;        // columns per wave
-    const int m = blockIdx.x, ni = blockIdx.y;
     const int L = a.L;
     const int ntt = (L + 63) >> 6;
-    const int tt = blockIdx.z % ntt, g = blockIdx.z / ntt;
+    // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so the ntt theta
+    // tiles of one (m, n, column group) unit get consecutive slots on one XCD and share
+    // its L2 for the unit's coefficient rows and recursion tables
+    const int nunit = a.mcount * a.nn * ((2 * o.B * NS + CW - 1) / CW);
+    const int bid = blockIdx.x, xcd = bid & 7, kx = bid >> 3;
+    const int tt = kx % ntt, unit = (kx / ntt) * 8 + xcd;
+    if (unit >= nunit) return;
+    const int m = unit % a.mcount, ni = (unit / a.mcount) % a.nn, g = unit / (a.mcount * a.nn);
     const int lane = threadIdx.x;
     const int n = a.nval[ni], ng = a.nglob[ni];
     const int an = n < 0 ? -n : n;
@@ -288,7 +294,8 @@ static void launch_lsum_mm_t(const LsumArgs &a, const MixOut &o, int NS, hipStre
 {
     const int ntt = (a.L + 63) / 64;
     const int ngrp = (2 * o.B * NS + 16 * NC - 1) / (16 * NC);
-    dim3 grid(a.mcount, a.nn, ntt * ngrp);
+    const long nunit = (long)a.mcount * a.nn * ngrp;
+    dim3 grid((unsigned)(8L * ntt * ((nunit + 7) / 8)));
     if (NS == 1) hipLaunchKernelGGL((k_lsum_mm<1, NC>), grid, dim3(64), 0, st, a, o);
     else hipLaunchKernelGGL((k_lsum_mm<2, NC>), grid, dim3(64), 0, st, a, o);
 }
