@@ -269,6 +269,13 @@ DftArgs dft_args(const DevGrid &g, const void *in, long istride, void *out, long
     a.w1 = g.dft.w1;
     a.w2 = g.dft.w2;
     a.scale = scale;
+    // modular inverses for the index maps: input index x sits at position m1 n2 + m2 with
+    // m1 = x n2^-1 mod n1, m2 = x n1^-1 mod n2; output frequency k at (k mod n1) n2 + k mod n2
+    a.inv21 = a.inv12 = 0;
+    for (int v = 1; v < a.n1; ++v)
+        if ((long)v * a.n2 % a.n1 == 1) { a.inv21 = v; break; }
+    for (int v = 1; v < a.n2; ++v)
+        if ((long)v * a.n1 % a.n2 == 1) { a.inv12 = v; break; }
     return a;
 }
 
@@ -293,7 +300,7 @@ LsumArgs lsum_args(s2w_plan p, const DevGrid &g, int mcount, const std::vector<i
         auto it = p->tile_lsum.find(g.L);
         a.tileT = it == p->tile_lsum.end() ? 0 : it->second;
         auto jt = p->tile_lsum_mm.find(g.L);
-        a.tileNC = jt == p->tile_lsum_mm.end() ? 0 : jt->second;
+        a.tileW = jt == p->tile_lsum_mm.end() ? 0 : jt->second;
     }
     a.A = p->A;
     a.B = p->Bt;
@@ -537,12 +544,13 @@ void autotune(s2w_plan p)
             la.out[s] = p->bufA + s * cstride;
             mo.out[s] = (float *)p->bufA + s * cstride;
         }
-        const std::vector<int> cands = mixed ? std::vector<int>{1, 2, 4} : std::vector<int>{1, 2, 4, 8};
+        // candidates that all give the same sums in the same order (only the work split differs)
+        const std::vector<int> cands = mixed ? std::vector<int>{2, 4} : std::vector<int>{1, 2, 4, 8};
         int best = 0;
         float best_ms = 0.0f;
         for (int c : cands) {
             auto launch = [&]() {
-                if (mixed) { la.tileNC = c; s2w::launch_lsum_mm(la, mo, NS, nullptr); }
+                if (mixed) { la.tileW = c; s2w::launch_lsum_mm(la, mo, NS, nullptr); }
                 else { la.tileT = c; s2w::launch_lsum(la, NS, B, nullptr); }
             };
             launch();

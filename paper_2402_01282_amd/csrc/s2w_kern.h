@@ -31,7 +31,7 @@ struct LsumArgs {
     int wstride;
     double *out[MAX_NS];         // [B][nn][mcount][L] complex
     int tileT;                   // theta samples per lane of k_lsum (1, 2, 4, 8; 0: default)
-    int tileNC;                  // 16-column MFMA tiles per wave of k_lsum_mm (1, 2, 4; 0: default)
+    int tileW;                   // waves per block of k_lsum_mm (1, 2, 4; 0: default)
 };
 
 // sum over theta (reduction across lanes)
@@ -66,6 +66,7 @@ struct DftArgs {
     double scale;
     int rpb;                     // row pairs per block (set by the launcher)
     int inplace;                 // stages overwrite their input (set by the launcher)
+    int inv21, inv12;            // n2^-1 mod n1 and n1^-1 mod n2 (0 for a factor of 1)
 };
 
 struct GammaArgs {

@@ -997,92 +997,158 @@ __global__ __launch_bounds__(128) void k_dft_r2c_direct(const DftArgs a)
 
 // --------------------------------------------------------- gamma stages ----
 //
-// c2r side: E[b][g][theta][m] = ph * fm(m) * sum_ni C[b][ni][m][theta] e^{+i n_ni gamma_g} (complex)
-// 16 x 16 (m, theta) tiles through LDS.
+// Both sides transpose (m, theta) tiles through LDS.  Every global load of a tile is
+// issued before the first is used (the n and gamma loops are unrolled to their
+// maxima and predicated), so a block keeps its whole tile in flight, and the
+// twiddles e^{+-i n gamma_g} are staged once per block in LDS.
 
-template <typename Tr>
+constexpr int GAMMA_MAXG = 2 * GAMMA_MAXN - 1;
+
+template <typename Tr, int NN, int NG>
+__device__ __forceinline__ void gamma_twiddles(const GammaArgs &a, typename V2<Tr>::t (*tw)[NG])
+{
+    const int tid = threadIdx.x;
+    if (tid < NN * NG) {
+        const int ni = tid / NG, g = tid % NG;
+        Tr c = 0, sn = 0;
+        if (ni < a.nn && g < a.ng) {
+            int idx = (a.nval[ni] * g) % a.ng;
+            if (idx < 0) idx += a.ng;
+            c = (Tr)a.tw[2 * idx];
+            sn = (Tr)(a.sgn * a.tw[2 * idx + 1]);
+        }
+        tw[ni][g] = mk2<Tr>(c, sn);
+    }
+}
+
+// c2r side: E[b][g][theta][m] = ph * fm(m) * sum_ni C[b][ni][m][theta] e^{+i n_ni gamma_g} (complex)
+// TM x TT (m x theta) tile per block: loaded theta-fastest, written m-fastest.
+template <typename Tr, int TM, int TT, int NN, int NG>
 __global__ __launch_bounds__(256) void k_gamma_c2r(const GammaArgs a)
 {
     typedef typename V2<Tr>::t C2;
-    __shared__ C2 tile[GAMMA_MAXN][16][17];
+    constexpr int EPT = TM * TT / 256;
+    __shared__ C2 tile[NN][TM][TT + 1];
+    __shared__ C2 tw[NN][NG];
     const int tid = threadIdx.x;
-    const int m0 = blockIdx.x * 16, th0 = blockIdx.y * 16, b = blockIdx.z;
+    const int m0 = blockIdx.x * TM, th0 = blockIdx.y * TT, b = blockIdx.z;
     const C2 *src = reinterpret_cast<const C2 *>(a.src);
+    gamma_twiddles<Tr, NN, NG>(a, tw);
     {
-        const int tt = tid % 16, tm = tid / 16;
-        const int m = m0 + tm, th = th0 + tt;
-        for (int ni = 0; ni < a.nn; ++ni) {
-            C2 v = mk2<Tr>(0, 0);
-            if (m < a.M && th < a.L) v = src[(((size_t)b * a.nn + ni) * a.M + m) * a.L + th];
-            tile[ni][tm][tt] = v;
+        C2 v[EPT][NN];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int idx = tid + 256 * e, tt = idx % TT, tm = idx / TT;
+            const int m = m0 + tm, th = th0 + tt;
+            const bool ok = m < a.M && th < a.L;
+#pragma unroll
+            for (int ni = 0; ni < NN; ++ni)
+                v[e][ni] = (ok && ni < a.nn) ? src[(((size_t)b * a.nn + ni) * a.M + m) * a.L + th] : mk2<Tr>(0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int idx = tid + 256 * e, tt = idx % TT, tm = idx / TT;
+#pragma unroll
+            for (int ni = 0; ni < NN; ++ni) tile[ni][tm][tt] = v[e][ni];
         }
     }
     __syncthreads();
-    const int tm = tid % 16, tt = tid / 16;
-    const int m = m0 + tm, th = th0 + tt;
-    if (m >= a.M || th >= a.L) return;
-    const Tr fm = (Tr)((m == 0) ? a.fm0 : a.fm1) * (Tr)a.wscale;
     const Tr phr = (Tr)a.phr, phi = (Tr)a.phi;
-    for (int g = 0; g < a.ng; ++g) {
-        Tr re = 0, im = 0;
-        for (int ni = 0; ni < a.nn; ++ni) {
-            int idx = (a.nval[ni] * g) % a.ng;
-            if (idx < 0) idx += a.ng;
-            const Tr cw = (Tr)a.tw[2 * idx], sw = (Tr)(a.sgn * a.tw[2 * idx + 1]);
-            const C2 v = tile[ni][tm][tt];
-            re += v.x * cw - v.y * sw;
-            im += v.x * sw + v.y * cw;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int idx = tid + 256 * e, tm = idx % TM, tt = idx / TM;
+        const int m = m0 + tm, th = th0 + tt;
+        if (m >= a.M || th >= a.L) continue;
+        C2 x[NN];
+#pragma unroll
+        for (int ni = 0; ni < NN; ++ni) x[ni] = tile[ni][tm][tt];
+        const Tr fm = (Tr)((m == 0) ? a.fm0 : a.fm1) * (Tr)a.wscale;
+        C2 *dst = reinterpret_cast<C2 *>(a.dst) + ((size_t)b * a.ng * a.L + th) * a.Mout + m;
+        for (int g = 0; g < a.ng; ++g) {
+            Tr re = 0, im = 0;
+#pragma unroll
+            for (int ni = 0; ni < NN; ++ni) {
+                const C2 w = tw[ni][g];
+                re += x[ni].x * w.x - x[ni].y * w.y;
+                im += x[ni].x * w.y + x[ni].y * w.x;
+            }
+            dst[(size_t)g * a.L * a.Mout] = mk2<Tr>(fm * (phr * re - phi * im), fm * (phr * im + phi * re));
         }
-        reinterpret_cast<C2 *>(a.dst)[(((size_t)b * a.ng + g) * a.L + th) * a.Mout + m] =
-            mk2<Tr>(fm * (phr * re - phi * im), fm * (phr * im + phi * re));
     }
 }
 
 // r2c side: F[sig][b][m'][ni][c][theta] = w * fm(m) * ph * sum_g X[b][g][theta][m] e^{-i n_ni gamma_g}
-template <typename Tr>
+// TM x TT tile per block: loaded m-fastest, written theta-fastest.
+template <typename Tr, int TM, int TT, int NN, int NG>
 __global__ __launch_bounds__(256) void k_gamma_r2c(const GammaArgs a)
 {
     typedef typename V2<Tr>::t C2;
-    __shared__ Tr tile[GAMMA_MAXN][2][16][17];
+    constexpr int EPT = TM * TT / 256;
+    __shared__ Tr tile[NN][2][TM][TT + 1];
+    __shared__ C2 tw[NN][NG];
     const int tid = threadIdx.x;
-    const int m0 = blockIdx.x * 16, th0 = blockIdx.y * 16, b = blockIdx.z;
+    const int m0 = blockIdx.x * TM, th0 = blockIdx.y * TT, b = blockIdx.z;
     const C2 *src = reinterpret_cast<const C2 *>(a.src);
     Tr *dst = reinterpret_cast<Tr *>(a.dst);
-    {
-        const int tm = tid % 16, tt = tid / 16;
+    gamma_twiddles<Tr, NN, NG>(a, tw);
+    C2 x[EPT][NG];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int idx = tid + 256 * e, tm = idx % TM, tt = idx / TM;
         const int m = m0 + tm, th = th0 + tt;
-        Tr accr[GAMMA_MAXN], acci[GAMMA_MAXN];
-        for (int ni = 0; ni < a.nn; ++ni) { accr[ni] = 0; acci[ni] = 0; }
-        if (m < a.M && th < a.L) {
-            for (int g = 0; g < a.ng; ++g) {
-                const C2 v = src[(((size_t)b * a.ng + g) * a.L + th) * a.Min + m];
-                for (int ni = 0; ni < a.nn; ++ni) {
-                    int idx = (a.nval[ni] * g) % a.ng;
-                    if (idx < 0) idx += a.ng;
-                    const Tr cw = (Tr)a.tw[2 * idx], sw = (Tr)(a.sgn * a.tw[2 * idx + 1]);
-                    accr[ni] += v.x * cw - v.y * sw;
-                    acci[ni] += v.x * sw + v.y * cw;
-                }
+        const bool ok = m < a.M && th < a.L;
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+            x[e][g] = (ok && g < a.ng) ? src[(((size_t)b * a.ng + g) * a.L + th) * a.Min + m] : mk2<Tr>(0, 0);
+    }
+    __syncthreads();
+    const Tr phr = (Tr)a.phr, phi = (Tr)a.phi;
+    // gamma outermost: one sample's twiddles are live at a time
+    Tr ar[EPT][NN], ai[EPT][NN];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e)
+#pragma unroll
+        for (int ni = 0; ni < NN; ++ni) { ar[e][ni] = 0; ai[e][ni] = 0; }
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        C2 w[NN];
+#pragma unroll
+        for (int ni = 0; ni < NN; ++ni) w[ni] = tw[ni][g];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e)
+#pragma unroll
+            for (int ni = 0; ni < NN; ++ni) {
+                ar[e][ni] += x[e][g].x * w[ni].x - x[e][g].y * w[ni].y;
+                ai[e][ni] += x[e][g].x * w[ni].y + x[e][g].y * w[ni].x;
             }
-        }
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int idx = tid + 256 * e, tm = idx % TM, tt = idx / TM;
+        const int m = m0 + tm;
         const Tr fm = (Tr)((m == 0) ? a.fm0 : a.fm1) * (Tr)a.wscale;
-        const Tr phr = (Tr)a.phr, phi = (Tr)a.phi;
-        for (int ni = 0; ni < a.nn; ++ni) {
-            tile[ni][0][tm][tt] = fm * (phr * accr[ni] - phi * acci[ni]);
-            tile[ni][1][tm][tt] = fm * (phr * acci[ni] + phi * accr[ni]);
+#pragma unroll
+        for (int ni = 0; ni < NN; ++ni) {
+            tile[ni][0][tm][tt] = fm * (phr * ar[e][ni] - phi * ai[e][ni]);
+            tile[ni][1][tm][tt] = fm * (phr * ai[e][ni] + phi * ar[e][ni]);
         }
     }
     __syncthreads();
-    const int tt = tid % 16, tm = tid / 16;
-    const int m = m0 + tm, th = th0 + tt;
-    if (m >= a.M || th >= a.L) return;
-    const int sig = (m + a.npar) & 1;
-    const int mp = m >> 1;
-    const size_t base = (sig == 0 ? 0 : (size_t)a.B * a.M0 * a.nn * 2)
-                        + (((size_t)b * (sig == 0 ? a.M0 : a.M1) + mp) * a.nn) * 2;
-    for (int ni = 0; ni < a.nn; ++ni) {
-        dst[(base + (size_t)ni * 2 + 0) * a.L + th] = tile[ni][0][tm][tt];
-        dst[(base + (size_t)ni * 2 + 1) * a.L + th] = tile[ni][1][tm][tt];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int idx = tid + 256 * e, tt = idx % TT, tm = idx / TT;
+        const int m = m0 + tm, th = th0 + tt;
+        if (m >= a.M || th >= a.L) continue;
+        const int sig = (m + a.npar) & 1;
+        const int mp = m >> 1;
+        const size_t base = (sig == 0 ? 0 : (size_t)a.B * a.M0 * a.nn * 2)
+                            + (((size_t)b * (sig == 0 ? a.M0 : a.M1) + mp) * a.nn) * 2;
+#pragma unroll
+        for (int ni = 0; ni < NN; ++ni) {
+            if (ni >= a.nn) break;
+            dst[(base + (size_t)ni * 2 + 0) * a.L + th] = tile[ni][0][tm][tt];
+            dst[(base + (size_t)ni * 2 + 1) * a.L + th] = tile[ni][1][tm][tt];
+        }
     }
 }
 
@@ -1363,18 +1429,36 @@ void launch_dft_r2c(DftArgs a, hipStream_t st, bool f32, bool in64, bool in32)
         hipLaunchKernelGGL((k_dft_r2c<double, double>), grid, dim3(thr), lds, st, a);
 }
 
+// tiles: FP32 c2r 32 m x 16 theta (256-byte row segments on the larger, written side),
+// FP32 r2c 16 m x 32 theta, FP64 16 x 16; each about 35 KB of LDS
 void launch_gamma_c2r(const GammaArgs &a, hipStream_t st, bool f32)
 {
-    dim3 grid((a.M + 15) / 16, (a.L + 15) / 16, a.B);
-    if (f32) hipLaunchKernelGGL(k_gamma_c2r<float>, grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(k_gamma_c2r<double>, grid, dim3(256), 0, st, a);
+    // the loops over n and gamma are unrolled to NN, NG; nn = ng = 1 (harmonic transforms)
+    // has its own instantiation
+    const bool one = a.nn == 1 && a.ng == 1;
+    if (f32) {
+        dim3 grid((a.M + 31) / 32, (a.L + 15) / 16, a.B);
+        if (one) hipLaunchKernelGGL((k_gamma_c2r<float, 32, 16, 1, 1>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_gamma_c2r<float, 32, 16, GAMMA_MAXN, GAMMA_MAXG>), grid, dim3(256), 0, st, a);
+    } else {
+        dim3 grid((a.M + 15) / 16, (a.L + 15) / 16, a.B);
+        if (one) hipLaunchKernelGGL((k_gamma_c2r<double, 16, 16, 1, 1>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_gamma_c2r<double, 16, 16, GAMMA_MAXN, GAMMA_MAXG>), grid, dim3(256), 0, st, a);
+    }
 }
 
 void launch_gamma_r2c(const GammaArgs &a, hipStream_t st, bool f32)
 {
-    dim3 grid((a.M + 15) / 16, (a.L + 15) / 16, a.B);
-    if (f32) hipLaunchKernelGGL(k_gamma_r2c<float>, grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(k_gamma_r2c<double>, grid, dim3(256), 0, st, a);
+    const bool one = a.nn == 1 && a.ng == 1;
+    if (f32) {
+        dim3 grid((a.M + 15) / 16, (a.L + 31) / 32, a.B);
+        if (one) hipLaunchKernelGGL((k_gamma_r2c<float, 16, 32, 1, 1>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_gamma_r2c<float, 16, 32, GAMMA_MAXN, GAMMA_MAXG>), grid, dim3(256), 0, st, a);
+    } else {
+        dim3 grid((a.M + 15) / 16, (a.L + 15) / 16, a.B);
+        if (one) hipLaunchKernelGGL((k_gamma_r2c<double, 16, 16, 1, 1>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_gamma_r2c<double, 16, 16, GAMMA_MAXN, GAMMA_MAXG>), grid, dim3(256), 0, st, a);
+    }
 }
 
 void launch_convert(const void *in, void *out, size_t n, bool to_f32, hipStream_t st)

@@ -4,9 +4,10 @@
 // start, same tables as the FP64 kernels) and is shared by every map of the
 // batch; d is rounded to FP32 in chunks of 16 degrees, staged in LDS, and
 // contracted on FP32 matrix cores (16x16x4 MFMA) against coefficient tiles of
-// 64 columns, a column being (scale, map, real/imaginary part).  Partial sums
-// are promoted to FP64: every 64 degrees for the sum over l, and in the
-// fixed-order cross-wave reduction for the sum over theta.
+// 64 columns, a column being (scale, map, real/imaginary part).  The sum over l
+// is carried from the matrix-core accumulator into a second FP32 accumulator
+// every 64 degrees; the sum over theta is completed in FP64 in a fixed-order
+// cross-wave reduction.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -25,33 +26,37 @@ __device__ __forceinline__ f4 mfma16(float a, float b, f4 c)
 
 // ------------------------------------------------------------ k_lsum_mm ----
 // C_s[b][ni][m][theta] (complex FP32) = sum_{l >= l0} d^l_mn(theta) w_s[ni][l] flm[b][m][l]
-// one wave per block: a 64-theta tile of one (m, n, column group of 16 NC columns).
+// W waves per block: wave w owns the 64-theta tile
+// (tb W + w) of one (m, n, group of 64 columns) unit, and the waves share one staged
+// 16-degree x 64-column coefficient tile per chunk.  The coefficient loads for the next
+// chunk are issued before the current chunk's recursion and matrix-core work, as
+// 16-byte (re, im) pairs.  Sums over l accumulate in FP32 on the matrix cores and are
+// carried into a second FP32 accumulator every 64 degrees.
 
-template <int NS, int NC>
-__global__ __launch_bounds__(64) void k_lsum_mm(const LsumArgs a, const MixOut o)
+template <int NS, int W>
+__global__ __launch_bounds__(64 * W) void k_lsum_mm(const LsumArgs a, const MixOut o)
 {
-    constexpr int CW = 16 * NC;        // columns per wave
+    constexpr int R = 4 / W;           // staging slots per thread
     const int L = a.L;
     const int ntt = (L + 63) >> 6;
-    // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so the ntt theta
-    // tiles of one (m, n, column group) unit get consecutive slots on one XCD and share
-    // its L2 for the unit's coefficient rows and recursion tables
-    const int nunit = a.mcount * a.nn * ((2 * o.B * NS + CW - 1) / CW);
+    const int ntb = (ntt + W - 1) / W;
+    const int B = o.B, ncols = 2 * B * NS;
+    const int ngrp = (ncols + 63) >> 6;
+    const int nunit = a.mcount * a.nn * ngrp;
+    // XCD-aware order: the ntb theta blocks of one unit get consecutive slots on one XCD
     const int bid = blockIdx.x, xcd = bid & 7, kx = bid >> 3;
-    const int tt = kx % ntt, unit = (kx / ntt) * 8 + xcd;
+    const int tb = kx % ntb, unit = (kx / ntb) * 8 + xcd;
     if (unit >= nunit) return;
     const int m = unit % a.mcount, ni = (unit / a.mcount) % a.nn, g = unit / (a.mcount * a.nn);
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int n = a.nval[ni], ng = a.nglob[ni];
     const int an = n < 0 ? -n : n;
     const int l0 = m > an ? m : an;
-    const int B = o.B, ncols = 2 * B * NS;
-    const int th = tt * 64 + lane;
+    const int th = (tb * W + w) * 64 + lane;
     const bool valid = th < L;
 
-    __shared__ float Ds[16][64 + 4];
-    __shared__ float Us[16][CW + 4];
-    __shared__ float Ot[CW][64 + 1];
+    __shared__ float Ds[W][16][64 + 4];   // d chunk of each wave [l][theta]; output staging at the end
+    __shared__ float Us[16][64 + 4];         // coefficient chunk [l][column]
 
     const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
     double c = 0.0, cl = 0.0, e = 0.0, ep = 0.0;
@@ -64,48 +69,69 @@ __global__ __launch_bounds__(64) void k_lsum_mm(const LsumArgs a, const MixOut o
         start_value(a.smant[(size_t)ng * a.Lrec + m], a.sexp[(size_t)ng * a.Lrec + m], p1, p2, a.ch[th],
                     a.sh[th], a.ceps[th], a.seps[th], e, k);
     }
-    f4 acc[4][NC];
-    double accd[4][NC][4];
+
+    // staging: slot q = tid + 64 W r (r < R) of the 32 column pairs x 8 degree pairs of a
+    // chunk is column pair p = q / 8 (re, im of one map and scale), degrees lb + iq, lb + iq + 1
+    int iq[R], pc[R];
+    bool cok[R];
+    const double *wv[R];
+    const double2 *fl[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int q = tid + 64 * W * r;
+        pc[r] = q >> 3;
+        iq[r] = (q & 7) * 2;
+        const int cg = g * 64 + 2 * pc[r];
+        cok[r] = cg < ncols;
+        int cs = 0, cb = 0;
+        if (cok[r]) {
+            cs = cg / (2 * B);
+            cb = (cg - cs * 2 * B) >> 1;
+        }
+        wv[r] = a.w[cs < NS ? cs : 0] + (size_t)ni * a.wstride;
+        fl[r] = reinterpret_cast<const double2 *>(a.flm) + ((size_t)cb * a.flm_m + m) * a.flm_l;
+    }
+    double2 f0[R], f1[R];
+    double w0[R], w1[R];
+    auto fetch = [&](int lb) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int la = lb + iq[r];
+            f0[r] = make_double2(0.0, 0.0);
+            f1[r] = make_double2(0.0, 0.0);
+            w0[r] = 0.0;
+            w1[r] = 0.0;
+            if (cok[r] && la < L) { f0[r] = fl[r][la]; w0[r] = wv[r][la]; }
+            if (cok[r] && la + 1 < L) { f1[r] = fl[r][la + 1]; w1[r] = wv[r][la + 1]; }
+        }
+    };
+    if (l0 < L) fetch(l0);
+
+    f4 acc[4][4], acc2[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < NC; ++j) {
+        for (int j = 0; j < 4; ++j) {
             acc[i][j] = f4{0, 0, 0, 0};
-#pragma unroll
-            for (int r = 0; r < 4; ++r) accd[i][j][r] = 0.0;
+            acc2[i][j] = f4{0, 0, 0, 0};
         }
-
-    // this lane stages column (lane % CW) for degrees i = lane / CW + (64 / CW) * q
-    const int ccol = lane % CW, cpart = lane / CW;
-    constexpr int NPART = 64 / CW;
-    const int cg = g * CW + ccol;
-    int cs = 0, cb = 0, ccc = 0;
-    const bool cok = cg < ncols;
-    if (cok) {
-        cs = cg / (2 * B);
-        const int rem = cg - cs * 2 * B;
-        cb = rem >> 1;
-        ccc = rem & 1;
-    }
-    const double *wv = a.w[cs < NS ? cs : 0] + (size_t)ni * a.wstride;
-    const double *fl = a.flm + ((size_t)cb * a.flm_m + m) * a.flm_l * 2 + ccc;
 
     int chunk = 0;
     for (int lb = l0; lb < L; lb += 16, ++chunk) {
 #pragma unroll
-        for (int q = 0; q < 16 / NPART; ++q) {
-            const int i = cpart + NPART * q;
-            const int l = lb + i;
-            float v = 0.f;
-            if (cok && l < L) v = (float)(wv[l] * fl[(size_t)l * 2]);
-            Us[i][ccol] = v;
+        for (int r = 0; r < R; ++r) {
+            Us[iq[r]][2 * pc[r]] = (float)(w0[r] * f0[r].x);
+            Us[iq[r]][2 * pc[r] + 1] = (float)(w0[r] * f0[r].y);
+            Us[iq[r] + 1][2 * pc[r]] = (float)(w1[r] * f1[r].x);
+            Us[iq[r] + 1][2 * pc[r] + 1] = (float)(w1[r] * f1[r].y);
         }
+        if (lb + 16 < L) fetch(lb + 16);
 #pragma unroll 4
         for (int i = 0; i < 16; ++i) {
             const int l = lb + i;
             double A = 0.0, Bv = 0.0, S = 0.0;
             if (l < L) { A = a.A[tabm + l]; Bv = a.B[tabm + l]; S = a.S[tabm + l]; }
-            Ds[i][lane] = (valid && k == 0) ? (float)(S * e) : 0.f;
+            Ds[w][i][lane] = (valid && k == 0) ? (float)(S * e) : 0.f;
             const double en = fma(fma(A, cl, fma(A, c, -Bv)), e, -ep);
             ep = e;
             e = en;
@@ -118,46 +144,48 @@ __global__ __launch_bounds__(64) void k_lsum_mm(const LsumArgs a, const MixOut o
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 4) {
-            float af[4], bf[NC];
+            float af[4], bf[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) af[i] = Ds[kk + (lane >> 4)][i * 16 + (lane & 15)];
+            for (int i = 0; i < 4; ++i) af[i] = Ds[w][kk + (lane >> 4)][i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < NC; ++j) bf[j] = Us[kk + (lane >> 4)][j * 16 + (lane & 15)];
+            for (int j = 0; j < 4; ++j) bf[j] = Us[kk + (lane >> 4)][j * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < NC; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
+                for (int j = 0; j < 4; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
         }
         __syncthreads();
         if ((chunk & 3) == 3) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < NC; ++j) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) accd[i][j][r] += (double)acc[i][j][r];
+                for (int j = 0; j < 4; ++j) {
+                    acc2[i][j] += acc[i][j];
                     acc[i][j] = f4{0, 0, 0, 0};
                 }
         }
     }
+    // output: one 16-column tile at a time through this wave's Ds slice, then
+    // (re, im) pairs written with theta contiguous
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
 #pragma unroll
-        for (int j = 0; j < NC; ++j)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                Ot[j * 16 + (lane & 15)][i * 16 + 4 * (lane >> 4) + r] = (float)(accd[i][j][r] + (double)acc[i][j][r]);
-    __syncthreads();
-    // write (re, im) pairs with theta contiguous
-    for (int p = 0; p < CW / 2; ++p) {
-        const int cgp = g * CW + 2 * p;
-        if (cgp >= ncols) break;
-        const int s = cgp / (2 * B);
-        const int b = (cgp - s * 2 * B) >> 1;
-        if (valid) {
-            float2 *dst = reinterpret_cast<float2 *>(o.out[s]);
-            dst[(((size_t)b * a.nn + ni) * a.mcount + m) * L + th] = make_float2(Ot[2 * p][lane], Ot[2 * p + 1][lane]);
+                Ds[w][lane & 15][i * 16 + 4 * (lane >> 4) + r] = acc2[i][j][r] + acc[i][j][r];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int cgp = g * 64 + 16 * j + 2 * q;
+            if (cgp < ncols && valid) {
+                const int s = cgp / (2 * B);
+                const int b = (cgp - s * 2 * B) >> 1;
+                float2 *dst = reinterpret_cast<float2 *>(o.out[s]);
+                dst[(((size_t)b * a.nn + ni) * a.mcount + m) * L + th] = make_float2(Ds[w][2 * q][lane], Ds[w][2 * q + 1][lane]);
+            }
         }
+        __syncthreads();
     }
 }
 
@@ -289,22 +317,25 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
 
 // ------------------------------------------------------------- launchers ---
 
-template <int NC>
-static void launch_lsum_mm_t(const LsumArgs &a, const MixOut &o, int NS, hipStream_t st)
-{
-    const int ntt = (a.L + 63) / 64;
-    const int ngrp = (2 * o.B * NS + 16 * NC - 1) / (16 * NC);
-    const long nunit = (long)a.mcount * a.nn * ngrp;
-    dim3 grid((unsigned)(8L * ntt * ((nunit + 7) / 8)));
-    if (NS == 1) hipLaunchKernelGGL((k_lsum_mm<1, NC>), grid, dim3(64), 0, st, a, o);
-    else hipLaunchKernelGGL((k_lsum_mm<2, NC>), grid, dim3(64), 0, st, a, o);
-}
-
 void launch_lsum_mm(const LsumArgs &a, const MixOut &o, int NS, hipStream_t st)
 {
-    if (a.tileNC == 1) launch_lsum_mm_t<1>(a, o, NS, st);
-    else if (a.tileNC == 4) launch_lsum_mm_t<4>(a, o, NS, st);
-    else launch_lsum_mm_t<2>(a, o, NS, st);
+    const int ntt = (a.L + 63) / 64;
+    int W = a.tileW == 1 || a.tileW == 2 || a.tileW == 4 ? a.tileW : 4;
+    if (W > ntt) W = ntt < 2 ? 1 : (ntt < 4 ? 2 : 4);
+    const int ntb = (ntt + W - 1) / W;
+    const int ngrp = (2 * o.B * NS + 63) / 64;
+    const long nunit = (long)a.mcount * a.nn * ngrp;
+    dim3 grid((unsigned)(8L * ntb * ((nunit + 7) / 8)));
+    const dim3 blk(64 * W);
+    if (NS == 1) {
+        if (W == 1) hipLaunchKernelGGL((k_lsum_mm<1, 1>), grid, blk, 0, st, a, o);
+        else if (W == 2) hipLaunchKernelGGL((k_lsum_mm<1, 2>), grid, blk, 0, st, a, o);
+        else hipLaunchKernelGGL((k_lsum_mm<1, 4>), grid, blk, 0, st, a, o);
+    } else {
+        if (W == 1) hipLaunchKernelGGL((k_lsum_mm<2, 1>), grid, blk, 0, st, a, o);
+        else if (W == 2) hipLaunchKernelGGL((k_lsum_mm<2, 2>), grid, blk, 0, st, a, o);
+        else hipLaunchKernelGGL((k_lsum_mm<2, 4>), grid, blk, 0, st, a, o);
+    }
 }
 
 void launch_tsum_mm(const TsumArgs &a, const MixIn &in, int NS, hipStream_t st)
@@ -341,21 +372,28 @@ __device__ __attribute__((always_inline)) inline void dft_mm_stage(float2 *Z, co
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int h = (p - 1) / 2, mt = (h + 16) / 16, ks = (h + 4) / 4;
     float fc[DMM_MT][DMM_KS], fs[DMM_MT][DMM_KS];
-    // fragments: lane holds C[16 i + lane % 16][4 s + lane / 16]
+    // fragments: lane holds C[16 i + lane % 16][4 s + lane / 16]; the table index
+    // j k mod p advances by 4 j mod p from one k step to the next
 #pragma unroll
-    for (int i = 0; i < DMM_MT; ++i)
+    for (int i = 0; i < DMM_MT; ++i) {
+        const int j = 16 * i + (lane & 15);
+        int jk = (j * (lane >> 4)) % p;
+        const int step = (4 * j) % p;
 #pragma unroll
         for (int s = 0; s < DMM_KS; ++s) {
-            const int j = 16 * i + (lane & 15), k = 4 * s + (lane >> 4);
+            const int k = 4 * s + (lane >> 4);
             float cv = 0.f, sv = 0.f;
             if (i < mt && s < ks && j <= h && k <= h) {
-                const float2 t = tw[(j * k) % p];
+                const float2 t = tw[jk];
                 cv = t.x;
                 sv = t.y;
             }
             fc[i][s] = cv;
             fs[i][s] = sv;
+            jk += step;
+            if (jk >= p) jk -= p;
         }
+    }
     float *Zf = reinterpret_cast<float *>(Z);
     const int ncol = 2 * R * q, ntile = (ncol + 15) / 16;
     for (int tile = w; tile < ntile; tile += nw) {
@@ -426,35 +464,86 @@ __global__ __launch_bounds__(256) void k_dft_mm(const DftArgs a)
         tw1[i] = make_float2((float)t.x, (float)t.y);
     }
     const long pair0 = (long)blockIdx.x * R;
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int n1 = a.n1, n2 = a.n2;
+    // index maps stepped in registers (tid + NT t for t = 0, 1, ...): input index x sits at
+    // position m1 n2 + m2 (m1 = x n2^-1 mod n1, m2 = x n1^-1 mod n2); output frequency k
+    // at (k mod n1) n2 + (k mod n2); -x has the negated residues
+    const int d1 = (int)((long)NT * a.inv21 % n1), d2 = (int)((long)NT * a.inv12 % n2);
+    const int e1 = NT % n1, e2 = NT % n2;
+    constexpr int U = 4;
     if (DIR > 0) {
         const float sc = (float)a.scale;
-        for (int idx = threadIdx.x; idx < R * Lh; idx += blockDim.x) {
-            const int s = idx / Lh, mm = idx - s * Lh;
-            const long r1 = 2 * (pair0 + s);
-            float2 *Zs = Z + (size_t)s * n;
-            float2 z1 = make_float2(0.f, 0.f), z2 = make_float2(0.f, 0.f);
-            if (r1 < a.nrows) {
-                z1 = reinterpret_cast<const float2 *>(a.in)[r1 * a.istride + mm];
-                if (r1 + 1 < a.nrows) z2 = reinterpret_cast<const float2 *>(a.in)[(r1 + 1) * a.istride + mm];
+        int m1 = (int)((long)tid * a.inv21 % n1), m2 = (int)((long)tid * a.inv12 % n2);
+        for (int mb = 0; mb < Lh; mb += U * NT) {
+            int pos[U], posc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                pos[u] = m1 * n2 + m2;
+                posc[u] = (m1 == 0 ? 0 : n1 - m1) * n2 + (m2 == 0 ? 0 : n2 - m2);
+                m1 += d1;
+                if (m1 >= n1) m1 -= n1;
+                m2 += d2;
+                if (m2 >= n2) m2 -= n2;
             }
-            if (mm == 0) {
-                Zs[a.inpos[0]] = make_float2(sc * z1.x, sc * z2.x);
-            } else {
-                Zs[a.inpos[mm]] = make_float2(sc * (z1.x - z2.y), sc * (z1.y + z2.x));
-                Zs[a.inpos[n - mm]] = make_float2(sc * (z1.x + z2.y), sc * (z2.x - z1.y));
+            for (int s = 0; s < R; ++s) {
+                const long r1 = 2 * (pair0 + s);
+                const float2 *in1 = reinterpret_cast<const float2 *>(a.in) + r1 * a.istride;
+                float2 z1[U], z2[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int mm = mb + tid + NT * u;
+                    z1[u] = make_float2(0.f, 0.f);
+                    z2[u] = make_float2(0.f, 0.f);
+                    if (mm < Lh && r1 < a.nrows) {
+                        z1[u] = in1[mm];
+                        if (r1 + 1 < a.nrows) z2[u] = in1[a.istride + mm];
+                    }
+                }
+                float2 *Zs = Z + (size_t)s * n;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int mm = mb + tid + NT * u;
+                    if (mm >= Lh) continue;
+                    if (mm == 0) {
+                        Zs[0] = make_float2(sc * z1[u].x, sc * z2[u].x);
+                    } else {
+                        Zs[pos[u]] = make_float2(sc * (z1[u].x - z2[u].y), sc * (z1[u].y + z2[u].x));
+                        Zs[posc[u]] = make_float2(sc * (z1[u].x + z2[u].y), sc * (z2[u].x - z1[u].y));
+                    }
+                }
             }
         }
     } else {
-        for (int idx = threadIdx.x; idx < R * n; idx += blockDim.x) {
-            const int s = idx / n, mm = idx - s * n;
-            const long r1 = 2 * (pair0 + s);
-            float x1 = 0.f, x2 = 0.f;
-            if (r1 < a.nrows) {
-                const Tin *x = reinterpret_cast<const Tin *>(a.in);
-                x1 = (float)x[r1 * a.istride + mm];
-                if (r1 + 1 < a.nrows) x2 = (float)x[(r1 + 1) * a.istride + mm];
+        int m1 = (int)((long)tid * a.inv21 % n1), m2 = (int)((long)tid * a.inv12 % n2);
+        for (int xb = 0; xb < n; xb += U * NT) {
+            int pos[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                pos[u] = m1 * n2 + m2;
+                m1 += d1;
+                if (m1 >= n1) m1 -= n1;
+                m2 += d2;
+                if (m2 >= n2) m2 -= n2;
             }
-            Z[(size_t)s * n + a.inpos[mm]] = make_float2(x1, x2);
+            for (int s = 0; s < R; ++s) {
+                const long r1 = 2 * (pair0 + s);
+                const Tin *x = reinterpret_cast<const Tin *>(a.in) + r1 * a.istride;
+                float x1[U], x2[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int xi = xb + tid + NT * u;
+                    x1[u] = 0.f;
+                    x2[u] = 0.f;
+                    if (xi < n && r1 < a.nrows) {
+                        x1[u] = (float)x[xi];
+                        if (r1 + 1 < a.nrows) x2[u] = (float)x[a.istride + xi];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (xb + tid + NT * u < n) Z[(size_t)s * n + pos[u]] = make_float2(x1[u], x2[u]);
+            }
         }
     }
     __syncthreads();
@@ -463,27 +552,61 @@ __global__ __launch_bounds__(256) void k_dft_mm(const DftArgs a)
     __syncthreads();
     dft_mm_stage(Z, tw2, n, R, a.n2, a.n1, 1, a.n2, sgn);
     __syncthreads();
+    int k1 = tid % n1, k2 = tid % n2;
     if (DIR > 0) {
-        for (int idx = threadIdx.x; idx < R * n; idx += blockDim.x) {
-            const int s = idx / n, aa = idx - s * n;
-            const long r1 = 2 * (pair0 + s);
-            if (r1 >= a.nrows) continue;
-            const float2 z = Z[(size_t)s * n + a.outpos[aa]];
-            reinterpret_cast<float *>(a.out)[r1 * a.ostride + aa] = z.x;
-            if (r1 + 1 < a.nrows) reinterpret_cast<float *>(a.out)[(r1 + 1) * a.ostride + aa] = z.y;
+        for (int ab = 0; ab < n; ab += U * NT) {
+            int pos[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                pos[u] = k1 * n2 + k2;
+                k1 += e1;
+                if (k1 >= n1) k1 -= n1;
+                k2 += e2;
+                if (k2 >= n2) k2 -= n2;
+            }
+            for (int s = 0; s < R; ++s) {
+                const long r1 = 2 * (pair0 + s);
+                if (r1 >= a.nrows) break;
+                float *o1 = reinterpret_cast<float *>(a.out) + r1 * a.ostride;
+                const float2 *Zs = Z + (size_t)s * n;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int aa = ab + tid + NT * u;
+                    if (aa >= n) continue;
+                    const float2 z = Zs[pos[u]];
+                    o1[aa] = z.x;
+                    if (r1 + 1 < a.nrows) o1[a.ostride + aa] = z.y;
+                }
+            }
         }
     } else {
         const float hs = (float)(0.5 * a.scale);
-        for (int idx = threadIdx.x; idx < R * Lh; idx += blockDim.x) {
-            const int s = idx / Lh, mm = idx - s * Lh;
-            const long r1 = 2 * (pair0 + s);
-            if (r1 >= a.nrows) continue;
-            const float2 *Zs = Z + (size_t)s * n;
-            const float2 X = Zs[a.outpos[mm]];
-            const float2 Xc = Zs[a.outpos[mm == 0 ? 0 : n - mm]];
-            float2 *O = reinterpret_cast<float2 *>(a.out);
-            O[r1 * a.ostride + mm] = make_float2(hs * (X.x + Xc.x), hs * (X.y - Xc.y));
-            if (r1 + 1 < a.nrows) O[(r1 + 1) * a.ostride + mm] = make_float2(hs * (X.y + Xc.y), -hs * (X.x - Xc.x));
+        for (int mb = 0; mb < Lh; mb += U * NT) {
+            int pos[U], posc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                pos[u] = k1 * n2 + k2;
+                posc[u] = (k1 == 0 ? 0 : n1 - k1) * n2 + (k2 == 0 ? 0 : n2 - k2);
+                k1 += e1;
+                if (k1 >= n1) k1 -= n1;
+                k2 += e2;
+                if (k2 >= n2) k2 -= n2;
+            }
+            for (int s = 0; s < R; ++s) {
+                const long r1 = 2 * (pair0 + s);
+                if (r1 >= a.nrows) break;
+                const float2 *Zs = Z + (size_t)s * n;
+                float2 *O = reinterpret_cast<float2 *>(a.out) + r1 * a.ostride;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int mm = mb + tid + NT * u;
+                    if (mm >= Lh) continue;
+                    const float2 X = Zs[pos[u]];
+                    const float2 Xc = Zs[posc[u]];
+                    O[mm] = make_float2(hs * (X.x + Xc.x), hs * (X.y - Xc.y));
+                    if (r1 + 1 < a.nrows) O[a.ostride + mm] = make_float2(hs * (X.y + Xc.y), -hs * (X.x - Xc.x));
+                }
+            }
         }
     }
 }
