@@ -140,7 +140,8 @@ struct Prof {
 };
 
 // algorithmic flop of a recursion + contraction pass: sum over (m, n) of
-// (L - l0) steps x L theta samples x (6 + 4 NS)
+// (L - l0) steps x L theta samples x (6 for the recursion step, needed once for
+// all maps, + 4 per scale and map for the complex x real multiply-add)
 double rec_flop(int L, int mcount, const std::vector<int> &ns, int NS, int B)
 {
     double steps = 0.0;
@@ -149,7 +150,7 @@ double rec_flop(int L, int mcount, const std::vector<int> &ns, int NS, int B)
             const int l0 = std::max(m, std::abs(n));
             if (l0 < L) steps += (double)(L - l0);
         }
-    return steps * L * (6.0 + 4.0 * NS) * B;
+    return steps * L * (6.0 + 4.0 * NS * B);
 }
 
 double dft_flop(int n, long rows) { return n > 1 ? 2.5 * n * std::log2((double)n) * (double)rows : 0.0; }

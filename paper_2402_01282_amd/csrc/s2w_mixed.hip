@@ -24,6 +24,15 @@ __device__ __forceinline__ f4 mfma16(float a, float b, f4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// lane i's value of v for a wave-uniform lane index i (two scalar moves)
+__device__ __forceinline__ double readlane_d(double v, int i)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), i);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), i);
+    return __hiloint2double(hi, lo);
+}
+
 // ------------------------------------------------------------ k_lsum_mm ----
 // C_s[b][ni][m][theta] (complex FP32) = sum_{l >= l0} d^l_mn(theta) w_s[ni][l] flm[b][m][l]
 // W waves per block: wave w owns the 64-theta tile
@@ -34,7 +43,7 @@ __device__ __forceinline__ f4 mfma16(float a, float b, f4 c)
 // carried into a second FP32 accumulator every 64 degrees.
 
 template <int NS, int W>
-__global__ __launch_bounds__(64 * W) void k_lsum_mm(const LsumArgs a, const MixOut o)
+__global__ __launch_bounds__(64 * W, 2) void k_lsum_mm(const LsumArgs a, const MixOut o)
 {
     constexpr int R = 4 / W;           // staging slots per thread
     const int L = a.L;
@@ -116,8 +125,25 @@ __global__ __launch_bounds__(64 * W) void k_lsum_mm(const LsumArgs a, const MixO
             acc2[i][j] = f4{0, 0, 0, 0};
         }
 
+    // recursion coefficients of a chunk: lane i < 16 holds A, B, S of degree lb + i,
+    // fetched one chunk ahead; each step reads them from that lane
+    double An = 0.0, Bn = 0.0, Sn = 0.0;
+    if (lane < 16 && l0 + lane < L) {
+        An = a.A[tabm + l0 + lane];
+        Bn = a.B[tabm + l0 + lane];
+        Sn = a.S[tabm + l0 + lane];
+    }
     int chunk = 0;
     for (int lb = l0; lb < L; lb += 16, ++chunk) {
+        const double Ac = An, Bc = Bn, Sc = Sn;
+        An = 0.0;
+        Bn = 0.0;
+        Sn = 0.0;
+        if (lane < 16 && lb + 16 + lane < L) {
+            An = a.A[tabm + lb + 16 + lane];
+            Bn = a.B[tabm + lb + 16 + lane];
+            Sn = a.S[tabm + lb + 16 + lane];
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             Us[iq[r]][2 * pc[r]] = (float)(w0[r] * f0[r].x);
@@ -128,9 +154,7 @@ __global__ __launch_bounds__(64 * W) void k_lsum_mm(const LsumArgs a, const MixO
         if (lb + 16 < L) fetch(lb + 16);
 #pragma unroll 4
         for (int i = 0; i < 16; ++i) {
-            const int l = lb + i;
-            double A = 0.0, Bv = 0.0, S = 0.0;
-            if (l < L) { A = a.A[tabm + l]; Bv = a.B[tabm + l]; S = a.S[tabm + l]; }
+            const double A = readlane_d(Ac, i), Bv = readlane_d(Bc, i), S = readlane_d(Sc, i);
             Ds[w][i][lane] = (valid && k == 0) ? (float)(S * e) : 0.f;
             const double en = fma(fma(A, cl, fma(A, c, -Bv)), e, -ep);
             ep = e;
@@ -194,14 +218,30 @@ __global__ __launch_bounds__(64 * W) void k_lsum_mm(const LsumArgs a, const MixO
 // with h rows (FP32) in the sigma-grouped layout [sig][b][m'][ni][c][theta].
 // grid (m, ni, column groups), NW = ceil(L/64) waves per block, wave w owns theta = 64 w + lane.
 // Each wave keeps its 64 x 64 (theta x column) slice of h in registers as MFMA
-// B operands; per chunk of 16 degrees it writes d (FP32) to LDS, forms the
-// 16 x 64 partial product on matrix cores, and the waves' partials are summed
-// in FP64 in a fixed order.
+// B operands; per chunk of 16 degrees it writes d (FP32) to its own LDS slice,
+// forms the 16 x 64 partial product on matrix cores and stores it over that
+// slice, and the waves' partials are summed in FP64 in a fixed order.  The
+// slices alternate between two buffers by chunk parity: a wave orders its own
+// slice with a wave-level fence, and one block barrier per chunk separates the
+// partial products from their sum (the next chunk writes the other buffer, whose
+// last readers finished before this chunk's barrier).
+
+constexpr int TS_RS = 64 * 17;         // floats per wave slice: d [64][16] or partial [64 col][17]
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <int NS>
-__global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn in)
+__global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn in, const double *__restrict__ rA,
+                                                  const double *__restrict__ rB)
 {
-    extern __shared__ float sm[];      // NW x 1024 floats: d chunks, then the partial products
+    // rA, rB alias a.A, a.B_: as restrict arguments they are known not to be written by
+    // this kernel's stores, so their wave-uniform reads become scalar loads
+    extern __shared__ float sm[];      // [2][NW][TS_RS]
     const int m = blockIdx.x, ni = blockIdx.y, g = blockIdx.z;
     const int L = a.L;
     const int NW = blockDim.x >> 6;
@@ -212,7 +252,6 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
     const int B = in.B, ncols = 2 * B * NS;
     const int th = w * 64 + lane;
     const bool valid = th < L;
-    float *Dw = sm + (size_t)w * 1024;
 
     // h slice: hb[ks][j] = h[theta = 64 w + 4 ks + lane / 16][col = 64 g + 16 j + lane % 16]
     const int sig = (m + a.npar) & 1;
@@ -252,14 +291,26 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
                     a.sh[th], a.ceps[th], a.seps[th], e, k);
     }
 
-    for (int lb = l0; lb < L; lb += 16) {
+    int par = 0;
+    for (int lb = l0; lb < L; lb += 16, par ^= 1) {
+        float *Dw = sm + (size_t)(par * NW + w) * TS_RS;
+        // scale factors of this thread's first output of the chunk, loaded before the
+        // chunk's recursion and matrix-core work so that their latency is hidden
+        double s0 = 0.0, w0 = 0.0;
+        {
+            const int t = threadIdx.x, col = 2 * (t >> 5) + (t & 1), l = lb + ((t >> 1) & 15), cg = g * 64 + col;
+            if (t < 1024 && l < L && cg < ncols) {
+                s0 = a.S[tabm + l];
+                w0 = a.w[cg / (2 * B)][(size_t)ni * a.wstride + l];
+            }
+        }
         // d chunk, swizzled [theta][l ^ (theta & 15)] so that both the per-step writes and the
         // MFMA A-operand reads avoid bank conflicts
 #pragma unroll 4
         for (int i = 0; i < 16; ++i) {
             const int l = lb + i;
             double A = 0.0, Bv = 0.0;
-            if (l < L) { A = a.A[tabm + l]; Bv = a.B_[tabm + l]; }
+            if (l < L) { A = rA[tabm + l]; Bv = rB[tabm + l]; }
             Dw[lane * 16 + (i ^ (lane & 15))] = (valid && k == 0) ? (float)e : 0.f;
             const double en = fma(fma(A, cl, fma(A, c, -Bv)), e, -ep);
             ep = e;
@@ -270,7 +321,7 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
                 k += 1;
             }
         }
-        __syncthreads();
+        wave_lds_sync();
         f4 pacc[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) pacc[j] = f4{0, 0, 0, 0};
@@ -281,27 +332,29 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
 #pragma unroll
             for (int j = 0; j < 4; ++j) pacc[j] = mfma16(av, hb[ks][j], pacc[j]);
         }
-        __syncthreads();
-        // partial 16 (l) x 64 (col) of this wave: register r of lane -> l = 4 (lane/16) + r, col = 16 j + lane%16
+        wave_lds_sync();
+        // partial 16 (l) x 64 (col) of this wave, stored [col][l] (stride 17): register r of
+        // lane -> l = 4 (lane/16) + r, col = 16 j + lane%16
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) Dw[(4 * (lane >> 4) + r) * 64 + 16 * j + (lane & 15)] = pacc[j][r];
+            for (int r = 0; r < 4; ++r) Dw[(16 * j + (lane & 15)) * 17 + 4 * (lane >> 4) + r] = pacc[j][r];
         __syncthreads();
+        // thread -> (column pair, l, re/im) so that a map's 16 degrees x (re, im) are written contiguously
+        const float *Pb = sm + (size_t)par * NW * TS_RS;
         for (int t = threadIdx.x; t < 1024; t += blockDim.x) {
-            const int li = t >> 6, col = t & 63;
+            const int col = 2 * (t >> 5) + (t & 1), li = (t >> 1) & 15;
             const int l = lb + li, cg = g * 64 + col;
             double v = 0.0;
-            for (int ww = 0; ww < NW; ++ww) v += (double)sm[(size_t)ww * 1024 + t];
+            for (int ww = 0; ww < NW; ++ww) v += (double)Pb[(size_t)ww * TS_RS + col * 17 + li];
             if (l < L && cg < ncols) {
                 const int s = cg / (2 * B);
                 const int rem = cg - s * 2 * B;
                 const int b = rem >> 1, cc = rem & 1;
-                const double sc = a.S[tabm + l] * a.w[s][(size_t)ni * a.wstride + l];
+                const double sc = t == (int)threadIdx.x ? s0 * w0 : a.S[tabm + l] * a.w[s][(size_t)ni * a.wstride + l];
                 in.out[s][((((size_t)b * a.mcount + m) * a.nn + ni) * L + l) * 2 + cc] = v * sc;
             }
         }
-        __syncthreads();
     }
     // zero l < l0
     const int nz = (l0 < L ? l0 : L);
@@ -343,9 +396,9 @@ void launch_tsum_mm(const TsumArgs &a, const MixIn &in, int NS, hipStream_t st)
     const int NW = (a.L + 63) / 64;
     const int ngrp = (2 * in.B * NS + 63) / 64;
     dim3 grid(a.mcount, a.nn, ngrp);
-    const size_t smem = sizeof(float) * 1024 * (size_t)NW;
-    if (NS == 1) hipLaunchKernelGGL(k_tsum_mm<1>, grid, dim3(64 * NW), smem, st, a, in);
-    else hipLaunchKernelGGL(k_tsum_mm<2>, grid, dim3(64 * NW), smem, st, a, in);
+    const size_t smem = sizeof(float) * 2 * TS_RS * (size_t)NW;   // 139 KB at NW = 16
+    if (NS == 1) hipLaunchKernelGGL(k_tsum_mm<1>, grid, dim3(64 * NW), smem, st, a, in, a.A, a.B_);
+    else hipLaunchKernelGGL(k_tsum_mm<2>, grid, dim3(64 * NW), smem, st, a, in, a.A, a.B_);
 }
 
 // ------------------------------------------------------------ k_dft_mm -----
