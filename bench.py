@@ -54,7 +54,64 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="skip the plan's tile-shape autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM traffic counters)")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no benchmark: read two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; csv output) "
+                         "of 'bench.py --precision mixed --steps 1 --warmup 0 --copy-calibration' and write "
+                         "profiles/traffic.json")
     return ap.parse_args()
+
+
+# library kernel symbol -> the name its launches carry in the per-kernel timing
+KERNEL_NAMES = [("k_tsum_mm", "tsum_mm"), ("k_lsum_mm", "lsum_mm"), ("k_gemm<float>", "gemm_theta_f32"),
+                ("k_gemm<double>", "gemm_theta"), ("k_dft_mm<1,", "dft_c2r_f32"), ("k_dft_mm<-1,", "dft_r2c_f32"),
+                ("k_gamma_c2r<float", "gamma_c2r_f32"), ("k_gamma_r2c<float", "gamma_r2c_f32"),
+                ("k_tsum<", "tsum"), ("k_lsum<", "lsum")]
+
+
+def record_traffic(fetch_dir, write_dir, args):
+    """HBM bytes per launch from FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by
+    what the same counter reads for the 1 GiB device copy of --copy-calibration."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    def load(d):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        val, name = defaultdict(float), {}
+        for r in csv.DictReader(open(f)):
+            val[r["Dispatch_Id"]] += float(r["Counter_Value"])
+            name[r["Dispatch_Id"]] = r["Kernel_Name"].replace(" ", "")
+        return val, name
+
+    fv, fn = load(fetch_dir)
+    wv, wn = load(write_dir)
+    gib_kib = float(1 << 20)
+    # the copy is the largest device copy dispatch of the run (1 GiB read, 1 GiB written)
+    cf = max(v for k, v in fv.items() if "copyBuffer" in fn[k])
+    cw = max(v for k, v in wv.items() if "copyBuffer" in wn[k])
+    ff, fw = gib_kib / cf, gib_kib / cw
+    kern = {}
+    for sym, bname in KERNEL_NAMES:
+        ks = [k for k in fv if sym.replace(" ", "") in fn[k]]
+        kw = [k for k in wv if sym.replace(" ", "") in wn[k]]
+        if not ks or len(ks) != len(kw):
+            continue
+        fb = 1024.0 * ff * sum(fv[k] for k in ks) / len(ks)
+        wb = 1024.0 * fw * sum(wv[k] for k in kw) / len(kw)
+        kern[bname] = {"workload": (f"sphere directional wavelets analysis+synthesis, mixed FP32/FP64 batched, "
+                                    f"L={args.L}, N={args.N}, lambda={args.lam:g}, J0={args.J0}, batch=64"),
+                       "launches": len(ks), "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                       "bytes_per_launch": fb + wb}
+    rec = {"source_sha256": source_hash(),
+           "copy_calibration": {"fetch_kib_for_1gib": cf, "write_kib_for_1gib": cw,
+                                "fetch_scale": ff, "write_scale": fw},
+           "command": ("cd /tmp && rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <dir> -o run --output-format csv "
+                       "-- python3 bench.py --precision mixed --steps 1 --warmup 0 --no-cpu-baseline "
+                       "--no-kernel-timing --copy-calibration"),
+           "kernels": kern}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec, indent=1))
 
 
 def cpu_baseline(L, N, lam, J0):
@@ -217,6 +274,9 @@ def run_form(args, precision, B):
 
 def main():
     args = parse()
+    if args.record_traffic:
+        record_traffic(args.record_traffic[0], args.record_traffic[1], args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "sharding across GPUs is not built", file=sys.stderr)
