@@ -28,7 +28,28 @@ struct DevDft {
     int n = 0, n1 = 0, n2 = 0;
     int *pin = nullptr, *pout = nullptr, *inpos = nullptr, *outpos = nullptr;
     double *w1 = nullptr, *w2 = nullptr;
+    float *frag1 = nullptr, *frag2 = nullptr;
 };
+
+// cos, sin of 2 pi j k / p for the matrix-core DFT stage of length p, laid out as the
+// MFMA A operand: entry (i, s, lane) holds j = 16 i + lane % 16, k = 4 s + lane / 16
+// (zero outside j, k <= (p - 1) / 2); w holds cos, sin of 2 pi t / p for t < p
+std::vector<float> dft_fragments(int p, const std::vector<double> &w)
+{
+    std::vector<float> f((size_t)s2w::DFT_FRAG_MT * s2w::DFT_FRAG_KS * 64 * 2, 0.0f);
+    const int h = (p - 1) / 2;
+    for (int i = 0; i < s2w::DFT_FRAG_MT; ++i)
+        for (int st = 0; st < s2w::DFT_FRAG_KS; ++st)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int j = 16 * i + lane % 16, k = 4 * st + lane / 16;
+                if (p <= 1 || j > h || k > h) continue;
+                const int t = (int)(((long)j * k) % p);
+                const size_t o = (((size_t)i * s2w::DFT_FRAG_KS + st) * 64 + lane) * 2;
+                f[o] = (float)w[2 * t];
+                f[o + 1] = (float)w[2 * t + 1];
+            }
+    return f;
+}
 
 struct DevGrid {
     int L = 0;
@@ -232,6 +253,9 @@ bool make_grid(s2w_plan p, int L)
         !upload(p, g.dft.outpos, outpos) ||
         !upload(p, g.dft.w1, pp.w1) || !upload(p, g.dft.w2, pp.w2))
         return false;
+    if (p->prec == S2W_MIXED && pp.n1 <= 95 && pp.n2 <= 95 &&
+        (!upload(p, g.dft.frag1, dft_fragments(pp.n1, pp.w1)) || !upload(p, g.dft.frag2, dft_fragments(pp.n2, pp.w2))))
+        return false;
     p->grids[L] = g;
     return true;
 }
@@ -269,6 +293,8 @@ DftArgs dft_args(const DevGrid &g, const void *in, long istride, void *out, long
     a.outpos = g.dft.outpos;
     a.w1 = g.dft.w1;
     a.w2 = g.dft.w2;
+    a.frag1 = g.dft.frag1;
+    a.frag2 = g.dft.frag2;
     a.scale = scale;
     // modular inverses for the index maps: input index x sits at position m1 n2 + m2 with
     // m1 = x n2^-1 mod n1, m2 = x n1^-1 mod n2; output frequency k at (k mod n1) n2 + k mod n2

@@ -67,7 +67,11 @@ struct DftArgs {
     int rpb;                     // row pairs per block (set by the launcher)
     int inplace;                 // stages overwrite their input (set by the launcher)
     int inv21, inv12;            // n2^-1 mod n1 and n1^-1 mod n2 (0 for a factor of 1)
+    const float *frag1, *frag2;  // matrix-core DFT: cos, sin of 2 pi j k / p of the stage over n1 (n2) in
+                                 // MFMA A-operand lane order, [DFT_FRAG_MT][DFT_FRAG_KS][64][2] (FP32 plans)
 };
+
+constexpr int DFT_FRAG_MT = 3, DFT_FRAG_KS = 12;   // 16-row tiles of j and 4-deep k steps (p <= 95)
 
 struct GammaArgs {
     const void *src;

@@ -10,6 +10,7 @@
 // cross-wave reduction.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "s2w_dev.h"
@@ -403,100 +404,88 @@ void launch_tsum_mm(const TsumArgs &a, const MixIn &in, int NS, hipStream_t st)
 
 // ------------------------------------------------------------ k_dft_mm -----
 // FP32 odd-length DFTs of the mixed path on matrix cores.  Same prime-factor
-// order and index tables as the FP64 kernels (input index (m1 n2 + m2 n1) mod n
-// at LDS position m1 n2 + m2; output frequency (a1 e1 + a2 e2) mod n at a1 n2 + a2),
-// R row pairs per block, two real rows per complex row.  Each length-p stage
-// pairs k with p-k (u_k = x_k + x_{p-k}, u_0 = x_0, v_k = x_k - x_{p-k}) and
-// forms, as dense products on 16x16x4 FP32 MFMA,
+// order as the FP64 kernels (input index (m1 n2 + m2 n1) mod n at LDS position
+// m1 n2 + m2; output frequency (a1 e1 + a2 e2) mod n at a1 n2 + a2), R row pairs
+// per block iteration, two real rows per complex row.  Each length-p stage pairs
+// k with p-k (u_k = x_k + x_{p-k}, u_0 = x_0, v_k = x_k - x_{p-k}) and forms, as
+// dense products on 16x16x4 FP32 MFMA,
 //   A = C u,  B = S v,  C[j][k] = cos(2 pi jk/p),  S[j][k] = sin(2 pi jk/p),  0 <= j, k <= h,
-// then X_j = A_j + i sgn B_j and X_{p-j} = A_j - i sgn B_j (h = (p-1)/2).  A column
-// of the products is the real or imaginary part of one sequence (slot, sequence):
-// a 16-column tile holds 8 whole sequences, and the wave that reads a tile is the
-// one that overwrites it, so each stage works in place.  C and S stay in
-// registers as MFMA A operands (p <= 95); the u, v operands come from LDS.
+// then X_j = A_j + i sgn B_j and X_{p-j} = A_j - i sgn B_j (h = (p-1)/2).  A wave
+// takes 16 whole sequences at a time, their real and imaginary parts as two MFMA
+// column tiles fed by the same 8-byte LDS reads, so the combination above happens
+// within each lane; the wave that reads a sequence is the one that overwrites it,
+// so each stage works in place.  C and S come from a per-plan table already in
+// A-operand lane order and stay in registers for all the row groups a block takes
+// (blocks loop over row groups); MT, KS bound the stage's j tiles and k steps.
 
-constexpr int DMM_MT = 3;     // 16-row tiles of j (h + 1 <= 48)
-constexpr int DMM_KS = 12;    // 4-deep steps of k
+template <int MT, int KS>
+__device__ __forceinline__ void dft_frag_load(const float *tab, float2 (&f)[MT][KS])
+{
+    const int lane = threadIdx.x & 63;
+    const float2 *t = reinterpret_cast<const float2 *>(tab);
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) f[i][s] = t[((size_t)i * DFT_FRAG_KS + s) * 64 + lane];
+}
 
-__device__ __attribute__((always_inline)) inline void dft_mm_stage(float2 *Z, const float2 *tw, int n, int R, int p,
-                                                                   int q, int sj, int sc, float sgn)
+template <int MT, int KS>
+__device__ __forceinline__ void dft_mm_stage(float2 *Z, const float2 (&f)[MT][KS], int n, int R, int p, int q,
+                                             int sj, int sc, float sgn)
 {
     if (p == 1) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int h = (p - 1) / 2, mt = (h + 16) / 16, ks = (h + 4) / 4;
-    float fc[DMM_MT][DMM_KS], fs[DMM_MT][DMM_KS];
-    // fragments: lane holds C[16 i + lane % 16][4 s + lane / 16]; the table index
-    // j k mod p advances by 4 j mod p from one k step to the next
+    const int nseq = R * q, ngrp = (nseq + 15) >> 4;
+    for (int gi = w; gi < ngrp; gi += nw) {
+        const int sq = 16 * gi + (lane & 15);
+        const bool ok = sq < nseq;
+        const int s = ok ? sq / q : 0;
+        const int c = ok ? sq - s * q : 0;
+        const int base = s * n + c * sc;    // element k of this lane's sequence at base + k sj
+        f4 aR[MT], aI[MT], bR[MT], bI[MT];
 #pragma unroll
-    for (int i = 0; i < DMM_MT; ++i) {
-        const int j = 16 * i + (lane & 15);
-        int jk = (j * (lane >> 4)) % p;
-        const int step = (4 * j) % p;
-#pragma unroll
-        for (int s = 0; s < DMM_KS; ++s) {
-            const int k = 4 * s + (lane >> 4);
-            float cv = 0.f, sv = 0.f;
-            if (i < mt && s < ks && j <= h && k <= h) {
-                const float2 t = tw[jk];
-                cv = t.x;
-                sv = t.y;
-            }
-            fc[i][s] = cv;
-            fs[i][s] = sv;
-            jk += step;
-            if (jk >= p) jk -= p;
-        }
-    }
-    float *Zf = reinterpret_cast<float *>(Z);
-    const int ncol = 2 * R * q, ntile = (ncol + 15) / 16;
-    for (int tile = w; tile < ntile; tile += nw) {
-        const int col = 16 * tile + (lane & 15);
-        const bool cok = col < ncol;
-        const int s = cok ? col / (2 * q) : 0;
-        const int rem = col - s * 2 * q;
-        const int c = rem >> 1, ri = rem & 1;
-        const int base = s * n + c * sc;      // complex index of element k = 0
-        f4 accA[DMM_MT], accB[DMM_MT];
-#pragma unroll
-        for (int i = 0; i < DMM_MT; ++i) {
-            accA[i] = f4{0.f, 0.f, 0.f, 0.f};
-            accB[i] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < MT; ++i) {
+            aR[i] = f4{0.f, 0.f, 0.f, 0.f};
+            aI[i] = f4{0.f, 0.f, 0.f, 0.f};
+            bR[i] = f4{0.f, 0.f, 0.f, 0.f};
+            bI[i] = f4{0.f, 0.f, 0.f, 0.f};
         }
 #pragma unroll
-        for (int st = 0; st < DMM_KS; ++st) {
+        for (int st = 0; st < KS; ++st) {
             if (st >= ks) continue;
             const int k = 4 * st + (lane >> 4);
-            float u = 0.f, v = 0.f;
-            if (cok && k <= h) {
-                const float x1 = Zf[2 * (base + k * sj) + ri];
+            float2 u = make_float2(0.f, 0.f), v = make_float2(0.f, 0.f);
+            if (ok && k <= h) {
+                const float2 x1 = Z[base + k * sj];
                 if (k == 0) {
                     u = x1;
                 } else {
-                    const float x2 = Zf[2 * (base + (p - k) * sj) + ri];
-                    u = x1 + x2;
-                    v = x1 - x2;
+                    const float2 x2 = Z[base + (p - k) * sj];
+                    u = make_float2(x1.x + x2.x, x1.y + x2.y);
+                    v = make_float2(x1.x - x2.x, x1.y - x2.y);
                 }
             }
 #pragma unroll
-            for (int i = 0; i < DMM_MT; ++i) {
+            for (int i = 0; i < MT; ++i) {
                 if (i >= mt) continue;
-                accA[i] = mfma16(fc[i][st], u, accA[i]);
-                accB[i] = mfma16(fs[i][st], v, accB[i]);
+                aR[i] = mfma16(f[i][st].x, u.x, aR[i]);
+                aI[i] = mfma16(f[i][st].x, u.y, aI[i]);
+                bR[i] = mfma16(f[i][st].y, v.x, bR[i]);
+                bI[i] = mfma16(f[i][st].y, v.y, bI[i]);
             }
         }
-        // combine real and imaginary columns (adjacent lanes) and write in place
+        // register r of tile i: j = 16 i + 4 (lane / 16) + r for this lane's sequence
 #pragma unroll
-        for (int i = 0; i < DMM_MT; ++i) {
+        for (int i = 0; i < MT; ++i) {
             if (i >= mt) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const float a = accA[i][r], b = accB[i][r];
-                const float ao = __shfl_xor(a, 1, 64), bo = __shfl_xor(b, 1, 64);
                 const int j = 16 * i + 4 * (lane >> 4) + r;
-                if (cok && ri == 0 && j <= h) {
-                    // this lane: A.re = a, B.re = b; partner: A.im = ao, B.im = bo
-                    Z[base + j * sj] = make_float2(a - sgn * bo, ao + sgn * b);
-                    if (j > 0) Z[base + (p - j) * sj] = make_float2(a + sgn * bo, ao - sgn * b);
+                if (ok && j <= h) {
+                    const float ar = aR[i][r], ai = aI[i][r], br = bR[i][r], bi = bI[i][r];
+                    Z[base + j * sj] = make_float2(ar - sgn * bi, ai + sgn * br);
+                    if (j > 0) Z[base + (p - j) * sj] = make_float2(ar + sgn * bi, ai - sgn * br);
                 }
             }
         }
@@ -505,194 +494,215 @@ __device__ __attribute__((always_inline)) inline void dft_mm_stage(float2 *Z, co
 
 // c2r (DIR = +1): Hermitian rows E (m < Lh, complex FP32) -> real rows of length n.
 // r2c (DIR = -1): real rows (Tin) -> X_m = scale sum_a x(a) e^{-2 pi i m a/n}, m < Lh.
-template <int DIR, typename Tin>
+template <int DIR, typename Tin, int MT1, int KS1, int MT2, int KS2>
 __global__ __launch_bounds__(256) void k_dft_mm(const DftArgs a)
 {
     extern __shared__ __align__(16) unsigned char dmm_smem[];
-    float2 *tw1 = reinterpret_cast<float2 *>(dmm_smem), *tw2 = tw1 + a.n1, *Z = tw2 + a.n2;
+    float2 *Z = reinterpret_cast<float2 *>(dmm_smem);
     const int n = a.n, Lh = (n + 1) / 2, R = a.rpb;
-    const double2 *w1 = reinterpret_cast<const double2 *>(a.w1), *w2 = reinterpret_cast<const double2 *>(a.w2);
-    for (int i = threadIdx.x; i < a.n1 + a.n2; i += blockDim.x) {
-        const double2 t = i < a.n1 ? w1[i] : w2[i - a.n1];
-        tw1[i] = make_float2((float)t.x, (float)t.y);
-    }
-    const long pair0 = (long)blockIdx.x * R;
     const int tid = threadIdx.x, NT = blockDim.x;
     const int n1 = a.n1, n2 = a.n2;
+    float2 f1[MT1][KS1], f2[MT2][KS2];
+    dft_frag_load(a.frag1, f1);
+    dft_frag_load(a.frag2, f2);
     // index maps stepped in registers (tid + NT t for t = 0, 1, ...): input index x sits at
     // position m1 n2 + m2 (m1 = x n2^-1 mod n1, m2 = x n1^-1 mod n2); output frequency k
     // at (k mod n1) n2 + (k mod n2); -x has the negated residues
     const int d1 = (int)((long)NT * a.inv21 % n1), d2 = (int)((long)NT * a.inv12 % n2);
     const int e1 = NT % n1, e2 = NT % n2;
+    const int m1t = (int)((long)tid * a.inv21 % n1), m2t = (int)((long)tid * a.inv12 % n2);
+    const int k1t = tid % n1, k2t = tid % n2;
+    const long npairs = (a.nrows + 1) / 2, ngroups = (npairs + R - 1) / R;
     constexpr int U = 4;
-    if (DIR > 0) {
-        const float sc = (float)a.scale;
-        int m1 = (int)((long)tid * a.inv21 % n1), m2 = (int)((long)tid * a.inv12 % n2);
-        for (int mb = 0; mb < Lh; mb += U * NT) {
-            int pos[U], posc[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                pos[u] = m1 * n2 + m2;
-                posc[u] = (m1 == 0 ? 0 : n1 - m1) * n2 + (m2 == 0 ? 0 : n2 - m2);
-                m1 += d1;
-                if (m1 >= n1) m1 -= n1;
-                m2 += d2;
-                if (m2 >= n2) m2 -= n2;
-            }
-            for (int s = 0; s < R; ++s) {
-                const long r1 = 2 * (pair0 + s);
-                const float2 *in1 = reinterpret_cast<const float2 *>(a.in) + r1 * a.istride;
-                float2 z1[U], z2[U];
+    for (long grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+        const long pair0 = grp * R;
+        if (DIR > 0) {
+            const float sc = (float)a.scale;
+            int m1 = m1t, m2 = m2t;
+            for (int mb = 0; mb < Lh; mb += U * NT) {
+                int pos[U], posc[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int mm = mb + tid + NT * u;
-                    z1[u] = make_float2(0.f, 0.f);
-                    z2[u] = make_float2(0.f, 0.f);
-                    if (mm < Lh && r1 < a.nrows) {
-                        z1[u] = in1[mm];
-                        if (r1 + 1 < a.nrows) z2[u] = in1[a.istride + mm];
+                    pos[u] = m1 * n2 + m2;
+                    posc[u] = (m1 == 0 ? 0 : n1 - m1) * n2 + (m2 == 0 ? 0 : n2 - m2);
+                    m1 += d1;
+                    if (m1 >= n1) m1 -= n1;
+                    m2 += d2;
+                    if (m2 >= n2) m2 -= n2;
+                }
+                for (int s = 0; s < R; ++s) {
+                    const long r1 = 2 * (pair0 + s);
+                    const float2 *in1 = reinterpret_cast<const float2 *>(a.in) + r1 * a.istride;
+                    float2 z1[U], z2[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int mm = mb + tid + NT * u;
+                        z1[u] = make_float2(0.f, 0.f);
+                        z2[u] = make_float2(0.f, 0.f);
+                        if (mm < Lh && r1 < a.nrows) {
+                            z1[u] = in1[mm];
+                            if (r1 + 1 < a.nrows) z2[u] = in1[a.istride + mm];
+                        }
+                    }
+                    float2 *Zs = Z + (size_t)s * n;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int mm = mb + tid + NT * u;
+                        if (mm >= Lh) continue;
+                        if (mm == 0) {
+                            Zs[0] = make_float2(sc * z1[u].x, sc * z2[u].x);
+                        } else {
+                            Zs[pos[u]] = make_float2(sc * (z1[u].x - z2[u].y), sc * (z1[u].y + z2[u].x));
+                            Zs[posc[u]] = make_float2(sc * (z1[u].x + z2[u].y), sc * (z2[u].x - z1[u].y));
+                        }
                     }
                 }
-                float2 *Zs = Z + (size_t)s * n;
+            }
+        } else {
+            int m1 = m1t, m2 = m2t;
+            for (int xb = 0; xb < n; xb += U * NT) {
+                int pos[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int mm = mb + tid + NT * u;
-                    if (mm >= Lh) continue;
-                    if (mm == 0) {
-                        Zs[0] = make_float2(sc * z1[u].x, sc * z2[u].x);
-                    } else {
-                        Zs[pos[u]] = make_float2(sc * (z1[u].x - z2[u].y), sc * (z1[u].y + z2[u].x));
-                        Zs[posc[u]] = make_float2(sc * (z1[u].x + z2[u].y), sc * (z2[u].x - z1[u].y));
+                    pos[u] = m1 * n2 + m2;
+                    m1 += d1;
+                    if (m1 >= n1) m1 -= n1;
+                    m2 += d2;
+                    if (m2 >= n2) m2 -= n2;
+                }
+                for (int s = 0; s < R; ++s) {
+                    const long r1 = 2 * (pair0 + s);
+                    const Tin *x = reinterpret_cast<const Tin *>(a.in) + r1 * a.istride;
+                    float x1[U], x2[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int xi = xb + tid + NT * u;
+                        x1[u] = 0.f;
+                        x2[u] = 0.f;
+                        if (xi < n && r1 < a.nrows) {
+                            x1[u] = (float)x[xi];
+                            if (r1 + 1 < a.nrows) x2[u] = (float)x[a.istride + xi];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (xb + tid + NT * u < n) Z[(size_t)s * n + pos[u]] = make_float2(x1[u], x2[u]);
+                }
+            }
+        }
+        __syncthreads();
+        const float sgn = DIR > 0 ? 1.f : -1.f;
+        dft_mm_stage(Z, f1, n, R, n1, n2, n2, 1, sgn);
+        __syncthreads();
+        dft_mm_stage(Z, f2, n, R, n2, n1, 1, n2, sgn);
+        __syncthreads();
+        int k1 = k1t, k2 = k2t;
+        if (DIR > 0) {
+            for (int ab = 0; ab < n; ab += U * NT) {
+                int pos[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    pos[u] = k1 * n2 + k2;
+                    k1 += e1;
+                    if (k1 >= n1) k1 -= n1;
+                    k2 += e2;
+                    if (k2 >= n2) k2 -= n2;
+                }
+                for (int s = 0; s < R; ++s) {
+                    const long r1 = 2 * (pair0 + s);
+                    if (r1 >= a.nrows) break;
+                    float *o1 = reinterpret_cast<float *>(a.out) + r1 * a.ostride;
+                    const float2 *Zs = Z + (size_t)s * n;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int aa = ab + tid + NT * u;
+                        if (aa >= n) continue;
+                        const float2 z = Zs[pos[u]];
+                        o1[aa] = z.x;
+                        if (r1 + 1 < a.nrows) o1[a.ostride + aa] = z.y;
+                    }
+                }
+            }
+        } else {
+            const float hs = (float)(0.5 * a.scale);
+            for (int mb = 0; mb < Lh; mb += U * NT) {
+                int pos[U], posc[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    pos[u] = k1 * n2 + k2;
+                    posc[u] = (k1 == 0 ? 0 : n1 - k1) * n2 + (k2 == 0 ? 0 : n2 - k2);
+                    k1 += e1;
+                    if (k1 >= n1) k1 -= n1;
+                    k2 += e2;
+                    if (k2 >= n2) k2 -= n2;
+                }
+                for (int s = 0; s < R; ++s) {
+                    const long r1 = 2 * (pair0 + s);
+                    if (r1 >= a.nrows) break;
+                    const float2 *Zs = Z + (size_t)s * n;
+                    float2 *O = reinterpret_cast<float2 *>(a.out) + r1 * a.ostride;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int mm = mb + tid + NT * u;
+                        if (mm >= Lh) continue;
+                        const float2 X = Zs[pos[u]];
+                        const float2 Xc = Zs[posc[u]];
+                        O[mm] = make_float2(hs * (X.x + Xc.x), hs * (X.y - Xc.y));
+                        if (r1 + 1 < a.nrows) O[a.ostride + mm] = make_float2(hs * (X.y + Xc.y), -hs * (X.x - Xc.x));
                     }
                 }
             }
         }
-    } else {
-        int m1 = (int)((long)tid * a.inv21 % n1), m2 = (int)((long)tid * a.inv12 % n2);
-        for (int xb = 0; xb < n; xb += U * NT) {
-            int pos[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                pos[u] = m1 * n2 + m2;
-                m1 += d1;
-                if (m1 >= n1) m1 -= n1;
-                m2 += d2;
-                if (m2 >= n2) m2 -= n2;
-            }
-            for (int s = 0; s < R; ++s) {
-                const long r1 = 2 * (pair0 + s);
-                const Tin *x = reinterpret_cast<const Tin *>(a.in) + r1 * a.istride;
-                float x1[U], x2[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int xi = xb + tid + NT * u;
-                    x1[u] = 0.f;
-                    x2[u] = 0.f;
-                    if (xi < n && r1 < a.nrows) {
-                        x1[u] = (float)x[xi];
-                        if (r1 + 1 < a.nrows) x2[u] = (float)x[a.istride + xi];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (xb + tid + NT * u < n) Z[(size_t)s * n + pos[u]] = make_float2(x1[u], x2[u]);
-            }
-        }
-    }
-    __syncthreads();
-    const float sgn = DIR > 0 ? 1.f : -1.f;
-    dft_mm_stage(Z, tw1, n, R, a.n1, a.n2, a.n2, 1, sgn);
-    __syncthreads();
-    dft_mm_stage(Z, tw2, n, R, a.n2, a.n1, 1, a.n2, sgn);
-    __syncthreads();
-    int k1 = tid % n1, k2 = tid % n2;
-    if (DIR > 0) {
-        for (int ab = 0; ab < n; ab += U * NT) {
-            int pos[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                pos[u] = k1 * n2 + k2;
-                k1 += e1;
-                if (k1 >= n1) k1 -= n1;
-                k2 += e2;
-                if (k2 >= n2) k2 -= n2;
-            }
-            for (int s = 0; s < R; ++s) {
-                const long r1 = 2 * (pair0 + s);
-                if (r1 >= a.nrows) break;
-                float *o1 = reinterpret_cast<float *>(a.out) + r1 * a.ostride;
-                const float2 *Zs = Z + (size_t)s * n;
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int aa = ab + tid + NT * u;
-                    if (aa >= n) continue;
-                    const float2 z = Zs[pos[u]];
-                    o1[aa] = z.x;
-                    if (r1 + 1 < a.nrows) o1[a.ostride + aa] = z.y;
-                }
-            }
-        }
-    } else {
-        const float hs = (float)(0.5 * a.scale);
-        for (int mb = 0; mb < Lh; mb += U * NT) {
-            int pos[U], posc[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                pos[u] = k1 * n2 + k2;
-                posc[u] = (k1 == 0 ? 0 : n1 - k1) * n2 + (k2 == 0 ? 0 : n2 - k2);
-                k1 += e1;
-                if (k1 >= n1) k1 -= n1;
-                k2 += e2;
-                if (k2 >= n2) k2 -= n2;
-            }
-            for (int s = 0; s < R; ++s) {
-                const long r1 = 2 * (pair0 + s);
-                if (r1 >= a.nrows) break;
-                const float2 *Zs = Z + (size_t)s * n;
-                float2 *O = reinterpret_cast<float2 *>(a.out) + r1 * a.ostride;
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int mm = mb + tid + NT * u;
-                    if (mm >= Lh) continue;
-                    const float2 X = Zs[pos[u]];
-                    const float2 Xc = Zs[posc[u]];
-                    O[mm] = make_float2(hs * (X.x + Xc.x), hs * (X.y - Xc.y));
-                    if (r1 + 1 < a.nrows) O[a.ostride + mm] = make_float2(hs * (X.y + Xc.y), -hs * (X.x - Xc.x));
-                }
-            }
-        }
+        __syncthreads();   // the next group's loads overwrite Z
     }
 }
 
 // Matrix-core DFT usable for this length: both prime-factor lengths within the
-// register-resident C and S (p <= 95).
-bool dft_mm_ok(const DftArgs &a) { return a.n1 <= 95 && a.n2 <= 95 && a.n >= 15; }
+// fragment tables (p <= 95), which the plan builds for FP32 plans.
+bool dft_mm_ok(const DftArgs &a) { return a.n1 <= 95 && a.n2 <= 95 && a.n >= 15 && a.frag1 && a.frag2; }
 
-static void dft_mm_shape(DftArgs &a, size_t &lds, int &blocks)
+// fragment tile class of a stage length: h <= 15 -> (1, 4), h <= 31 -> (2, 8), else (3, 12)
+static int dft_cls(int p)
 {
+    const int h = (p - 1) / 2;
+    return h <= 15 ? 0 : (h <= 31 ? 1 : 2);
+}
+
+template <int DIR, int C1, int C2>
+static void launch_dft_mm_t(const DftArgs &a, int blocks, size_t lds, hipStream_t st)
+{
+    constexpr int MT1 = C1 + 1, KS1 = 4 * (C1 + 1), MT2 = C2 + 1, KS2 = 4 * (C2 + 1);
+    if (DIR > 0) hipLaunchKernelGGL((k_dft_mm<1, float, MT1, KS1, MT2, KS2>), dim3(blocks), dim3(256), lds, st, a);
+    else hipLaunchKernelGGL((k_dft_mm<-1, float, MT1, KS1, MT2, KS2>), dim3(blocks), dim3(256), lds, st, a);
+}
+
+template <int DIR>
+static void launch_dft_mm_dir(DftArgs a, hipStream_t st)
+{
+    if (a.nrows <= 0) return;
     int R = 1;
     while (R < 8 && (size_t)(2 * R) * a.n * sizeof(float2) <= 65536) R *= 2;
     a.rpb = R;
-    lds = ((size_t)R * a.n + a.n1 + a.n2) * sizeof(float2);
-    blocks = (int)(((a.nrows + 1) / 2 + R - 1) / R);
+    const size_t lds = (size_t)R * a.n * sizeof(float2);
+    const long ngroups = ((a.nrows + 1) / 2 + R - 1) / R;
+    // blocks loop over row groups: enough for every CU several times over
+    const int blocks = (int)std::min<long>(ngroups, 2048);
+    const int c1 = dft_cls(a.n1), c2 = dft_cls(a.n2);
+    switch (3 * c1 + c2) {
+    case 0: launch_dft_mm_t<DIR, 0, 0>(a, blocks, lds, st); break;
+    case 1: launch_dft_mm_t<DIR, 0, 1>(a, blocks, lds, st); break;
+    case 2: launch_dft_mm_t<DIR, 0, 2>(a, blocks, lds, st); break;
+    case 3: launch_dft_mm_t<DIR, 1, 0>(a, blocks, lds, st); break;
+    case 4: launch_dft_mm_t<DIR, 1, 1>(a, blocks, lds, st); break;
+    case 5: launch_dft_mm_t<DIR, 1, 2>(a, blocks, lds, st); break;
+    case 6: launch_dft_mm_t<DIR, 2, 0>(a, blocks, lds, st); break;
+    case 7: launch_dft_mm_t<DIR, 2, 1>(a, blocks, lds, st); break;
+    default: launch_dft_mm_t<DIR, 2, 2>(a, blocks, lds, st); break;
+    }
 }
 
-void launch_dft_mm_c2r(DftArgs a, hipStream_t st)
-{
-    if (a.nrows <= 0) return;
-    size_t lds;
-    int blocks;
-    dft_mm_shape(a, lds, blocks);
-    hipLaunchKernelGGL((k_dft_mm<1, float>), dim3(blocks), dim3(256), lds, st, a);
-}
+void launch_dft_mm_c2r(DftArgs a, hipStream_t st) { launch_dft_mm_dir<1>(a, st); }
 
-void launch_dft_mm_r2c(DftArgs a, hipStream_t st)
-{
-    if (a.nrows <= 0) return;
-    size_t lds;
-    int blocks;
-    dft_mm_shape(a, lds, blocks);
-    hipLaunchKernelGGL((k_dft_mm<-1, float>), dim3(blocks), dim3(256), lds, st, a);
-}
+void launch_dft_mm_r2c(DftArgs a, hipStream_t st) { launch_dft_mm_dir<-1>(a, st); }
 
 }  // namespace s2w
