@@ -422,6 +422,145 @@ __global__ __launch_bounds__(64) void k_tsum_polar(const TsumArgs a)
     }
 }
 
+// ------------------------------------------------------------ k_tsum_mm64 ----
+// Batched form of k_tsum on FP64 matrix cores (16x16x4), for launches of many maps:
+// the recursion runs once per (m, n, theta) for 32 columns (scale, map, re/im) instead
+// of once per map.  grid (m, ni, groups of 32 columns); NW = ceil(L/64) waves per block,
+// wave w owns theta = 64 w + lane and keeps its 64 x 32 (theta x column) slice of h in
+// registers as MFMA B operands; per chunk of 16 degrees it writes d (FP64) to its LDS
+// slice, forms the 16 x 32 partial product and stores it over that slice, and the
+// waves' partials are summed in a fixed order.  Polar samples are left to k_tsum_polar.
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int TS64_RS = 64 * 16;       // doubles per wave slice: d [64][16] or partial [32 col][17]
+
+template <int NS>
+__global__ __launch_bounds__(1024) void k_tsum_mm64(const TsumArgs a, const double *__restrict__ rA,
+                                                    const double *__restrict__ rB)
+{
+    // rA, rB alias a.A, a.B_: as restrict arguments their wave-uniform reads become scalar loads
+    extern __shared__ double smd[];    // [NW][TS64_RS]
+    const int m = blockIdx.x, ni = blockIdx.y, g = blockIdx.z;
+    const int L = a.L;
+    const int NW = blockDim.x >> 6;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n = a.nval[ni], ng = a.nglob[ni];
+    const int an = n < 0 ? -n : n;
+    const int l0 = m > an ? m : an;
+    const int B = a.B, ncols = 2 * B * NS;
+    const int th = w * 64 + lane;
+    const bool valid = th < L && !is_polar(th, L, a.npol);
+
+    // h slice: hb[ks][j] = h[theta = 64 w + 4 ks + lane / 16][col = 32 g + 16 j + lane % 16]
+    const int sig = (m + a.npar) & 1;
+    const int mp = m >> 1;
+    const size_t sigoff = (sig == 0 ? 0 : (size_t)B * a.M0 * a.nn * 2);
+    const int Msig = (sig == 0 ? a.M0 : a.M1);
+    double hb[16][2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int cg = g * 32 + 16 * j + (lane & 15);
+        int s = 0, b = 0, cc = 0;
+        const bool cok = cg < ncols;
+        if (cok) {
+            s = cg / (2 * B);
+            const int rem = cg - s * 2 * B;
+            b = rem >> 1;
+            cc = rem & 1;
+        }
+        const double *hs = a.h[s < NS ? s : 0];
+        const size_t row = sigoff + (((size_t)b * Msig + mp) * a.nn + ni) * 2 + cc;
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            const int t2 = w * 64 + 4 * ks + (lane >> 4);
+            hb[ks][j] = (cok && t2 < L) ? hs[row * L + t2] : 0.0;
+        }
+    }
+
+    const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
+    double c = 0.0, cl = 0.0, e = 0.0, ep = 0.0;
+    int k = 0;
+    if (th < L && l0 < L) {
+        c = a.cth[th];
+        cl = a.ctl[th];
+        const int p1 = (m + n) < 0 ? -(m + n) : (m + n);
+        const int p2 = (m - n) < 0 ? -(m - n) : (m - n);
+        start_value(a.smant[(size_t)ng * a.Lrec + m], a.sexp[(size_t)ng * a.Lrec + m], p1, p2, a.ch[th],
+                    a.sh[th], a.ceps[th], a.seps[th], e, k);
+    }
+
+    double *Dw = smd + (size_t)w * TS64_RS;
+    for (int lb = l0; lb < L; lb += 16) {
+        // d chunk, swizzled [theta][l ^ (theta & 15)]
+#pragma unroll 4
+        for (int i = 0; i < 16; ++i) {
+            const int l = lb + i;
+            double A = 0.0, Bv = 0.0;
+            if (l < L) { A = rA[tabm + l]; Bv = rB[tabm + l]; }
+            Dw[lane * 16 + (i ^ (lane & 15))] = (valid && k == 0) ? e : 0.0;
+            const double en = fma(fma(A, cl, fma(A, c, -Bv)), e, -ep);
+            ep = e;
+            e = en;
+            if ((i & 7) == 7 && k < 0 && fabs(e) > 0x1p256) {
+                e *= 0x1p-512;
+                ep *= 0x1p-512;
+                k += 1;
+            }
+        }
+        wave_lds_fence();
+        d4v pacc[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) pacc[j] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            const int tl = 4 * ks + (lane >> 4);
+            const double av = Dw[tl * 16 + ((lane & 15) ^ (tl & 15))];   // A[l = lane%16][theta = tl]
+#pragma unroll
+            for (int j = 0; j < 2; ++j) pacc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, hb[ks][j], pacc[j], 0, 0, 0);
+        }
+        wave_lds_fence();
+        // partial 16 (l) x 32 (col), stored [col][l] with stride 17: register r of lane ->
+        // l = lane / 16 + 4 r (FP64 result layout), col = 16 j + lane % 16
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Dw[(16 * j + (lane & 15)) * 17 + (lane >> 4) + 4 * r] = pacc[j][r];
+        __syncthreads();
+        for (int t = threadIdx.x; t < 512; t += blockDim.x) {
+            const int col = 2 * (t >> 5) + (t & 1), li = (t >> 1) & 15;
+            const int l = lb + li, cg = g * 32 + col;
+            double v = 0.0;
+            for (int ww = 0; ww < NW; ++ww) v += smd[(size_t)ww * TS64_RS + col * 17 + li];
+            if (l < L && cg < ncols) {
+                const int s = cg / (2 * B);
+                const int rem = cg - s * 2 * B;
+                const int b = rem >> 1, cc = rem & 1;
+                const double sc = a.S[tabm + l] * a.w[s][(size_t)ni * a.wstride + l];
+                a.out[s][((((size_t)b * a.mcount + m) * a.nn + ni) * L + l) * 2 + cc] = v * sc;
+            }
+        }
+        __syncthreads();   // the next chunk's d overwrites the slices
+    }
+    // zero l < l0
+    const int nz = (l0 < L ? l0 : L);
+    for (int t = threadIdx.x; t < nz * 32; t += blockDim.x) {
+        const int l = t >> 5, col = t & 31, cg = g * 32 + col;
+        if (cg >= ncols) continue;
+        const int s = cg / (2 * B);
+        const int rem = cg - s * 2 * B;
+        const int b = rem >> 1, cc = rem & 1;
+        a.out[s][((((size_t)b * a.mcount + m) * a.nn + ni) * L + l) * 2 + cc] = 0.0;
+    }
+}
+
 // ------------------------------------------------------------- k_gemm ------
 // C[M][N] = A[M][K] * Bm[K][N], row-major, on matrix cores (16x16x4 MFMA, FP64 or FP32).
 // MFMA operand layout (both types): A fragment lane l holds
@@ -1312,7 +1451,29 @@ static void launch_tsum_t(const TsumArgs &a, int B, int nw, hipStream_t st)
     hipLaunchKernelGGL((k_tsum<T, NS>), grid, dim3(64 * nw), 0, st, a);
 }
 
+void launch_tsum_vec(const TsumArgs &a, int NS, int B, hipStream_t st);
+
 void launch_tsum(const TsumArgs &a, int NS, int B, hipStream_t st)
+{
+    if (B >= 16 && a.L <= 1024 && a.mcount > 0) {
+        // many maps: one recursion for 32 columns on FP64 matrix cores
+        const int NW = (a.L + 63) / 64;
+        const int ngrp = (2 * B * NS + 31) / 32;
+        dim3 grid(a.mcount, a.nn, ngrp);
+        const size_t smem = sizeof(double) * TS64_RS * (size_t)NW;   // 128 KB at NW = 16
+        if (NS == 1) hipLaunchKernelGGL(k_tsum_mm64<1>, grid, dim3(64 * NW), smem, st, a, a.A, a.B_);
+        else hipLaunchKernelGGL(k_tsum_mm64<2>, grid, dim3(64 * NW), smem, st, a, a.A, a.B_);
+    } else {
+        launch_tsum_vec(a, NS, B, st);
+    }
+    if (a.npol > 0 && a.mcount > 0) {
+        dim3 grid(a.mcount, a.nn, B);
+        if (NS == 1) hipLaunchKernelGGL(k_tsum_polar<1>, grid, dim3(64), 0, st, a);
+        else hipLaunchKernelGGL(k_tsum_polar<2>, grid, dim3(64), 0, st, a);
+    }
+}
+
+void launch_tsum_vec(const TsumArgs &a, int NS, int B, hipStream_t st)
 {
     // T theta samples per lane (at most 4, keeping the lane state in registers) and
     // up to 4 waves per block: T = ceil(L / (64 nw)) with nw = ceil(L / 256)
@@ -1326,11 +1487,6 @@ void launch_tsum(const TsumArgs &a, int NS, int B, hipStream_t st)
         if (T <= 1) launch_tsum_t<1, 2>(a, B, nw, st);
         else if (T <= 2) launch_tsum_t<2, 2>(a, B, nw, st);
         else launch_tsum_t<4, 2>(a, B, nw, st);
-    }
-    if (a.npol > 0 && a.mcount > 0) {
-        dim3 grid(a.mcount, a.nn, B);
-        if (NS == 1) hipLaunchKernelGGL(k_tsum_polar<1>, grid, dim3(64), 0, st, a);
-        else hipLaunchKernelGGL(k_tsum_polar<2>, grid, dim3(64), 0, st, a);
     }
 }
 
