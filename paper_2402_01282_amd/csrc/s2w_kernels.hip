@@ -561,6 +561,151 @@ __global__ __launch_bounds__(1024) void k_tsum_mm64(const TsumArgs a, const doub
     }
 }
 
+// ------------------------------------------------------------ k_lsum_mm64 ----
+// Batched form of k_lsum on FP64 matrix cores, for launches of many maps: the
+// recursion runs once per (m, n, theta) for 32 columns (scale, map, re/im).  W waves
+// per block, wave w owns the 64-theta tile (tb W + w) of one (m, n, 32 columns) unit;
+// per chunk of 16 degrees the waves share one staged coefficient tile (16-byte
+// (re, im) loads, 16 consecutive degrees per column pair), each writes its d chunk
+// (S_l d, FP64) to LDS and accumulates its 64 x 32 output on the matrix cores.
+// Polar samples are overwritten afterwards by k_lsum_polar.
+
+constexpr int LS64_DS = 64 + 1;        // row stride (doubles) of the d and staging tiles
+
+template <int NS, int W>
+__global__ __launch_bounds__(64 * W) void k_lsum_mm64(const LsumArgs a, const double *__restrict__ rA,
+                                                      const double *__restrict__ rB, const double *__restrict__ rS,
+                                                      int B)
+{
+    constexpr int R = 4 / W;           // staging slots per thread (16 column pairs x 16 degrees)
+    const int L = a.L;
+    const int ntt = (L + 63) >> 6;
+    const int ntb = (ntt + W - 1) / W;
+    const int ncols = 2 * B * NS;
+    const int ngrp = (ncols + 31) >> 5;
+    const int nunit = a.mcount * a.nn * ngrp;
+    // XCD-aware order: the ntb theta blocks of one unit get consecutive slots on one XCD
+    const int bid = blockIdx.x, xcd = bid & 7, kx = bid >> 3;
+    const int tb = kx % ntb, unit = (kx / ntb) * 8 + xcd;
+    if (unit >= nunit) return;
+    const int m = unit % a.mcount, ni = (unit / a.mcount) % a.nn, g = unit / (a.mcount * a.nn);
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int n = a.nval[ni], ng = a.nglob[ni];
+    const int an = n < 0 ? -n : n;
+    const int l0 = m > an ? m : an;
+    const int th = (tb * W + w) * 64 + lane;
+    const bool valid = th < L;
+
+    __shared__ double Ds[W][16 * LS64_DS];   // d chunk [l][theta]; output staging [col][theta] at the end
+    __shared__ double Us[16][32 + 2];        // coefficient chunk [l][column]
+
+    const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
+    double c = 0.0, cl = 0.0, e = 0.0, ep = 0.0;
+    int k = 0;
+    if (valid && l0 < L) {
+        c = a.cth[th];
+        cl = a.ctl[th];
+        const int p1 = (m + n) < 0 ? -(m + n) : (m + n);
+        const int p2 = (m - n) < 0 ? -(m - n) : (m - n);
+        start_value(a.smant[(size_t)ng * a.Lrec + m], a.sexp[(size_t)ng * a.Lrec + m], p1, p2, a.ch[th],
+                    a.sh[th], a.ceps[th], a.seps[th], e, k);
+    }
+
+    // staging slot q = tid + 64 W r: column pair p = q / 16 (re, im of one map and scale), degree lb + q % 16
+    int iq[R], pc[R];
+    bool cok[R];
+    const double *wv[R];
+    const double2 *fl[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int q = tid + 64 * W * r;
+        pc[r] = q >> 4;
+        iq[r] = q & 15;
+        const int cg = g * 32 + 2 * pc[r];
+        cok[r] = cg < ncols;
+        int cs = 0, cb = 0;
+        if (cok[r]) {
+            cs = cg / (2 * B);
+            cb = (cg - cs * 2 * B) >> 1;
+        }
+        wv[r] = a.w[cs < NS ? cs : 0] + (size_t)ni * a.wstride;
+        fl[r] = reinterpret_cast<const double2 *>(a.flm) + ((size_t)cb * a.flm_m + m) * a.flm_l;
+    }
+
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    d4 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+    for (int lb = l0; lb < L; lb += 16) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int l = lb + iq[r];
+            double2 f = make_double2(0.0, 0.0);
+            double wt = 0.0;
+            if (cok[r] && l < L) {
+                f = fl[r][l];
+                wt = wv[r][l];
+            }
+            Us[iq[r]][2 * pc[r]] = wt * f.x;
+            Us[iq[r]][2 * pc[r] + 1] = wt * f.y;
+        }
+#pragma unroll 4
+        for (int i = 0; i < 16; ++i) {
+            const int l = lb + i;
+            double A = 0.0, Bv = 0.0, S = 0.0;
+            if (l < L) { A = rA[tabm + l]; Bv = rB[tabm + l]; S = rS[tabm + l]; }
+            Ds[w][i * LS64_DS + lane] = (valid && k == 0) ? S * e : 0.0;
+            const double en = fma(fma(A, cl, fma(A, c, -Bv)), e, -ep);
+            ep = e;
+            e = en;
+            if ((i & 7) == 7 && k < 0 && fabs(e) > 0x1p256) {
+                e *= 0x1p-512;
+                ep *= 0x1p-512;
+                k += 1;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            double af[4], bf[2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) af[i] = Ds[w][(kk + (lane >> 4)) * LS64_DS + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bf[j] = Us[kk + (lane >> 4)][j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // output: one 16-column tile at a time through this wave's Ds slice ([col][theta]),
+    // register r of tile (i, j) holding theta = 16 i + lane / 16 + 4 r, column 16 j + lane % 16
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Ds[w][(lane & 15) * LS64_DS + i * 16 + (lane >> 4) + 4 * r] = acc[i][j][r];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int cgp = g * 32 + 16 * j + 2 * q;
+            if (cgp < ncols && valid) {
+                const int s = cgp / (2 * B);
+                const int b = (cgp - s * 2 * B) >> 1;
+                double2 *dst = reinterpret_cast<double2 *>(a.out[s]);
+                dst[(((size_t)b * a.nn + ni) * a.mcount + m) * L + th] =
+                    make_double2(Ds[w][(2 * q) * LS64_DS + lane], Ds[w][(2 * q + 1) * LS64_DS + lane]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------- k_gemm ------
 // C[M][N] = A[M][K] * Bm[K][N], row-major, on matrix cores (16x16x4 MFMA, FP64 or FP32).
 // MFMA operand layout (both types): A fragment lane l holds
@@ -1420,6 +1565,30 @@ static void launch_lsum_t(const LsumArgs &a, int B, hipStream_t st)
 
 void launch_lsum(const LsumArgs &a, int NS, int B, hipStream_t st)
 {
+    if (B >= 16 && a.mcount > 0) {
+        // many maps: one recursion for 32 columns on FP64 matrix cores
+        const int ntt = (a.L + 63) / 64;
+        const int W = ntt >= 4 ? 4 : (ntt >= 2 ? 2 : 1);
+        const int ntb = (ntt + W - 1) / W;
+        const long nunit = (long)a.mcount * a.nn * ((2 * B * NS + 31) / 32);
+        dim3 grid((unsigned)(8L * ntb * ((nunit + 7) / 8)));
+        const dim3 blk(64 * W);
+        if (NS == 1) {
+            if (W == 4) hipLaunchKernelGGL((k_lsum_mm64<1, 4>), grid, blk, 0, st, a, a.A, a.B, a.S, B);
+            else if (W == 2) hipLaunchKernelGGL((k_lsum_mm64<1, 2>), grid, blk, 0, st, a, a.A, a.B, a.S, B);
+            else hipLaunchKernelGGL((k_lsum_mm64<1, 1>), grid, blk, 0, st, a, a.A, a.B, a.S, B);
+        } else {
+            if (W == 4) hipLaunchKernelGGL((k_lsum_mm64<2, 4>), grid, blk, 0, st, a, a.A, a.B, a.S, B);
+            else if (W == 2) hipLaunchKernelGGL((k_lsum_mm64<2, 2>), grid, blk, 0, st, a, a.A, a.B, a.S, B);
+            else hipLaunchKernelGGL((k_lsum_mm64<2, 1>), grid, blk, 0, st, a, a.A, a.B, a.S, B);
+        }
+        if (a.npol > 0) {
+            dim3 pgrid(a.mcount, a.nn, B);
+            if (NS == 1) hipLaunchKernelGGL(k_lsum_polar<1>, pgrid, dim3(64), 0, st, a);
+            else hipLaunchKernelGGL(k_lsum_polar<2>, pgrid, dim3(64), 0, st, a);
+        }
+        return;
+    }
     int T = a.L > 512 ? 8 : (a.L > 256 ? 8 : (a.L > 128 ? 4 : (a.L > 64 ? 2 : 1)));
     if (a.tileT == 1 || a.tileT == 2 || a.tileT == 4 || a.tileT == 8) T = a.tileT;
     if (NS == 1) {
