@@ -737,15 +737,16 @@ struct GemmCfg<float> {
 };
 template <>
 struct GemmCfg<double> {
-    static constexpr int BK = 16, VEC = 2, APAD = 4, BPAD = 8;
+    static constexpr int BK = 16, VEC = 2, APAD = 2, BPAD = 16;
     typedef double2 V;
 };
 
 // Workgroup tile 128 x 128 (four waves of 64 x 64, 4 x 4 MFMA tiles each), K staged
 // BK at a time through two LDS buffers: the next K slice is fetched from global
 // memory into registers (16-byte vector loads when K and N allow) while the current
-// one feeds the matrix cores.  A is kept [m][k] with row stride BK + 4 and B [k][n]
-// with row stride 128 + BPAD, which makes the fragment reads conflict-free.  Tiles
+// one feeds the matrix cores.  A is kept [m][k] with row stride BK + APAD and B [k][n]
+// with row stride 128 + BPAD, chosen so that the fragment reads of each half-wave fall
+// on distinct banks (FP32: strides 36 and 144 words; FP64: 36 and 288 words, 8-byte reads).  Tiles
 // are assigned XCD-aware: consecutive workgroups go to different XCDs (each with its
 // own L2), so workgroup b runs tile (m, n) = (b % 8 + 8 ((b / 8) / nt), (b / 8) % nt),
 // and all column tiles of a 128-row block of A are read on one XCD.

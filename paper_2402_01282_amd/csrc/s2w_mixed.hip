@@ -65,8 +65,8 @@ __global__ __launch_bounds__(64 * W, 2) void k_lsum_mm(const LsumArgs a, const M
     const int th = (tb * W + w) * 64 + lane;
     const bool valid = th < L;
 
-    __shared__ float Ds[W][16][64 + 4];   // d chunk of each wave [l][theta]; output staging at the end
-    __shared__ float Us[16][64 + 4];         // coefficient chunk [l][column]
+    __shared__ float Ds[2][W][16][64 + 4];   // d chunks of each wave [l][theta]; output staging at the end
+    __shared__ float Us[2][16][64 + 4];      // coefficient chunks [l][column]
 
     const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
     double c = 0.0, cl = 0.0, e = 0.0, ep = 0.0;
@@ -126,59 +126,86 @@ __global__ __launch_bounds__(64 * W, 2) void k_lsum_mm(const LsumArgs a, const M
             acc2[i][j] = f4{0, 0, 0, 0};
         }
 
-    // recursion coefficients of a chunk: lane i < 16 holds A, B, S of degree lb + i,
-    // fetched one chunk ahead; each step reads them from that lane
-    double An = 0.0, Bn = 0.0, Sn = 0.0;
-    if (lane < 16 && l0 + lane < L) {
-        An = a.A[tabm + l0 + lane];
-        Bn = a.B[tabm + l0 + lane];
-        Sn = a.S[tabm + l0 + lane];
-    }
-    int chunk = 0;
-    for (int lb = l0; lb < L; lb += 16, ++chunk) {
-        const double Ac = An, Bc = Bn, Sc = Sn;
-        An = 0.0;
-        Bn = 0.0;
-        Sn = 0.0;
-        if (lane < 16 && lb + 16 + lane < L) {
-            An = a.A[tabm + lb + 16 + lane];
-            Bn = a.B[tabm + lb + 16 + lane];
-            Sn = a.S[tabm + lb + 16 + lane];
+    // The recursion and the coefficient staging run one chunk ahead of the matrix-core
+    // work, into the other of two LDS buffers: chunk c's products are issued between
+    // the recursion steps of chunk c + 1 (independent instructions that overlap on the
+    // VALU and the matrix cores), and one block barrier per chunk suffices (a buffer is
+    // rewritten only after the barrier that follows its last reads).
+    // Recursion coefficients: lane i < 16 holds A, B, S of degree l + i of the chunk
+    // whose recursion runs next (Ac) and of the one after (An, fetched ahead).
+    auto coef = [&](int lc, double &A, double &Bv, double &S) {
+        A = 0.0;
+        Bv = 0.0;
+        S = 0.0;
+        if (lane < 16 && lc + lane < L) {
+            A = a.A[tabm + lc + lane];
+            Bv = a.B[tabm + lc + lane];
+            S = a.S[tabm + lc + lane];
         }
+    };
+    double Ac, Bc, Sc, An, Bn, Sn;
+    coef(l0, Ac, Bc, Sc);
+    coef(l0 + 16, An, Bn, Sn);
+    auto stage = [&](int buf) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            Us[iq[r]][2 * pc[r]] = (float)(w0[r] * f0[r].x);
-            Us[iq[r]][2 * pc[r] + 1] = (float)(w0[r] * f0[r].y);
-            Us[iq[r] + 1][2 * pc[r]] = (float)(w1[r] * f1[r].x);
-            Us[iq[r] + 1][2 * pc[r] + 1] = (float)(w1[r] * f1[r].y);
+            Us[buf][iq[r]][2 * pc[r]] = (float)(w0[r] * f0[r].x);
+            Us[buf][iq[r]][2 * pc[r] + 1] = (float)(w0[r] * f0[r].y);
+            Us[buf][iq[r] + 1][2 * pc[r]] = (float)(w1[r] * f1[r].x);
+            Us[buf][iq[r] + 1][2 * pc[r] + 1] = (float)(w1[r] * f1[r].y);
         }
-        if (lb + 16 < L) fetch(lb + 16);
+    };
+    auto rstep = [&](int buf, int i) {
+        const double A = readlane_d(Ac, i), Bv = readlane_d(Bc, i), S = readlane_d(Sc, i);
+        Ds[buf][w][i][lane] = (valid && k == 0) ? (float)(S * e) : 0.f;
+        const double en = fma(fma(A, cl, fma(A, c, -Bv)), e, -ep);
+        ep = e;
+        e = en;
+        if ((i & 7) == 7 && k < 0 && fabs(e) > 0x1p256) {
+            e *= 0x1p-512;
+            ep *= 0x1p-512;
+            k += 1;
+        }
+    };
+    if (l0 < L) {
+        stage(0);
+        if (l0 + 16 < L) fetch(l0 + 16);
 #pragma unroll 4
-        for (int i = 0; i < 16; ++i) {
-            const double A = readlane_d(Ac, i), Bv = readlane_d(Bc, i), S = readlane_d(Sc, i);
-            Ds[w][i][lane] = (valid && k == 0) ? (float)(S * e) : 0.f;
-            const double en = fma(fma(A, cl, fma(A, c, -Bv)), e, -ep);
-            ep = e;
-            e = en;
-            if ((i & 7) == 7 && k < 0 && fabs(e) > 0x1p256) {
-                e *= 0x1p-512;
-                ep *= 0x1p-512;
-                k += 1;
-            }
+        for (int i = 0; i < 16; ++i) rstep(0, i);
+        Ac = An;
+        Bc = Bn;
+        Sc = Sn;
+        coef(l0 + 32, An, Bn, Sn);
+    }
+    __syncthreads();
+    int chunk = 0;
+    for (int lb = l0; lb < L; lb += 16, ++chunk) {
+        const int cb = chunk & 1, nb = cb ^ 1;
+        const bool nxt = lb + 16 < L;
+        if (nxt) {
+            stage(nb);
+            if (lb + 32 < L) fetch(lb + 32);
         }
-        __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 4) {
             float af[4], bf[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) af[i] = Ds[w][kk + (lane >> 4)][i * 16 + (lane & 15)];
+            for (int i = 0; i < 4; ++i) af[i] = Ds[cb][w][kk + (lane >> 4)][i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bf[j] = Us[kk + (lane >> 4)][j * 16 + (lane & 15)];
+            for (int j = 0; j < 4; ++j) bf[j] = Us[cb][kk + (lane >> 4)][j * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
+            if (nxt) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) rstep(nb, kk + i);
+            }
         }
+        Ac = An;
+        Bc = Bn;
+        Sc = Sn;
+        coef(lb + 48, An, Bn, Sn);
         __syncthreads();
         if ((chunk & 3) == 3) {
 #pragma unroll
@@ -198,7 +225,7 @@ __global__ __launch_bounds__(64 * W, 2) void k_lsum_mm(const LsumArgs a, const M
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                Ds[w][lane & 15][i * 16 + 4 * (lane >> 4) + r] = acc2[i][j][r] + acc[i][j][r];
+                Ds[0][w][lane & 15][i * 16 + 4 * (lane >> 4) + r] = acc2[i][j][r] + acc[i][j][r];
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -207,7 +234,7 @@ __global__ __launch_bounds__(64 * W, 2) void k_lsum_mm(const LsumArgs a, const M
                 const int s = cgp / (2 * B);
                 const int b = (cgp - s * 2 * B) >> 1;
                 float2 *dst = reinterpret_cast<float2 *>(o.out[s]);
-                dst[(((size_t)b * a.nn + ni) * a.mcount + m) * L + th] = make_float2(Ds[w][2 * q][lane], Ds[w][2 * q + 1][lane]);
+                dst[(((size_t)b * a.nn + ni) * a.mcount + m) * L + th] = make_float2(Ds[0][w][2 * q][lane], Ds[0][w][2 * q + 1][lane]);
             }
         }
         __syncthreads();

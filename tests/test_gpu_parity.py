@@ -160,3 +160,29 @@ def test_deterministic():
     w1 = w1.clone()
     w2, s2 = plan.analysis(f)
     assert torch.equal(w1, w2)
+
+
+def test_batched_fp64_matrix_core_path():
+    """Launches of 16 or more maps take the batched FP64 matrix-core contractions (one
+    recursion per 32 columns); 17 maps (a ragged second column group) at L = 70 (a
+    ragged theta tile, polar samples active) against the oracle, map by map."""
+    torch = _torch()
+    L, N, J0, B = 70, 3, 0, 17
+    print(f"[batched FP64 L={L} N={N} B={B}]", flush=True)
+    plan = _plan(L, N, J0, B=B)
+    P = wavelets.Plan(L, N, 2.0, J0)
+    maps = np.stack([_map(L, S.stream_key(5, b)) for b in range(B)])
+    flm = plan.sht_forward(torch.from_numpy(maps).cuda()).cpu().numpy()
+    wav, scal = plan.analysis(torch.from_numpy(maps).cuda())
+    views = plan.wav_views(wav)
+    for b in range(B):
+        assert _rel(flm[b], mw.sht_forward(maps[b], L)) < TOL
+        wr, sr = wavelets.analysis(maps[b], P)
+        for k, w in enumerate(wr):
+            assert _rel(views[k][b].cpu().numpy(), w) < TOL, (b, k)
+        assert _rel(scal[b].cpu().numpy(), sr) < TOL
+    f2 = plan.synthesis(wav, scal).cpu().numpy()
+    for b in range(B):
+        assert _rel(f2[b], maps[b]) < TOL
+    g = plan.sht_inverse(torch.from_numpy(flm).cuda()).cpu().numpy()
+    assert _rel(g, maps) < TOL
