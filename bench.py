@@ -56,16 +56,17 @@ def parse():
                     help="also run a plain 1 GiB device copy (for scaling HBM traffic counters)")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="no benchmark: read two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; csv output) "
-                         "of 'bench.py --precision mixed --steps 1 --warmup 0 --copy-calibration' and write "
-                         "profiles/traffic.json")
+                         "of 'bench.py --precision mixed --steps 1 --warmup 0 --no-tune --copy-calibration' (one "
+                         "round trip, so the averages are per launch of that step) and write profiles/traffic.json")
     return ap.parse_args()
 
 
-# library kernel symbol -> the name its launches carry in the per-kernel timing
-KERNEL_NAMES = [("k_tsum_mm", "tsum_mm"), ("k_lsum_mm", "lsum_mm"), ("k_gemm<float>", "gemm_theta_f32"),
-                ("k_gemm<double>", "gemm_theta"), ("k_dft_mm<1,", "dft_c2r_f32"), ("k_dft_mm<-1,", "dft_r2c_f32"),
-                ("k_gamma_c2r<float", "gamma_c2r_f32"), ("k_gamma_r2c<float", "gamma_r2c_f32"),
-                ("k_tsum<", "tsum"), ("k_lsum<", "lsum")]
+# name a launch carries in the per-kernel timing -> the library kernel symbols it runs
+KERNEL_NAMES = [("tsum_mm", ["k_tsum_mm<"]), ("lsum_mm", ["k_lsum_mm<"]), ("gemm_theta_f32", ["k_gemm<float>"]),
+                ("gemm_theta", ["k_gemm<double>"]), ("dft_c2r_f32", ["k_dft_mm<1,"]),
+                ("dft_r2c_f32", ["k_dft_mm<-1,"]), ("gamma_c2r_f32", ["k_gamma_c2r<float"]),
+                ("gamma_r2c_f32", ["k_gamma_r2c<float"]), ("tsum", ["k_tsum_mm64<", "k_tsum<"]),
+                ("lsum", ["k_lsum_mm64<", "k_lsum<"])]
 
 
 def record_traffic(fetch_dir, write_dir, args):
@@ -91,9 +92,9 @@ def record_traffic(fetch_dir, write_dir, args):
     cw = max(v for k, v in wv.items() if "copyBuffer" in wn[k])
     ff, fw = gib_kib / cf, gib_kib / cw
     kern = {}
-    for sym, bname in KERNEL_NAMES:
-        ks = [k for k in fv if sym.replace(" ", "") in fn[k]]
-        kw = [k for k in wv if sym.replace(" ", "") in wn[k]]
+    for bname, syms in KERNEL_NAMES:
+        ks = [k for k in fv if any(sy.replace(" ", "") in fn[k] for sy in syms)]
+        kw = [k for k in wv if any(sy.replace(" ", "") in wn[k] for sy in syms)]
         if not ks or len(ks) != len(kw):
             continue
         fb = 1024.0 * ff * sum(fv[k] for k in ks) / len(ks)
@@ -106,7 +107,7 @@ def record_traffic(fetch_dir, write_dir, args):
            "copy_calibration": {"fetch_kib_for_1gib": cf, "write_kib_for_1gib": cw,
                                 "fetch_scale": ff, "write_scale": fw},
            "command": ("cd /tmp && rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <dir> -o run --output-format csv "
-                       "-- python3 bench.py --precision mixed --steps 1 --warmup 0 --no-cpu-baseline "
+                       "-- python3 bench.py --precision mixed --steps 1 --warmup 0 --no-tune --no-cpu-baseline "
                        "--no-kernel-timing --copy-calibration"),
            "kernels": kern}
     with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
