@@ -462,7 +462,7 @@ __device__ __forceinline__ void dft_mm_stage(float2 *Z, const float2 (&f)[MT][KS
 {
     if (p == 1) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int h = (p - 1) / 2, mt = (h + 16) / 16, ks = (h + 4) / 4;
+    const int h = (p - 1) / 2, mt = (h + 16) / 16;
     const int nseq = R * q, ngrp = (nseq + 15) >> 4;
     for (int gi = w; gi < ngrp; gi += nw) {
         const int sq = 16 * gi + (lane & 15);
@@ -478,9 +478,10 @@ __device__ __forceinline__ void dft_mm_stage(float2 *Z, const float2 (&f)[MT][KS
             bR[i] = f4{0.f, 0.f, 0.f, 0.f};
             bI[i] = f4{0.f, 0.f, 0.f, 0.f};
         }
+        // every k step and j tile up to KS, MT is issued (no branch around the products, so the
+        // accumulators stay in place): fragments and u, v are zero beyond j, k <= h
 #pragma unroll
         for (int st = 0; st < KS; ++st) {
-            if (st >= ks) continue;
             const int k = 4 * st + (lane >> 4);
             float2 u = make_float2(0.f, 0.f), v = make_float2(0.f, 0.f);
             if (ok && k <= h) {
@@ -495,7 +496,6 @@ __device__ __forceinline__ void dft_mm_stage(float2 *Z, const float2 (&f)[MT][KS
             }
 #pragma unroll
             for (int i = 0; i < MT; ++i) {
-                if (i >= mt) continue;
                 aR[i] = mfma16(f[i][st].x, u.x, aR[i]);
                 aI[i] = mfma16(f[i][st].x, u.y, aI[i]);
                 bR[i] = mfma16(f[i][st].y, v.x, bR[i]);
@@ -522,7 +522,7 @@ __device__ __forceinline__ void dft_mm_stage(float2 *Z, const float2 (&f)[MT][KS
 // c2r (DIR = +1): Hermitian rows E (m < Lh, complex FP32) -> real rows of length n.
 // r2c (DIR = -1): real rows (Tin) -> X_m = scale sum_a x(a) e^{-2 pi i m a/n}, m < Lh.
 template <int DIR, typename Tin, int MT1, int KS1, int MT2, int KS2>
-__global__ __launch_bounds__(256) void k_dft_mm(const DftArgs a)
+__global__ __launch_bounds__(256, 2) void k_dft_mm(const DftArgs a)
 {
     extern __shared__ __align__(16) unsigned char dmm_smem[];
     float2 *Z = reinterpret_cast<float2 *>(dmm_smem);
@@ -688,17 +688,18 @@ __global__ __launch_bounds__(256) void k_dft_mm(const DftArgs a)
 // fragment tables (p <= 95), which the plan builds for FP32 plans.
 bool dft_mm_ok(const DftArgs &a) { return a.n1 <= 95 && a.n2 <= 95 && a.n >= 15 && a.frag1 && a.frag2; }
 
-// fragment tile class of a stage length: h <= 15 -> (1, 4), h <= 31 -> (2, 8), else (3, 12)
-static int dft_cls(int p)
+// tile shape (j tiles MT, 4-deep k steps KS) of a stage of length p: MT = ceil((h+1)/16),
+// KS = ceil((h+1)/4), h = (p - 1) / 2; the class bounds (1, 4), (2, 8), (3, 12) cover any p <= 95
+static void dft_shape(int p, int &mt, int &ks)
 {
     const int h = (p - 1) / 2;
-    return h <= 15 ? 0 : (h <= 31 ? 1 : 2);
+    mt = (h + 16) / 16;
+    ks = (h + 4) / 4;
 }
 
-template <int DIR, int C1, int C2>
+template <int DIR, int MT1, int KS1, int MT2, int KS2>
 static void launch_dft_mm_t(const DftArgs &a, int blocks, size_t lds, hipStream_t st)
 {
-    constexpr int MT1 = C1 + 1, KS1 = 4 * (C1 + 1), MT2 = C2 + 1, KS2 = 4 * (C2 + 1);
     if (DIR > 0) hipLaunchKernelGGL((k_dft_mm<1, float, MT1, KS1, MT2, KS2>), dim3(blocks), dim3(256), lds, st, a);
     else hipLaunchKernelGGL((k_dft_mm<-1, float, MT1, KS1, MT2, KS2>), dim3(blocks), dim3(256), lds, st, a);
 }
@@ -714,17 +715,30 @@ static void launch_dft_mm_dir(DftArgs a, hipStream_t st)
     const long ngroups = ((a.nrows + 1) / 2 + R - 1) / R;
     // blocks loop over row groups: enough for every CU several times over
     const int blocks = (int)std::min<long>(ngroups, 2048);
-    const int c1 = dft_cls(a.n1), c2 = dft_cls(a.n2);
-    switch (3 * c1 + c2) {
-    case 0: launch_dft_mm_t<DIR, 0, 0>(a, blocks, lds, st); break;
-    case 1: launch_dft_mm_t<DIR, 0, 1>(a, blocks, lds, st); break;
-    case 2: launch_dft_mm_t<DIR, 0, 2>(a, blocks, lds, st); break;
-    case 3: launch_dft_mm_t<DIR, 1, 0>(a, blocks, lds, st); break;
-    case 4: launch_dft_mm_t<DIR, 1, 1>(a, blocks, lds, st); break;
-    case 5: launch_dft_mm_t<DIR, 1, 2>(a, blocks, lds, st); break;
-    case 6: launch_dft_mm_t<DIR, 2, 0>(a, blocks, lds, st); break;
-    case 7: launch_dft_mm_t<DIR, 2, 1>(a, blocks, lds, st); break;
-    default: launch_dft_mm_t<DIR, 2, 2>(a, blocks, lds, st); break;
+    int m1, k1, m2, k2;
+    dft_shape(a.n1, m1, k1);
+    dft_shape(a.n2, m2, k2);
+    const auto is = [&](int a1, int b1, int a2, int b2) { return m1 == a1 && k1 == b1 && m2 == a2 && k2 == b2; };
+    // exact shapes of the lengths 2L - 1 for L = 1024, 512, 256, 128, 32 (23 89, 31 33, 7 73, 15 17, 7 9)
+    if (is(1, 3, 3, 12)) launch_dft_mm_t<DIR, 1, 3, 3, 12>(a, blocks, lds, st);
+    else if (is(1, 4, 2, 5)) launch_dft_mm_t<DIR, 1, 4, 2, 5>(a, blocks, lds, st);
+    else if (is(1, 1, 3, 10)) launch_dft_mm_t<DIR, 1, 1, 3, 10>(a, blocks, lds, st);
+    else if (is(1, 2, 1, 3)) launch_dft_mm_t<DIR, 1, 2, 1, 3>(a, blocks, lds, st);
+    else if (is(1, 1, 1, 2)) launch_dft_mm_t<DIR, 1, 1, 1, 2>(a, blocks, lds, st);
+    else {
+        // any other shape within the class bounds (products beyond h add zeros)
+        const int c1 = m1 - 1, c2 = m2 - 1;
+        switch (3 * c1 + c2) {
+        case 0: launch_dft_mm_t<DIR, 1, 4, 1, 4>(a, blocks, lds, st); break;
+        case 1: launch_dft_mm_t<DIR, 1, 4, 2, 8>(a, blocks, lds, st); break;
+        case 2: launch_dft_mm_t<DIR, 1, 4, 3, 12>(a, blocks, lds, st); break;
+        case 3: launch_dft_mm_t<DIR, 2, 8, 1, 4>(a, blocks, lds, st); break;
+        case 4: launch_dft_mm_t<DIR, 2, 8, 2, 8>(a, blocks, lds, st); break;
+        case 5: launch_dft_mm_t<DIR, 2, 8, 3, 12>(a, blocks, lds, st); break;
+        case 6: launch_dft_mm_t<DIR, 3, 12, 1, 4>(a, blocks, lds, st); break;
+        case 7: launch_dft_mm_t<DIR, 3, 12, 2, 8>(a, blocks, lds, st); break;
+        default: launch_dft_mm_t<DIR, 3, 12, 3, 12>(a, blocks, lds, st); break;
+        }
     }
 }
 
