@@ -732,21 +732,22 @@ template <typename Tp>
 struct GemmCfg;
 template <>
 struct GemmCfg<float> {
-    static constexpr int BK = 32, VEC = 4, APAD = 4, BPAD = 16;
+    static constexpr int BN = 128, BK = 32, VEC = 4, APAD = 4, BPAD = 16;
     typedef float4 V;
 };
 template <>
 struct GemmCfg<double> {
-    static constexpr int BK = 16, VEC = 2, APAD = 2, BPAD = 16;
+    // 64 columns per block: a wave's 64 x 32 FP64 tile keeps its accumulators in 64 registers
+    static constexpr int BN = 64, BK = 16, VEC = 2, APAD = 2, BPAD = 16;
     typedef double2 V;
 };
 
-// Workgroup tile 128 x 128 (four waves of 64 x 64, 4 x 4 MFMA tiles each), K staged
+// Workgroup tile 128 x BN (four waves of 64 x BN/2; BN = 128 for FP32, 64 for FP64), K staged
 // BK at a time through two LDS buffers: the next K slice is fetched from global
 // memory into registers (16-byte vector loads when K and N allow) while the current
 // one feeds the matrix cores.  A is kept [m][k] with row stride BK + APAD and B [k][n]
-// with row stride 128 + BPAD, chosen so that the fragment reads of each half-wave fall
-// on distinct banks (FP32: strides 36 and 144 words; FP64: 36 and 288 words, 8-byte reads).  Tiles
+// with row stride BN + BPAD, chosen so that the fragment reads of each half-wave fall
+// on distinct banks (FP32: strides 36 and 144 words; FP64: 36 and 160 words, 8-byte reads).  Tiles
 // are assigned XCD-aware: consecutive workgroups go to different XCDs (each with its
 // own L2), so workgroup b runs tile (m, n) = (b % 8 + 8 ((b / 8) / nt), (b / 8) % nt),
 // and all column tiles of a 128-row block of A are read on one XCD.
@@ -755,7 +756,8 @@ __global__ __launch_bounds__(256) void k_gemm(const Tp *__restrict__ A, const Tp
                                               Tp *__restrict__ C, int M, int N, int K, int accum, int mt, int nt,
                                               int vec)
 {
-    constexpr int BM = 128, BN = 128, BK = GemmCfg<Tp>::BK, VEC = GemmCfg<Tp>::VEC;
+    constexpr int BM = 128, BN = GemmCfg<Tp>::BN, BK = GemmCfg<Tp>::BK, VEC = GemmCfg<Tp>::VEC;
+    constexpr int WN = BN / 32;        // 16-column MFMA tiles per wave (two waves across the block)
     constexpr int AS = BK + GemmCfg<Tp>::APAD, BS = BN + GemmCfg<Tp>::BPAD;
     constexpr int AV = BM * BK / VEC / 256, BV = BK * BN / VEC / 256;   // vectors per thread
     typedef typename GemmCfg<Tp>::V V;
@@ -818,11 +820,11 @@ __global__ __launch_bounds__(256) void k_gemm(const Tp *__restrict__ A, const Tp
             *reinterpret_cast<V *>(b + bk * BS + bq * VEC) = rb[r];
         }
     };
-    v4 acc[4][4];
+    v4 acc[4][WN];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = v4{0, 0, 0, 0};
+        for (int j = 0; j < WN; ++j) acc[i][j] = v4{0, 0, 0, 0};
     const int nk = (K + BK - 1) / BK;
     gload(0);
     sstore(0);
@@ -834,15 +836,15 @@ __global__ __launch_bounds__(256) void k_gemm(const Tp *__restrict__ A, const Tp
         const Tp *b = Bs + cur * BK * BS;
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
-            Tp af[4], bf[4];
+            Tp af[4], bf[WN];
 #pragma unroll
             for (int i = 0; i < 4; ++i) af[i] = a[(wr * 64 + i * 16 + (lane & 15)) * AS + kk + (lane >> 4)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bf[j] = b[(kk + (lane >> 4)) * BS + wc * 64 + j * 16 + (lane & 15)];
+            for (int j = 0; j < WN; ++j) bf[j] = b[(kk + (lane >> 4)) * BS + wc * (BN / 2) + j * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = Mfma16<Tp>::op(af[i], bf[j], acc[i][j]);
+                for (int j = 0; j < WN; ++j) acc[i][j] = Mfma16<Tp>::op(af[i], bf[j], acc[i][j]);
         }
         if (t + 1 < nk) sstore(cur ^ 1);
         __syncthreads();
@@ -852,22 +854,22 @@ __global__ __launch_bounds__(256) void k_gemm(const Tp *__restrict__ A, const Tp
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < WN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int gr = row0 + wr * 64 + i * 16 + Mfma16<Tp>::row(lane, r);
-                    const int gc = col0 + wc * 64 + j * 16 + (lane & 15);
+                    const int gc = col0 + wc * (BN / 2) + j * 16 + (lane & 15);
                     if (gr < M && gc < N) C[(size_t)gr * N + gc] += acc[i][j][r];
                 }
     } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < WN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int gr = row0 + wr * 64 + i * 16 + Mfma16<Tp>::row(lane, r);
-                    const int gc = col0 + wc * 64 + j * 16 + (lane & 15);
+                    const int gc = col0 + wc * (BN / 2) + j * 16 + (lane & 15);
                     if (gr < M && gc < N) C[(size_t)gr * N + gc] = acc[i][j][r];
                 }
     }
@@ -1671,10 +1673,10 @@ template <typename Tp>
 static void launch_gemm_t(const Tp *A, const Tp *Bm, Tp *C, int M, int N, int K, hipStream_t st, bool accum)
 {
     if (M <= 0 || N <= 0) return;
-    constexpr int VEC = GemmCfg<Tp>::VEC, BK = GemmCfg<Tp>::BK;
-    const int mt = (M + 127) / 128, nt = (N + 127) / 128;
+    constexpr int VEC = GemmCfg<Tp>::VEC, BK = GemmCfg<Tp>::BK, BN = GemmCfg<Tp>::BN;
+    const int mt = (M + 127) / 128, nt = (N + BN - 1) / BN;
     const bool vec = (K % VEC == 0) && (N % VEC == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)Bm % 16 == 0);
-    const size_t lds = sizeof(Tp) * 2 * ((size_t)128 * (BK + GemmCfg<Tp>::APAD) + (size_t)BK * (128 + GemmCfg<Tp>::BPAD));
+    const size_t lds = sizeof(Tp) * 2 * ((size_t)128 * (BK + GemmCfg<Tp>::APAD) + (size_t)BK * (BN + GemmCfg<Tp>::BPAD));
     const unsigned blocks = 8u * (unsigned)nt * (unsigned)((mt + 7) / 8);
     hipLaunchKernelGGL(k_gemm<Tp>, dim3(blocks), dim3(256), lds, st, A, Bm, C, M, N, K, accum ? 1 : 0, mt, nt,
                        vec ? 1 : 0);
