@@ -732,7 +732,7 @@ template <typename Tp>
 struct GemmCfg;
 template <>
 struct GemmCfg<float> {
-    static constexpr int BN = 128, BK = 32, VEC = 4, APAD = 4, BPAD = 16;
+    static constexpr int BN = 128, BK = 16, VEC = 4, APAD = 4, BPAD = 16;
     typedef float4 V;
 };
 template <>
