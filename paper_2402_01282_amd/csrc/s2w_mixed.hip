@@ -445,19 +445,19 @@ void launch_tsum_mm(const TsumArgs &a, const MixIn &in, int NS, hipStream_t st)
 // A-operand lane order and stay in registers for all the row groups a block takes
 // (blocks loop over row groups); MT, KS bound the stage's j tiles and k steps.
 
+// copy a stage's fragment table (MT x KS x 64 lanes of (cos, sin)) into LDS
 template <int MT, int KS>
-__device__ __forceinline__ void dft_frag_load(const float *tab, float2 (&f)[MT][KS])
+__device__ __forceinline__ void dft_frag_load(const float *tab, float2 *F)
 {
-    const int lane = threadIdx.x & 63;
     const float2 *t = reinterpret_cast<const float2 *>(tab);
-#pragma unroll
-    for (int i = 0; i < MT; ++i)
-#pragma unroll
-        for (int s = 0; s < KS; ++s) f[i][s] = t[((size_t)i * DFT_FRAG_KS + s) * 64 + lane];
+    for (int e = threadIdx.x; e < MT * KS * 64; e += blockDim.x) {
+        const int i = e / (KS * 64), r = e - i * KS * 64, s = r >> 6, lane = r & 63;
+        F[e] = t[((size_t)i * DFT_FRAG_KS + s) * 64 + lane];
+    }
 }
 
 template <int MT, int KS>
-__device__ __forceinline__ void dft_mm_stage(float2 *Z, const float2 (&f)[MT][KS], int n, int R, int p, int q,
+__device__ __forceinline__ void dft_mm_stage(float2 *Z, const float2 *F, int n, int R, int p, int q,
                                              int sj, int sc, float sgn)
 {
     if (p == 1) return;
@@ -496,10 +496,11 @@ __device__ __forceinline__ void dft_mm_stage(float2 *Z, const float2 (&f)[MT][KS
             }
 #pragma unroll
             for (int i = 0; i < MT; ++i) {
-                aR[i] = mfma16(f[i][st].x, u.x, aR[i]);
-                aI[i] = mfma16(f[i][st].x, u.y, aI[i]);
-                bR[i] = mfma16(f[i][st].y, v.x, bR[i]);
-                bI[i] = mfma16(f[i][st].y, v.y, bI[i]);
+                const float2 f = F[(i * KS + st) * 64 + lane];   // (cos, sin) A-operand fragment
+                aR[i] = mfma16(f.x, u.x, aR[i]);
+                aI[i] = mfma16(f.x, u.y, aI[i]);
+                bR[i] = mfma16(f.y, v.x, bR[i]);
+                bI[i] = mfma16(f.y, v.y, bI[i]);
             }
         }
         // register r of tile i: j = 16 i + 4 (lane / 16) + r for this lane's sequence
@@ -522,16 +523,16 @@ __device__ __forceinline__ void dft_mm_stage(float2 *Z, const float2 (&f)[MT][KS
 // c2r (DIR = +1): Hermitian rows E (m < Lh, complex FP32) -> real rows of length n.
 // r2c (DIR = -1): real rows (Tin) -> X_m = scale sum_a x(a) e^{-2 pi i m a/n}, m < Lh.
 template <int DIR, typename Tin, int MT1, int KS1, int MT2, int KS2>
-__global__ __launch_bounds__(256, 2) void k_dft_mm(const DftArgs a)
+__global__ __launch_bounds__(256, 3) void k_dft_mm(const DftArgs a)
 {
     extern __shared__ __align__(16) unsigned char dmm_smem[];
     float2 *Z = reinterpret_cast<float2 *>(dmm_smem);
     const int n = a.n, Lh = (n + 1) / 2, R = a.rpb;
     const int tid = threadIdx.x, NT = blockDim.x;
     const int n1 = a.n1, n2 = a.n2;
-    float2 f1[MT1][KS1], f2[MT2][KS2];
-    dft_frag_load(a.frag1, f1);
-    dft_frag_load(a.frag2, f2);
+    float2 *F1 = Z + (size_t)R * n, *F2 = F1 + MT1 * KS1 * 64;
+    dft_frag_load<MT1, KS1>(a.frag1, F1);
+    dft_frag_load<MT2, KS2>(a.frag2, F2);
     // index maps stepped in registers (tid + NT t for t = 0, 1, ...): input index x sits at
     // position m1 n2 + m2 (m1 = x n2^-1 mod n1, m2 = x n1^-1 mod n2); output frequency k
     // at (k mod n1) n2 + (k mod n2); -x has the negated residues
@@ -619,9 +620,9 @@ __global__ __launch_bounds__(256, 2) void k_dft_mm(const DftArgs a)
         }
         __syncthreads();
         const float sgn = DIR > 0 ? 1.f : -1.f;
-        dft_mm_stage(Z, f1, n, R, n1, n2, n2, 1, sgn);
+        dft_mm_stage<MT1, KS1>(Z, F1, n, R, n1, n2, n2, 1, sgn);
         __syncthreads();
-        dft_mm_stage(Z, f2, n, R, n2, n1, 1, n2, sgn);
+        dft_mm_stage<MT2, KS2>(Z, F2, n, R, n2, n1, 1, n2, sgn);
         __syncthreads();
         int k1 = k1t, k2 = k2t;
         if (DIR > 0) {
@@ -698,8 +699,18 @@ static void dft_shape(int p, int &mt, int &ks)
 }
 
 template <int DIR, int MT1, int KS1, int MT2, int KS2>
-static void launch_dft_mm_t(const DftArgs &a, int blocks, size_t lds, hipStream_t st)
+static void launch_dft_mm_t(DftArgs a, hipStream_t st)
 {
+    // row pairs per block iteration: LDS for them and the two fragment tables within 54 KB,
+    // so that three blocks fit on a compute unit
+    const size_t frag = (size_t)(MT1 * KS1 + MT2 * KS2) * 64 * sizeof(float2);
+    int R = 1;
+    while (R < 8 && (size_t)(2 * R) * a.n * sizeof(float2) + frag <= 55296) R *= 2;
+    a.rpb = R;
+    const size_t lds = (size_t)R * a.n * sizeof(float2) + frag;
+    const long ngroups = ((a.nrows + 1) / 2 + R - 1) / R;
+    // blocks loop over row groups: enough for every CU several times over
+    const int blocks = (int)std::min<long>(ngroups, 2048);
     if (DIR > 0) hipLaunchKernelGGL((k_dft_mm<1, float, MT1, KS1, MT2, KS2>), dim3(blocks), dim3(256), lds, st, a);
     else hipLaunchKernelGGL((k_dft_mm<-1, float, MT1, KS1, MT2, KS2>), dim3(blocks), dim3(256), lds, st, a);
 }
@@ -708,36 +719,29 @@ template <int DIR>
 static void launch_dft_mm_dir(DftArgs a, hipStream_t st)
 {
     if (a.nrows <= 0) return;
-    int R = 1;
-    while (R < 8 && (size_t)(2 * R) * a.n * sizeof(float2) <= 65536) R *= 2;
-    a.rpb = R;
-    const size_t lds = (size_t)R * a.n * sizeof(float2);
-    const long ngroups = ((a.nrows + 1) / 2 + R - 1) / R;
-    // blocks loop over row groups: enough for every CU several times over
-    const int blocks = (int)std::min<long>(ngroups, 2048);
     int m1, k1, m2, k2;
     dft_shape(a.n1, m1, k1);
     dft_shape(a.n2, m2, k2);
     const auto is = [&](int a1, int b1, int a2, int b2) { return m1 == a1 && k1 == b1 && m2 == a2 && k2 == b2; };
     // exact shapes of the lengths 2L - 1 for L = 1024, 512, 256, 128, 32 (23 89, 31 33, 7 73, 15 17, 7 9)
-    if (is(1, 3, 3, 12)) launch_dft_mm_t<DIR, 1, 3, 3, 12>(a, blocks, lds, st);
-    else if (is(1, 4, 2, 5)) launch_dft_mm_t<DIR, 1, 4, 2, 5>(a, blocks, lds, st);
-    else if (is(1, 1, 3, 10)) launch_dft_mm_t<DIR, 1, 1, 3, 10>(a, blocks, lds, st);
-    else if (is(1, 2, 1, 3)) launch_dft_mm_t<DIR, 1, 2, 1, 3>(a, blocks, lds, st);
-    else if (is(1, 1, 1, 2)) launch_dft_mm_t<DIR, 1, 1, 1, 2>(a, blocks, lds, st);
+    if (is(1, 3, 3, 12)) launch_dft_mm_t<DIR, 1, 3, 3, 12>(a, st);
+    else if (is(1, 4, 2, 5)) launch_dft_mm_t<DIR, 1, 4, 2, 5>(a, st);
+    else if (is(1, 1, 3, 10)) launch_dft_mm_t<DIR, 1, 1, 3, 10>(a, st);
+    else if (is(1, 2, 1, 3)) launch_dft_mm_t<DIR, 1, 2, 1, 3>(a, st);
+    else if (is(1, 1, 1, 2)) launch_dft_mm_t<DIR, 1, 1, 1, 2>(a, st);
     else {
         // any other shape within the class bounds (products beyond h add zeros)
         const int c1 = m1 - 1, c2 = m2 - 1;
         switch (3 * c1 + c2) {
-        case 0: launch_dft_mm_t<DIR, 1, 4, 1, 4>(a, blocks, lds, st); break;
-        case 1: launch_dft_mm_t<DIR, 1, 4, 2, 8>(a, blocks, lds, st); break;
-        case 2: launch_dft_mm_t<DIR, 1, 4, 3, 12>(a, blocks, lds, st); break;
-        case 3: launch_dft_mm_t<DIR, 2, 8, 1, 4>(a, blocks, lds, st); break;
-        case 4: launch_dft_mm_t<DIR, 2, 8, 2, 8>(a, blocks, lds, st); break;
-        case 5: launch_dft_mm_t<DIR, 2, 8, 3, 12>(a, blocks, lds, st); break;
-        case 6: launch_dft_mm_t<DIR, 3, 12, 1, 4>(a, blocks, lds, st); break;
-        case 7: launch_dft_mm_t<DIR, 3, 12, 2, 8>(a, blocks, lds, st); break;
-        default: launch_dft_mm_t<DIR, 3, 12, 3, 12>(a, blocks, lds, st); break;
+        case 0: launch_dft_mm_t<DIR, 1, 4, 1, 4>(a, st); break;
+        case 1: launch_dft_mm_t<DIR, 1, 4, 2, 8>(a, st); break;
+        case 2: launch_dft_mm_t<DIR, 1, 4, 3, 12>(a, st); break;
+        case 3: launch_dft_mm_t<DIR, 2, 8, 1, 4>(a, st); break;
+        case 4: launch_dft_mm_t<DIR, 2, 8, 2, 8>(a, st); break;
+        case 5: launch_dft_mm_t<DIR, 2, 8, 3, 12>(a, st); break;
+        case 6: launch_dft_mm_t<DIR, 3, 12, 1, 4>(a, st); break;
+        case 7: launch_dft_mm_t<DIR, 3, 12, 2, 8>(a, st); break;
+        default: launch_dft_mm_t<DIR, 3, 12, 3, 12>(a, st); break;
         }
     }
 }
