@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="skip the plan's tile-shape autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM traffic counters)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="no headline line: the mixed form at batch 1, 4, 16, 64, each eager and with HIP-graph "
+                         "replay, one JSON line with maps/s per setting")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="no benchmark: read two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; csv output) "
                          "of 'bench.py --precision mixed --steps 1 --warmup 0 --no-tune --copy-calibration' (one "
@@ -277,6 +280,19 @@ def main():
     args = parse()
     if args.record_traffic:
         record_traffic(args.record_traffic[0], args.record_traffic[1], args)
+        return
+    if args.sweep:
+        if args.gpus != 1:
+            sys.exit(2)
+        rows = []
+        for B in (1, 4, 16, 64):
+            for graph in (False, True):
+                args.graph = graph
+                r = run_form(args, "mixed", B)
+                rows.append({"batch": B, "graph": graph, "maps_per_s": r["value"], "ms_per_call": r["ms_per_step"],
+                             "round_trip_rel_err": r["round_trip_rel_err"]})
+        print(json.dumps({"sweep": "mixed form, L=%d, N=%d, lambda=%g, J0=%d" % (args.L, args.N, args.lam, args.J0),
+                          "rows": rows}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
