@@ -162,6 +162,15 @@ s2w_status b3w_plan_layout(b3w_plan plan, int *nang, int *nrad, int *Lk, int *Nk
 s2w_status b3w_analysis(b3w_plan plan, const double *f, void *wav, double *scal, void *stream);
 s2w_status b3w_synthesis(b3w_plan plan, const void *wav, const double *scal, double *f, void *stream);
 
+/* Spherical-Laguerre transform on the plan's grid (Section 2.3, eq:forward_spherical_laguerre
+ * and eq:inverse_spherical_laguerre): f on the P radial nodes, [B][P][L][2L-1] FP64, and
+ * its coefficients f_lmp, complex interleaved [B][P][L][2L-1] (per p the harmonic layout
+ * of s2w_sht_forward).  Both run in FP64 for either precision of the plan.  Inputs to
+ * b3w_sl_inverse must describe real maps (f_{l,-m,p} = (-1)^m conj(f_lmp)); only m >= 0
+ * entries are read.  Device buffers, stream-ordered; errors as for s2w plans. */
+s2w_status b3w_sl_forward(b3w_plan plan, const double *f, double *flmp, void *stream);
+s2w_status b3w_sl_inverse(b3w_plan plan, const double *flmp, double *f, void *stream);
+
 /* Kernel timing for ball transforms: as s2w_plan_profile / s2w_plan_profile_read. */
 s2w_status b3w_plan_profile(b3w_plan plan, int capacity);
 s2w_status b3w_plan_profile_read(b3w_plan plan, int max, char *names, double *total_ms,

@@ -64,6 +64,8 @@ def _load():
         "b3w_plan_layout": [vp, ip, ip, ip, ip, ip, i64p, dp],
         "b3w_analysis": [vp, vp, vp, vp, vp],
         "b3w_synthesis": [vp, vp, vp, vp, vp],
+        "b3w_sl_forward": [vp, vp, vp, vp],
+        "b3w_sl_inverse": [vp, vp, vp, vp],
         "b3w_plan_profile": [vp, ctypes.c_int],
         "b3w_plan_profile_read": [vp, ctypes.c_int, ctypes.c_char_p, dp, i64p, dp, ip, i64p],
     }
@@ -85,7 +87,7 @@ EXPORTS = ["s2w_plan_create", "s2w_plan_destroy", "s2w_plan_layout", "s2w_analys
            "s2w_last_error", "s2w_host_scales", "s2w_host_filters", "s2w_host_theta_matrix",
            "s2w_host_wigner_d", "s2w_host_laguerre_rule",
            "b3w_plan_create", "b3w_plan_destroy", "b3w_plan_layout", "b3w_analysis", "b3w_synthesis",
-           "b3w_plan_profile", "b3w_plan_profile_read"]
+           "b3w_sl_forward", "b3w_sl_inverse", "b3w_plan_profile", "b3w_plan_profile_read"]
 
 
 def lib():
@@ -351,6 +353,27 @@ class BallPlan:
         f = torch.empty(self.map_shape, dtype=torch.float64, device=self._dev()) if f is None else f
         _check(_lib.b3w_synthesis(self._h, ctypes.c_void_p(wav.data_ptr()), ctypes.c_void_p(scal.data_ptr()),
                                   ctypes.c_void_p(f.data_ptr()), _stream_ptr(torch, self.device)))
+        return f
+
+    def sl_forward(self, f):
+        """Spherical-Laguerre coefficients f_lmp [B, P, L, 2L-1] (complex128) of maps on the nodes."""
+        torch = self._torch
+        if f.dtype != torch.float64 or not f.is_cuda or tuple(f.shape) != self.map_shape or not f.is_contiguous():
+            raise ValueError(f"expected a contiguous float64 CUDA tensor of shape {self.map_shape}")
+        flmp = torch.empty(self.map_shape + (2,), dtype=torch.float64, device=self._dev())
+        _check(_lib.b3w_sl_forward(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(flmp.data_ptr()),
+                                   _stream_ptr(torch, self.device)))
+        return torch.view_as_complex(flmp)
+
+    def sl_inverse(self, flmp):
+        """Maps on the radial nodes from real-map spherical-Laguerre coefficients [B, P, L, 2L-1]."""
+        torch = self._torch
+        if tuple(flmp.shape) != self.map_shape:
+            raise ValueError(f"expected coefficients of shape {self.map_shape}")
+        x = torch.view_as_real(flmp.to(device=self._dev(), dtype=torch.complex128)).contiguous()
+        f = torch.empty(self.map_shape, dtype=torch.float64, device=self._dev())
+        _check(_lib.b3w_sl_inverse(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                                   _stream_ptr(torch, self.device)))
         return f
 
     def profile(self, capacity):

@@ -1496,6 +1496,40 @@ s2w_status b3w_synthesis(b3w_plan p, const void *wav, const double *scal, double
     return post_launch("b3w_synthesis");
 }
 
+// Z and Z^{-1}: per-shell spherical-harmonic transforms (B P shells at a time) and the
+// radial projection onto the Laguerre basis (quadrature weights folded into Zf)
+s2w_status b3w_sl_forward(b3w_plan p, const double *f, double *flmp, void *stream)
+{
+    if (!p || !p->alive) return fail(S2W_EINVAL, "invalid plan");
+    if (!f || !flmp) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    s2w_plan sp = p->sp;
+    const int B = p->B, P = p->P, L = p->L;
+    {
+        BatchScope bs(sp, B * P);
+        sht_forward_internal(sp, f, p->shell, st);
+        ball_radial(p, p->Zf, p->shell, P, p->flmp, P, false, st);
+        s2w::launch_flm_to_ext(p->flmp, flmp, L, B * P, st);
+    }
+    return post_launch("b3w_sl_forward");
+}
+
+s2w_status b3w_sl_inverse(b3w_plan p, const double *flmp, double *f, void *stream)
+{
+    if (!p || !p->alive) return fail(S2W_EINVAL, "invalid plan");
+    if (!f || !flmp) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    s2w_plan sp = p->sp;
+    const int B = p->B, P = p->P, L = p->L;
+    {
+        BatchScope bs(sp, B * P);
+        s2w::launch_flm_from_ext(flmp, p->flmp, L, B * P, st);
+        ball_radial(p, p->Zi, p->flmp, P, p->shell, P, false, st);
+        sht_inverse_internal(sp, p->shell, f, st);
+    }
+    return post_launch("b3w_sl_inverse");
+}
+
 s2w_status b3w_plan_profile(b3w_plan p, int capacity)
 {
     if (!p || !p->alive) return fail(S2W_EINVAL, "invalid plan");

@@ -105,3 +105,23 @@ def test_ball_mixed_small():
     assert _rel(scal[1].cpu().numpy(), sr) < 1e-6
     f2 = plan.synthesis(wav, scal).cpu().numpy()
     assert _rel(f2, f) < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_spherical_laguerre_transform_against_oracle(prec):
+    """b3w_sl_forward / b3w_sl_inverse (FP64 for either plan precision) against the
+    oracle's forward and inverse spherical-Laguerre transforms, 3 maps, ragged L and P."""
+    torch = _torch()
+    import paper_2402_01282_amd as s2w
+    L, N, P, B = 13, 3, 11, 3
+    print(f"[spherical-Laguerre L={L} P={P} B={B} {prec}]", flush=True)
+    BP = ball.BallPlan(L, N, P, 2.0, 2.0, 0, 0, 0.8)
+    plan = s2w.BallPlan(L, N, P, 2.0, 2.0, 0, 0, 0.8, batch=B, device=0,
+                        precision=s2w.S2W_MIXED if prec == "mixed" else s2w.S2W_FP64)
+    flmp, f = _maps(L, P, BP, B, 9)
+    got = plan.sl_forward(torch.from_numpy(f).cuda()).cpu().numpy()
+    for b in range(B):
+        assert _rel(got[b], ball.sl_forward(f[b], BP)) < 1e-12, b
+        assert _rel(got[b], flmp[b]) < 1e-12, b
+    back = plan.sl_inverse(torch.from_numpy(np.stack(flmp))).cpu().numpy()
+    assert _rel(back, f) < 1e-12
