@@ -252,9 +252,13 @@ __global__ __launch_bounds__(64 * W, 2) void k_lsum_mm(const LsumArgs a, const M
 // slices alternate between two buffers by chunk parity: a wave orders its own
 // slice with a wave-level fence, and one block barrier per chunk separates the
 // partial products from their sum (the next chunk writes the other buffer, whose
-// last readers finished before this chunk's barrier).
+// last readers finished before this chunk's barrier).  The (m, n) row of
+// recursion coefficients is staged in LDS once per block, and every LDS address
+// of the chunk loop is a per-lane base plus a constant (rows of 17 floats), so
+// that the loop holds no per-step address registers.
 
-constexpr int TS_RS = 64 * 17;         // floats per wave slice: d [64][16] or partial [64 col][17]
+constexpr int TS_RS = 64 * 17;         // floats per wave slice: d [64 theta][17] or partial [64 col][17]
+constexpr int TS_CPAD = 16;            // coefficient entries past L (zero) read by the last chunk
 
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -263,16 +267,16 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int NS>
+template <int NS, int NWC>
 __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn in, const double *__restrict__ rA,
                                                   const double *__restrict__ rB)
 {
-    // rA, rB alias a.A, a.B_: as restrict arguments they are known not to be written by
-    // this kernel's stores, so their wave-uniform reads become scalar loads
-    extern __shared__ float sm[];      // [2][NW][TS_RS]
+    // NWC: the number of waves when fixed at compile time (16 for L > 960), else 0
+    // rA, rB alias a.A, a.B_ (restrict: not written by this kernel)
+    extern __shared__ double2 smc[];   // [L + TS_CPAD] (A_l, B_l), then [2][NW][TS_RS] floats
     const int m = blockIdx.x, ni = blockIdx.y, g = blockIdx.z;
     const int L = a.L;
-    const int NW = blockDim.x >> 6;
+    const int NW = NWC > 0 ? NWC : blockDim.x >> 6;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int n = a.nval[ni], ng = a.nglob[ni];
     const int an = n < 0 ? -n : n;
@@ -308,6 +312,16 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
     }
 
     const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
+    double2 *cf = smc;
+    float *sm = reinterpret_cast<float *>(smc + L + TS_CPAD);
+    for (int l = l0 + (int)threadIdx.x; l < L + TS_CPAD; l += blockDim.x) {
+        double2 v = {0.0, 0.0};
+        if (l < L) {
+            v.x = rA[tabm + l];
+            v.y = rB[tabm + l];
+        }
+        cf[l] = v;
+    }
     double c = 0.0, cl = 0.0, e = 0.0, ep = 0.0;
     int k = 0;
     if (valid && l0 < L) {
@@ -319,28 +333,34 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
                     a.sh[th], a.ceps[th], a.seps[th], e, k);
     }
 
+    // this thread's first reduction output (column rcol, degree lb + rli of each chunk):
+    // its scale-factor rows and output row are resolved once per block
+    const int rcol = 2 * ((int)threadIdx.x >> 5) + ((int)threadIdx.x & 1), rli = ((int)threadIdx.x >> 1) & 15;
+    const int rcg = g * 64 + rcol;
+    const bool rok = rcg < ncols;
+    const int rs = rok ? rcg / (2 * B) : 0;
+    const int rrem = rok ? rcg - rs * 2 * B : 0;
+    const double *Srow = a.S + tabm;
+    const double *wrow = a.w[rs] + (size_t)ni * a.wstride;
+    double *orow = in.out[rs] + ((((size_t)(rrem >> 1) * a.mcount + m) * a.nn + ni) * L) * 2 + (rrem & 1);
+
+    __syncthreads();                   // coefficient row staged
+
     int par = 0;
     for (int lb = l0; lb < L; lb += 16, par ^= 1) {
         float *Dw = sm + (size_t)(par * NW + w) * TS_RS;
-        // scale factors of this thread's first output of the chunk, loaded before the
-        // chunk's recursion and matrix-core work so that their latency is hidden
-        double s0 = 0.0, w0 = 0.0;
-        {
-            const int t = threadIdx.x, col = 2 * (t >> 5) + (t & 1), l = lb + ((t >> 1) & 15), cg = g * 64 + col;
-            if (t < 1024 && l < L && cg < ncols) {
-                s0 = a.S[tabm + l];
-                w0 = a.w[cg / (2 * B)][(size_t)ni * a.wstride + l];
-            }
-        }
-        // d chunk, swizzled [theta][l ^ (theta & 15)] so that both the per-step writes and the
-        // MFMA A-operand reads avoid bank conflicts
-#pragma unroll 4
+        // scale factors of this thread's first output of the chunk, loaded (without a
+        // branch, degree clamped) before the chunk's recursion and matrix-core work
+        const int lr = lb + rli < L ? lb + rli : L - 1;
+        const double s0 = Srow[lr], w0 = wrow[lr];
+        // d chunk [theta][17]: lane theta writes its row (the odd row length spreads the
+        // 64 lanes over distinct banks); coefficients past L are zero
+        float *Dl = Dw + lane * 17;
+#pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const int l = lb + i;
-            double A = 0.0, Bv = 0.0;
-            if (l < L) { A = rA[tabm + l]; Bv = rB[tabm + l]; }
-            Dw[lane * 16 + (i ^ (lane & 15))] = (valid && k == 0) ? (float)e : 0.f;
-            const double en = fma(fma(A, cl, fma(A, c, -Bv)), e, -ep);
+            const double2 ab = cf[lb + i];
+            Dl[i] = (valid && k == 0) ? (float)e : 0.f;
+            const double en = fma(fma(ab.x, cl, fma(ab.x, c, -ab.y)), e, -ep);
             ep = e;
             e = en;
             if ((i & 7) == 7 && k < 0 && fabs(e) > 0x1p256) {
@@ -353,10 +373,11 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
         f4 pacc[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) pacc[j] = f4{0, 0, 0, 0};
+        // A[l = lane%16][theta = 4 ks + lane/16]
+        const float *Da = Dw + (lane >> 4) * 17 + (lane & 15);
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks) {
-            const int tl = 4 * ks + (lane >> 4);
-            const float av = Dw[tl * 16 + ((lane & 15) ^ (tl & 15))];   // A[l = lane%16][theta = tl]
+            const float av = Da[68 * ks];
 #pragma unroll
             for (int j = 0; j < 4; ++j) pacc[j] = mfma16(av, hb[ks][j], pacc[j]);
         }
@@ -368,19 +389,40 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
 #pragma unroll
             for (int r = 0; r < 4; ++r) Dw[(16 * j + (lane & 15)) * 17 + 4 * (lane >> 4) + r] = pacc[j][r];
         __syncthreads();
+        // the scale product is formed here: the empty asm keeps the compiler from waiting
+        // on the two loads before the matrix-core section
+        double sc0 = s0, wc0 = w0;
+        asm volatile("" : "+v"(sc0), "+v"(wc0));
         // thread -> (column pair, l, re/im) so that a map's 16 degrees x (re, im) are written contiguously
         const float *Pb = sm + (size_t)par * NW * TS_RS;
-        for (int t = threadIdx.x; t < 1024; t += blockDim.x) {
+        for (int t = threadIdx.x; t < 1024; t += 64 * NW) {
             const int col = 2 * (t >> 5) + (t & 1), li = (t >> 1) & 15;
             const int l = lb + li, cg = g * 64 + col;
+            // all NW (<= 16) partials are read before the sum, which runs in wave order
+            const float *pp = Pb + col * 17 + li;
+            float pv[16];
+#pragma unroll
+            for (int ww = 0; ww < 16; ++ww) {
+                if (NWC == 16) {
+                    pv[ww] = pp[ww * TS_RS];
+                } else {
+                    const float x = pp[(ww < NW ? ww : 0) * TS_RS];
+                    pv[ww] = ww < NW ? x : 0.f;
+                }
+            }
             double v = 0.0;
-            for (int ww = 0; ww < NW; ++ww) v += (double)Pb[(size_t)ww * TS_RS + col * 17 + li];
+#pragma unroll
+            for (int ww = 0; ww < 16; ++ww) v += (double)pv[ww];
             if (l < L && cg < ncols) {
-                const int s = cg / (2 * B);
-                const int rem = cg - s * 2 * B;
-                const int b = rem >> 1, cc = rem & 1;
-                const double sc = t == (int)threadIdx.x ? s0 * w0 : a.S[tabm + l] * a.w[s][(size_t)ni * a.wstride + l];
-                in.out[s][((((size_t)b * a.mcount + m) * a.nn + ni) * L + l) * 2 + cc] = v * sc;
+                if (t == (int)threadIdx.x) {
+                    orow[(size_t)l * 2] = v * (sc0 * wc0);
+                } else {
+                    const int s = cg / (2 * B);
+                    const int rem = cg - s * 2 * B;
+                    const int b = rem >> 1, cc = rem & 1;
+                    const double sc = a.S[tabm + l] * a.w[s][(size_t)ni * a.wstride + l];
+                    in.out[s][((((size_t)b * a.mcount + m) * a.nn + ni) * L + l) * 2 + cc] = v * sc;
+                }
             }
         }
     }
@@ -424,9 +466,15 @@ void launch_tsum_mm(const TsumArgs &a, const MixIn &in, int NS, hipStream_t st)
     const int NW = (a.L + 63) / 64;
     const int ngrp = (2 * in.B * NS + 63) / 64;
     dim3 grid(a.mcount, a.nn, ngrp);
-    const size_t smem = sizeof(float) * 2 * TS_RS * (size_t)NW;   // 139 KB at NW = 16
-    if (NS == 1) hipLaunchKernelGGL(k_tsum_mm<1>, grid, dim3(64 * NW), smem, st, a, in, a.A, a.B_);
-    else hipLaunchKernelGGL(k_tsum_mm<2>, grid, dim3(64 * NW), smem, st, a, in, a.A, a.B_);
+    // 155 KB at L = 1024: coefficient row 16.6 KB + slices 139 KB
+    const size_t smem = sizeof(double2) * (size_t)(a.L + TS_CPAD) + sizeof(float) * 2 * TS_RS * (size_t)NW;
+    if (NW == 16) {
+        if (NS == 1) hipLaunchKernelGGL((k_tsum_mm<1, 16>), grid, dim3(64 * NW), smem, st, a, in, a.A, a.B_);
+        else hipLaunchKernelGGL((k_tsum_mm<2, 16>), grid, dim3(64 * NW), smem, st, a, in, a.A, a.B_);
+    } else {
+        if (NS == 1) hipLaunchKernelGGL((k_tsum_mm<1, 0>), grid, dim3(64 * NW), smem, st, a, in, a.A, a.B_);
+        else hipLaunchKernelGGL((k_tsum_mm<2, 0>), grid, dim3(64 * NW), smem, st, a, in, a.A, a.B_);
+    }
 }
 
 // ------------------------------------------------------------ k_dft_mm -----
