@@ -25,16 +25,8 @@ __device__ __forceinline__ f4 mfma16(float a, float b, f4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// lane i's value of v for a wave-uniform lane index i (two scalar moves)
-__device__ __forceinline__ double readlane_d(double v, int i)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), i);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), i);
-    return __hiloint2double(hi, lo);
-}
-
 // ------------------------------------------------------------ k_lsum_mm ----
+
 // C_s[b][ni][m][theta] (complex FP32) = sum_{l >= l0} d^l_mn(theta) w_s[ni][l] flm[b][m][l]
 // W waves per block: wave w owns the 64-theta tile
 // (tb W + w) of one (m, n, group of 64 columns) unit, and the waves share one staged
@@ -42,6 +34,8 @@ __device__ __forceinline__ double readlane_d(double v, int i)
 // chunk are issued before the current chunk's recursion and matrix-core work, as
 // 16-byte (re, im) pairs.  Sums over l accumulate in FP32 on the matrix cores and are
 // carried into a second FP32 accumulator every 64 degrees.
+
+constexpr int LS_CPAD = 16;            // coefficient entries past L (zero) read by the last chunk
 
 template <int NS, int W>
 __global__ __launch_bounds__(64 * W, 2) void k_lsum_mm(const LsumArgs a, const MixOut o)
@@ -67,8 +61,23 @@ __global__ __launch_bounds__(64 * W, 2) void k_lsum_mm(const LsumArgs a, const M
 
     __shared__ float Ds[2][W][16][64 + 4];   // d chunks of each wave [l][theta]; output staging at the end
     __shared__ float Us[2][16][64 + 4];      // coefficient chunks [l][column]
+    // recursion coefficients of this (m, n) row: (A_l, B_l) and S_l for l0 <= l < L + LS_CPAD
+    // (zero past L), staged once per block
+    extern __shared__ double2 lsab[];
+    double *lss = reinterpret_cast<double *>(lsab + L + LS_CPAD);
 
     const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
+    for (int l = l0 + tid; l < L + LS_CPAD; l += 64 * W) {
+        double2 v = {0.0, 0.0};
+        double sv = 0.0;
+        if (l < L) {
+            v.x = a.A[tabm + l];
+            v.y = a.B[tabm + l];
+            sv = a.S[tabm + l];
+        }
+        lsab[l] = v;
+        lss[l] = sv;
+    }
     double c = 0.0, cl = 0.0, e = 0.0, ep = 0.0;
     int k = 0;
     if (valid && l0 < L) {
@@ -131,21 +140,6 @@ __global__ __launch_bounds__(64 * W, 2) void k_lsum_mm(const LsumArgs a, const M
     // the recursion steps of chunk c + 1 (independent instructions that overlap on the
     // VALU and the matrix cores), and one block barrier per chunk suffices (a buffer is
     // rewritten only after the barrier that follows its last reads).
-    // Recursion coefficients: lane i < 16 holds A, B, S of degree l + i of the chunk
-    // whose recursion runs next (Ac) and of the one after (An, fetched ahead).
-    auto coef = [&](int lc, double &A, double &Bv, double &S) {
-        A = 0.0;
-        Bv = 0.0;
-        S = 0.0;
-        if (lane < 16 && lc + lane < L) {
-            A = a.A[tabm + lc + lane];
-            Bv = a.B[tabm + lc + lane];
-            S = a.S[tabm + lc + lane];
-        }
-    };
-    double Ac, Bc, Sc, An, Bn, Sn;
-    coef(l0, Ac, Bc, Sc);
-    coef(l0 + 16, An, Bn, Sn);
     auto stage = [&](int buf) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -155,8 +149,10 @@ __global__ __launch_bounds__(64 * W, 2) void k_lsum_mm(const LsumArgs a, const M
             Us[buf][iq[r] + 1][2 * pc[r] + 1] = (float)(w1[r] * f1[r].y);
         }
     };
-    auto rstep = [&](int buf, int i) {
-        const double A = readlane_d(Ac, i), Bv = readlane_d(Bc, i), S = readlane_d(Sc, i);
+    // recursion step i of the chunk starting at degree lc (wave-uniform LDS reads)
+    auto rstep = [&](int buf, int lc, int i) {
+        const double2 ab = lsab[lc + i];
+        const double A = ab.x, Bv = ab.y, S = lss[lc + i];
         Ds[buf][w][i][lane] = (valid && k == 0) ? (float)(S * e) : 0.f;
         const double en = fma(fma(A, cl, fma(A, c, -Bv)), e, -ep);
         ep = e;
@@ -167,15 +163,12 @@ __global__ __launch_bounds__(64 * W, 2) void k_lsum_mm(const LsumArgs a, const M
             k += 1;
         }
     };
+    __syncthreads();                   // coefficient row staged
     if (l0 < L) {
         stage(0);
         if (l0 + 16 < L) fetch(l0 + 16);
 #pragma unroll 4
-        for (int i = 0; i < 16; ++i) rstep(0, i);
-        Ac = An;
-        Bc = Bn;
-        Sc = Sn;
-        coef(l0 + 32, An, Bn, Sn);
+        for (int i = 0; i < 16; ++i) rstep(0, l0, i);
     }
     __syncthreads();
     int chunk = 0;
@@ -199,13 +192,9 @@ __global__ __launch_bounds__(64 * W, 2) void k_lsum_mm(const LsumArgs a, const M
                 for (int j = 0; j < 4; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
             if (nxt) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) rstep(nb, kk + i);
+                for (int i = 0; i < 4; ++i) rstep(nb, lb + 16, kk + i);
             }
         }
-        Ac = An;
-        Bc = Bn;
-        Sc = Sn;
-        coef(lb + 48, An, Bn, Sn);
         __syncthreads();
         if ((chunk & 3) == 3) {
 #pragma unroll
@@ -450,14 +439,16 @@ void launch_lsum_mm(const LsumArgs &a, const MixOut &o, int NS, hipStream_t st)
     const long nunit = (long)a.mcount * a.nn * ngrp;
     dim3 grid((unsigned)(8L * ntb * ((nunit + 7) / 8)));
     const dim3 blk(64 * W);
+    // coefficient row: 24.6 KB at L = 1024
+    const size_t smem = (sizeof(double2) + sizeof(double)) * (size_t)(a.L + LS_CPAD);
     if (NS == 1) {
-        if (W == 1) hipLaunchKernelGGL((k_lsum_mm<1, 1>), grid, blk, 0, st, a, o);
-        else if (W == 2) hipLaunchKernelGGL((k_lsum_mm<1, 2>), grid, blk, 0, st, a, o);
-        else hipLaunchKernelGGL((k_lsum_mm<1, 4>), grid, blk, 0, st, a, o);
+        if (W == 1) hipLaunchKernelGGL((k_lsum_mm<1, 1>), grid, blk, smem, st, a, o);
+        else if (W == 2) hipLaunchKernelGGL((k_lsum_mm<1, 2>), grid, blk, smem, st, a, o);
+        else hipLaunchKernelGGL((k_lsum_mm<1, 4>), grid, blk, smem, st, a, o);
     } else {
-        if (W == 1) hipLaunchKernelGGL((k_lsum_mm<2, 1>), grid, blk, 0, st, a, o);
-        else if (W == 2) hipLaunchKernelGGL((k_lsum_mm<2, 2>), grid, blk, 0, st, a, o);
-        else hipLaunchKernelGGL((k_lsum_mm<2, 4>), grid, blk, 0, st, a, o);
+        if (W == 1) hipLaunchKernelGGL((k_lsum_mm<2, 1>), grid, blk, smem, st, a, o);
+        else if (W == 2) hipLaunchKernelGGL((k_lsum_mm<2, 2>), grid, blk, smem, st, a, o);
+        else hipLaunchKernelGGL((k_lsum_mm<2, 4>), grid, blk, smem, st, a, o);
     }
 }
 
