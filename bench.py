@@ -65,7 +65,7 @@ def parse():
 
 
 # name a launch carries in the per-kernel timing -> the library kernel symbols it runs
-KERNEL_NAMES = [("tsum_mm", ["k_tsum_mm<"]), ("lsum_mm", ["k_lsum_mm<"]), ("gemm_theta_f32", ["k_gemm<float>"]),
+KERNEL_NAMES = [("tsum_mm", ["k_tsum_mm<", "k_tsum_mm16<"]), ("lsum_mm", ["k_lsum_mm<"]), ("gemm_theta_f32", ["k_gemm<float>"]),
                 ("gemm_theta", ["k_gemm<double>"]), ("dft_c2r_f32", ["k_dft_mm<1,"]),
                 ("dft_r2c_f32", ["k_dft_mm<-1,"]), ("gamma_c2r_f32", ["k_gamma_c2r<float"]),
                 ("gamma_r2c_f32", ["k_gamma_r2c<float"]), ("tsum", ["k_tsum_mm64<", "k_tsum<"]),

@@ -256,30 +256,17 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int NS, int NWC>
-__global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn in, const double *__restrict__ rA,
-                                                  const double *__restrict__ rB)
+// wave w's h slice as MFMA B operands: hb[ks][j] = h[theta = 64 w + 4 ks + lane / 16][col =
+// 64 g + 16 j + lane % 16], zero for theta >= L or col >= 2 B NS
+template <int NS>
+__device__ __forceinline__ void tsum_h_slice(const TsumArgs &a, const MixIn &in, int m, int ni, int g, int w,
+                                             int lane, float (&hb)[16][4])
 {
-    // NWC: the number of waves when fixed at compile time (16 for L > 960), else 0
-    // rA, rB alias a.A, a.B_ (restrict: not written by this kernel)
-    extern __shared__ double2 smc[];   // [L + TS_CPAD] (A_l, B_l), then [2][NW][TS_RS] floats
-    const int m = blockIdx.x, ni = blockIdx.y, g = blockIdx.z;
-    const int L = a.L;
-    const int NW = NWC > 0 ? NWC : blockDim.x >> 6;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int n = a.nval[ni], ng = a.nglob[ni];
-    const int an = n < 0 ? -n : n;
-    const int l0 = m > an ? m : an;
-    const int B = in.B, ncols = 2 * B * NS;
-    const int th = w * 64 + lane;
-    const bool valid = th < L;
-
-    // h slice: hb[ks][j] = h[theta = 64 w + 4 ks + lane / 16][col = 64 g + 16 j + lane % 16]
+    const int L = a.L, B = in.B, ncols = 2 * B * NS;
     const int sig = (m + a.npar) & 1;
     const int mp = m >> 1;
     const size_t sigoff = (sig == 0 ? 0 : (size_t)B * a.M0 * a.nn * 2);
     const int Msig = (sig == 0 ? a.M0 : a.M1);
-    float hb[16][4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int cg = g * 64 + 16 * j + (lane & 15);
@@ -299,6 +286,27 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
             hb[ks][j] = (cok && t2 < L) ? hs[row * L + t2] : 0.f;
         }
     }
+}
+
+template <int NS>
+__global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn in, const double *__restrict__ rA,
+                                                  const double *__restrict__ rB)
+{
+    // rA, rB alias a.A, a.B_ (restrict: not written by this kernel)
+    extern __shared__ double2 smc[];   // [L + TS_CPAD] (A_l, B_l), then [2][NW][TS_RS] floats
+    const int m = blockIdx.x, ni = blockIdx.y, g = blockIdx.z;
+    const int L = a.L;
+    const int NW = blockDim.x >> 6;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n = a.nval[ni], ng = a.nglob[ni];
+    const int an = n < 0 ? -n : n;
+    const int l0 = m > an ? m : an;
+    const int B = in.B, ncols = 2 * B * NS;
+    const int th = w * 64 + lane;
+    const bool valid = th < L;
+
+    float hb[16][4];
+    tsum_h_slice<NS>(a, in, m, ni, g, w, lane, hb);
 
     const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
     double2 *cf = smc;
@@ -392,12 +400,8 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
             float pv[16];
 #pragma unroll
             for (int ww = 0; ww < 16; ++ww) {
-                if (NWC == 16) {
-                    pv[ww] = pp[ww * TS_RS];
-                } else {
-                    const float x = pp[(ww < NW ? ww : 0) * TS_RS];
-                    pv[ww] = ww < NW ? x : 0.f;
-                }
+                const float x = pp[(ww < NW ? ww : 0) * TS_RS];
+                pv[ww] = ww < NW ? x : 0.f;
             }
             double v = 0.0;
 #pragma unroll
@@ -418,6 +422,169 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
     // zero l < l0
     const int nz = (l0 < L ? l0 : L);
     for (int t = threadIdx.x; t < nz * 64; t += blockDim.x) {
+        const int l = t >> 6, col = t & 63, cg = g * 64 + col;
+        if (cg >= ncols) continue;
+        const int s = cg / (2 * B);
+        const int rem = cg - s * 2 * B;
+        const int b = rem >> 1, cc = rem & 1;
+        in.out[s][((((size_t)b * a.mcount + m) * a.nn + ni) * L + l) * 2 + cc] = 0.0;
+    }
+}
+
+// 16-wave form (L > 960) with the phases of consecutive chunks overlapped.  Per chunk a
+// wave reads its 16 A operands of d in two halves; the matrix-core products of the
+// first half are issued between the FP64 cross-wave sum of the previous chunk's
+// partials, and those of the second half, once both halves are in registers, between
+// the recursion steps of the next chunk, which overwrite the wave's d rows.  The
+// partials have their own LDS buffer: one barrier before they are written (every
+// wave has finished summing the previous ones) and one after.  Same arithmetic and
+// summation order as k_tsum_mm.
+
+constexpr int TS16_CPAD = 32;          // coefficient entries past L (zero): the recursion runs for
+                                       // every chunk, including the one after the last
+
+template <int NS>
+__global__ __launch_bounds__(1024) void k_tsum_mm16(const TsumArgs a, const MixIn in, const double *__restrict__ rA,
+                                                    const double *__restrict__ rB)
+{
+    // rA, rB alias a.A, a.B_ (restrict: not written by this kernel)
+    extern __shared__ double2 smc[];   // [L + TS16_CPAD] (A_l, B_l), d rows [16][TS_RS], partials [16][TS_RS]
+    constexpr int NW = 16;
+    const int m = blockIdx.x, ni = blockIdx.y, g = blockIdx.z;
+    const int L = a.L;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n = a.nval[ni], ng = a.nglob[ni];
+    const int an = n < 0 ? -n : n;
+    const int l0 = m > an ? m : an;
+    const int B = in.B, ncols = 2 * B * NS;
+    const int th = w * 64 + lane;
+    const bool valid = th < L;
+
+    float hb[16][4];
+    tsum_h_slice<NS>(a, in, m, ni, g, w, lane, hb);
+
+    const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
+    double2 *cf = smc;
+    float *Dw = reinterpret_cast<float *>(smc + L + TS16_CPAD) + w * TS_RS;
+    const float *P = reinterpret_cast<const float *>(smc + L + TS16_CPAD) + NW * TS_RS;
+    float *Pw = reinterpret_cast<float *>(smc + L + TS16_CPAD) + (NW + w) * TS_RS;
+    for (int l = l0 + (int)threadIdx.x; l < L + TS16_CPAD; l += 64 * NW) {
+        double2 v = {0.0, 0.0};
+        if (l < L) {
+            v.x = rA[tabm + l];
+            v.y = rB[tabm + l];
+        }
+        cf[l] = v;
+    }
+    double c = 0.0, cl = 0.0, e = 0.0, ep = 0.0;
+    int k = 0;
+    if (valid && l0 < L) {
+        c = a.cth[th];
+        cl = a.ctl[th];
+        const int p1 = (m + n) < 0 ? -(m + n) : (m + n);
+        const int p2 = (m - n) < 0 ? -(m - n) : (m - n);
+        start_value(a.smant[(size_t)ng * a.Lrec + m], a.sexp[(size_t)ng * a.Lrec + m], p1, p2, a.ch[th],
+                    a.sh[th], a.ceps[th], a.seps[th], e, k);
+    }
+    // this thread's reduction output (column rcol, degree lb + rli of each chunk)
+    const int rcol = 2 * ((int)threadIdx.x >> 5) + ((int)threadIdx.x & 1), rli = ((int)threadIdx.x >> 1) & 15;
+    const int rcg = g * 64 + rcol;
+    const bool rok = rcg < ncols;
+    const int rs = rok ? rcg / (2 * B) : 0;
+    const int rrem = rok ? rcg - rs * 2 * B : 0;
+    const double *Srow = a.S + tabm;
+    const double *wrow = a.w[rs] + (size_t)ni * a.wstride;
+    double *orow = in.out[rs] + ((((size_t)(rrem >> 1) * a.mcount + m) * a.nn + ni) * L) * 2 + (rrem & 1);
+    const float *Pr = P + rcol * 17 + rli;
+
+    __syncthreads();                   // coefficient row staged
+
+    // recursion step i of the chunk starting at degree lc: d into row `lane` of this wave's slice
+    float *Dl = Dw + lane * 17;
+    auto rstep = [&](int lc, int i) {
+        const double2 ab = cf[lc + i];
+        Dl[i] = (valid && k == 0) ? (float)e : 0.f;
+        const double en = fma(fma(ab.x, cl, fma(ab.x, c, -ab.y)), e, -ep);
+        ep = e;
+        e = en;
+        if ((i & 7) == 7 && k < 0 && fabs(e) > 0x1p256) {
+            e *= 0x1p-512;
+            ep *= 0x1p-512;
+            k += 1;
+        }
+    };
+    if (l0 < L) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) rstep(l0, i);
+    }
+
+    const float *Da = Dw + (lane >> 4) * 17 + (lane & 15);   // A[l = lane%16][theta = 4 ks + lane/16]
+    for (int lb = l0; lb < L; lb += 16) {
+        // scale factors of the previous chunk's output, stored after this chunk's first 8 k steps
+        // (degree clamped to [0, L): on the first chunk there is no previous output)
+        const int lq = lb - 16 + rli;
+        const int lr = lq < 0 ? 0 : (lq < L ? lq : L - 1);
+        const double s0 = Srow[lr], w0 = wrow[lr];
+        wave_lds_sync();               // this wave's d rows of the chunk are written
+        f4 pacc[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pacc[j] = f4{0, 0, 0, 0};
+        // k steps 0..7, with the sum of the previous chunk's partials (read even on the first
+        // chunk, where the result is not stored), then its store
+        double v = 0.0;
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            const float av = Da[68 * ks];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) pacc[j] = mfma16(av, hb[ks][j], pacc[j]);
+            v += (double)Pr[(2 * ks) * TS_RS];
+            v += (double)Pr[(2 * ks + 1) * TS_RS];
+            // keeps each k step's partial reads beside its products (hoisting all of them
+            // ahead would cost 16 registers at the 128-register budget)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (lb > l0) {
+            const int l = lb - 16 + rli;
+            if (l < L && rok) orow[(size_t)l * 2] = v * (s0 * w0);
+        }
+        // k steps 8..11
+#pragma unroll
+        for (int ks = 8; ks < 12; ++ks) {
+            const float av = Da[68 * ks];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) pacc[j] = mfma16(av, hb[ks][j], pacc[j]);
+        }
+        float av[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) av[q] = Da[68 * (q + 12)];
+        wave_lds_sync();               // all A operands read: the rows may be overwritten
+        // k steps 12..15, with the recursion of the next chunk
+#pragma unroll
+        for (int ks = 12; ks < 16; ++ks) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) pacc[j] = mfma16(av[ks - 12], hb[ks][j], pacc[j]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) rstep(lb + 16, 4 * (ks - 12) + i);
+        }
+        __syncthreads();               // every wave has summed the previous partials
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Pw[(16 * j + (lane & 15)) * 17 + 4 * (lane >> 4) + r] = pacc[j][r];
+        __syncthreads();               // this chunk's partials are visible
+    }
+    if (l0 < L) {
+        const int lb = l0 + ((L - 1 - l0) & ~15);  // the last chunk
+        const int l = lb + rli;
+        const double sc = Srow[l < L ? l : L - 1] * wrow[l < L ? l : L - 1];
+        double v = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) v += (double)Pr[ww * TS_RS];
+        if (l < L && rok) orow[(size_t)l * 2] = v * sc;
+    }
+    // zero l < l0
+    const int nz = (l0 < L ? l0 : L);
+    for (int t = threadIdx.x; t < nz * 64; t += 64 * NW) {
         const int l = t >> 6, col = t & 63, cg = g * 64 + col;
         if (cg >= ncols) continue;
         const int s = cg / (2 * B);
@@ -457,14 +624,15 @@ void launch_tsum_mm(const TsumArgs &a, const MixIn &in, int NS, hipStream_t st)
     const int NW = (a.L + 63) / 64;
     const int ngrp = (2 * in.B * NS + 63) / 64;
     dim3 grid(a.mcount, a.nn, ngrp);
-    // 155 KB at L = 1024: coefficient row 16.6 KB + slices 139 KB
-    const size_t smem = sizeof(double2) * (size_t)(a.L + TS_CPAD) + sizeof(float) * 2 * TS_RS * (size_t)NW;
     if (NW == 16) {
-        if (NS == 1) hipLaunchKernelGGL((k_tsum_mm<1, 16>), grid, dim3(64 * NW), smem, st, a, in, a.A, a.B_);
-        else hipLaunchKernelGGL((k_tsum_mm<2, 16>), grid, dim3(64 * NW), smem, st, a, in, a.A, a.B_);
+        // 156 KB: coefficient row 16.9 KB + d rows 69.6 KB + partials 69.6 KB
+        const size_t smem = sizeof(double2) * (size_t)(a.L + TS16_CPAD) + sizeof(float) * 2 * TS_RS * 16;
+        if (NS == 1) hipLaunchKernelGGL(k_tsum_mm16<1>, grid, dim3(1024), smem, st, a, in, a.A, a.B_);
+        else hipLaunchKernelGGL(k_tsum_mm16<2>, grid, dim3(1024), smem, st, a, in, a.A, a.B_);
     } else {
-        if (NS == 1) hipLaunchKernelGGL((k_tsum_mm<1, 0>), grid, dim3(64 * NW), smem, st, a, in, a.A, a.B_);
-        else hipLaunchKernelGGL((k_tsum_mm<2, 0>), grid, dim3(64 * NW), smem, st, a, in, a.A, a.B_);
+        const size_t smem = sizeof(double2) * (size_t)(a.L + TS_CPAD) + sizeof(float) * 2 * TS_RS * (size_t)NW;
+        if (NS == 1) hipLaunchKernelGGL(k_tsum_mm<1>, grid, dim3(64 * NW), smem, st, a, in, a.A, a.B_);
+        else hipLaunchKernelGGL(k_tsum_mm<2>, grid, dim3(64 * NW), smem, st, a, in, a.A, a.B_);
     }
 }
 
