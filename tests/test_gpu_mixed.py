@@ -117,3 +117,43 @@ def test_mixed_L1024_N8_B64():
     e = _rel(got, ref)
     print(f"  top scale rel err {e:.2e}", flush=True)
     assert e < TOL
+
+
+def test_mixed_ragged_L1000_N3():
+    """L=1000 (above 960: the 16-wave theta contraction, whose last wave holds 40 samples),
+    N=3, three maps: every scale of the analysis against the oracle for two maps; the
+    synthesis of the oracle's coefficients against the input map (the transform
+    reconstructs exactly, so that map is the synthesis' exact value); the round trip."""
+    torch = _torch()
+    print("[mixed L=1000 N=3 B=3]", flush=True)
+    L, N, J0, B = 1000, 3, 0, 3
+    import paper_2402_01282_amd as s2w
+    plan = _plan(L, N, J0, B)
+    P = wavelets.Plan(L, N, 2.0, J0)
+    flm = np.stack([S.sphere_flm(L, S.stream_key(5, b)) for b in range(B)])
+    p64 = s2w.Plan(L, N, 2.0, J0, batch=B, device=0)
+    f = p64.sht_inverse(torch.from_numpy(flm).cuda())
+    wav, scal = plan.analysis(f)
+    views = plan.wav_views(wav)
+    packed = torch.zeros(plan.wav_offset[-1], dtype=torch.float32, device="cuda")
+    pv = plan.wav_views(packed)
+    sc = torch.zeros(plan.scal_shape, dtype=torch.float64, device="cuda")
+    for b in (0, B - 1):
+        wr, sr = wavelets.analysis_lm(flm[b], P)
+        es = [_rel(views[k][b].double().cpu().numpy(), w) for k, w in enumerate(wr)]
+        print(f"  map {b} per-scale rel err: " + " ".join(f"{x:.1e}" for x in es), flush=True)
+        assert max(es) < TOL
+        assert _rel(scal[b].cpu().numpy(), sr) < TOL
+        for k, w in enumerate(wr):
+            pv[k][b].copy_(torch.from_numpy(w).float())
+        sc[b].copy_(torch.from_numpy(sr))
+    g = plan.synthesis(packed, sc)
+    for b in (0, B - 1):
+        e = (torch.linalg.norm(g[b] - f[b]) / torch.linalg.norm(f[b])).item()
+        print(f"  map {b} synthesis of the oracle's coefficients rel err {e:.2e}", flush=True)
+        assert e < TOL
+    assert torch.count_nonzero(g[1]).item() == 0
+    f2 = plan.synthesis(wav, scal)
+    errs = [(torch.linalg.norm(f2[b] - f[b]) / torch.linalg.norm(f[b])).item() for b in range(B)]
+    print(f"  round trip rel err: max {max(errs):.2e}", flush=True)
+    assert max(errs) < TOL
