@@ -729,14 +729,16 @@ __device__ __forceinline__ void dft_mm_stage(float2 *Z, const float2 *F, int n, 
 
 // c2r (DIR = +1): Hermitian rows E (m < Lh, complex FP32) -> real rows of length n.
 // r2c (DIR = -1): real rows (Tin) -> X_m = scale sum_a x(a) e^{-2 pi i m a/n}, m < Lh.
-template <int DIR, typename Tin, int MT1, int KS1, int MT2, int KS2>
+// N1C, N2C, RC: the factors n1, n2 and the row pairs per block when fixed at compile time
+// (then every index map, stride and stage bound folds to constants), else 0
+template <int DIR, typename Tin, int MT1, int KS1, int MT2, int KS2, int N1C = 0, int N2C = 0, int RC = 0>
 __global__ __launch_bounds__(256, 3) void k_dft_mm(const DftArgs a)
 {
     extern __shared__ __align__(16) unsigned char dmm_smem[];
     float2 *Z = reinterpret_cast<float2 *>(dmm_smem);
-    const int n = a.n, Lh = (n + 1) / 2, R = a.rpb;
+    const int n1 = N1C > 0 ? N1C : a.n1, n2 = N2C > 0 ? N2C : a.n2;
+    const int n = N1C > 0 ? N1C * N2C : a.n, Lh = (n + 1) / 2, R = RC > 0 ? RC : a.rpb;
     const int tid = threadIdx.x, NT = blockDim.x;
-    const int n1 = a.n1, n2 = a.n2;
     float2 *F1 = Z + (size_t)R * n, *F2 = F1 + MT1 * KS1 * 64;
     dft_frag_load<MT1, KS1>(a.frag1, F1);
     dft_frag_load<MT2, KS2>(a.frag2, F2);
@@ -918,6 +920,20 @@ static void launch_dft_mm_t(DftArgs a, hipStream_t st)
     const long ngroups = ((a.nrows + 1) / 2 + R - 1) / R;
     // blocks loop over row groups: enough for every CU several times over
     const int blocks = (int)std::min<long>(ngroups, 2048);
+    // 2047 = 23 x 89 (L = 1024, the two top scales) with all sizes as constants
+    constexpr bool top = MT1 == 1 && KS1 == 3 && MT2 == 3 && KS2 == 12;
+    if (top && a.n1 == 23 && a.n2 == 89 && R == 2) {
+        if (DIR > 0) hipLaunchKernelGGL((k_dft_mm<1, float, MT1, KS1, MT2, KS2, 23, 89, 2>), dim3(blocks), dim3(256), lds, st, a);
+        else hipLaunchKernelGGL((k_dft_mm<-1, float, MT1, KS1, MT2, KS2, 23, 89, 2>), dim3(blocks), dim3(256), lds, st, a);
+        return;
+    }
+    // 1023 = 31 x 33 (L = 512)
+    constexpr bool l512 = MT1 == 1 && KS1 == 4 && MT2 == 2 && KS2 == 5;
+    if (l512 && a.n1 == 31 && a.n2 == 33 && R == 4) {
+        if (DIR > 0) hipLaunchKernelGGL((k_dft_mm<1, float, MT1, KS1, MT2, KS2, 31, 33, 4>), dim3(blocks), dim3(256), lds, st, a);
+        else hipLaunchKernelGGL((k_dft_mm<-1, float, MT1, KS1, MT2, KS2, 31, 33, 4>), dim3(blocks), dim3(256), lds, st, a);
+        return;
+    }
     if (DIR > 0) hipLaunchKernelGGL((k_dft_mm<1, float, MT1, KS1, MT2, KS2>), dim3(blocks), dim3(256), lds, st, a);
     else hipLaunchKernelGGL((k_dft_mm<-1, float, MT1, KS1, MT2, KS2>), dim3(blocks), dim3(256), lds, st, a);
 }
