@@ -288,6 +288,21 @@ __device__ __forceinline__ void tsum_h_slice(const TsumArgs &a, const MixIn &in,
     }
 }
 
+// out[s][b][m][ni][l] = 0 for l < nz (d^l_mn vanishes below max(|m|, |n|)) for this block's
+// 32 column pairs: a pair (re, im of one scale and map) owns a contiguous run of nz (re, im)
+// values, written as 16-byte stores by blockDim / 32 threads
+__device__ __forceinline__ void tsum_zero_head(const TsumArgs &a, const MixIn &in, int m, int ni, int g, int nz,
+                                               int ncols)
+{
+    const int tpp = blockDim.x >> 5;
+    const int pr = threadIdx.x / tpp, q = threadIdx.x - pr * tpp;
+    const int cg = g * 64 + 2 * pr;
+    if (cg >= ncols) return;
+    const int s = cg / (2 * in.B), b = (cg - s * 2 * in.B) >> 1;
+    double2 *row = reinterpret_cast<double2 *>(in.out[s]) + (((size_t)b * a.mcount + m) * a.nn + ni) * a.L;
+    for (int l = q; l < nz; l += tpp) row[l] = make_double2(0.0, 0.0);
+}
+
 template <int NS>
 __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn in, const double *__restrict__ rA,
                                                   const double *__restrict__ rB)
@@ -419,16 +434,7 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
             }
         }
     }
-    // zero l < l0
-    const int nz = (l0 < L ? l0 : L);
-    for (int t = threadIdx.x; t < nz * 64; t += blockDim.x) {
-        const int l = t >> 6, col = t & 63, cg = g * 64 + col;
-        if (cg >= ncols) continue;
-        const int s = cg / (2 * B);
-        const int rem = cg - s * 2 * B;
-        const int b = rem >> 1, cc = rem & 1;
-        in.out[s][((((size_t)b * a.mcount + m) * a.nn + ni) * L + l) * 2 + cc] = 0.0;
-    }
+    tsum_zero_head(a, in, m, ni, g, l0 < L ? l0 : L, ncols);
 }
 
 // 16-wave form (L > 960) with the phases of consecutive chunks overlapped.  Per chunk a
@@ -582,16 +588,7 @@ __global__ __launch_bounds__(1024) void k_tsum_mm16(const TsumArgs a, const MixI
         for (int ww = 0; ww < NW; ++ww) v += (double)Pr[ww * TS_RS];
         if (l < L && rok) orow[(size_t)l * 2] = v * sc;
     }
-    // zero l < l0
-    const int nz = (l0 < L ? l0 : L);
-    for (int t = threadIdx.x; t < nz * 64; t += 64 * NW) {
-        const int l = t >> 6, col = t & 63, cg = g * 64 + col;
-        if (cg >= ncols) continue;
-        const int s = cg / (2 * B);
-        const int rem = cg - s * 2 * B;
-        const int b = rem >> 1, cc = rem & 1;
-        in.out[s][((((size_t)b * a.mcount + m) * a.nn + ni) * L + l) * 2 + cc] = 0.0;
-    }
+    tsum_zero_head(a, in, m, ni, g, l0 < L ? l0 : L, ncols);
 }
 
 // ------------------------------------------------------------- launchers ---
