@@ -549,15 +549,19 @@ __global__ __launch_bounds__(1024) void k_tsum_mm64(const TsumArgs a, const doub
         }
         __syncthreads();   // the next chunk's d overwrites the slices
     }
-    // zero l < l0
+    // zero l < l0: each of the block's 16 column pairs (re, im of one scale and map) owns a
+    // contiguous run of nz (re, im) values, written by blockDim / 16 threads along l
     const int nz = (l0 < L ? l0 : L);
-    for (int t = threadIdx.x; t < nz * 32; t += blockDim.x) {
-        const int l = t >> 5, col = t & 31, cg = g * 32 + col;
-        if (cg >= ncols) continue;
-        const int s = cg / (2 * B);
-        const int rem = cg - s * 2 * B;
-        const int b = rem >> 1, cc = rem & 1;
-        a.out[s][((((size_t)b * a.mcount + m) * a.nn + ni) * L + l) * 2 + cc] = 0.0;
+    const int tpp = blockDim.x >> 4;
+    const int pz = threadIdx.x / tpp, qz = threadIdx.x - pz * tpp;
+    const int cz = g * 32 + 2 * pz;
+    if (cz < ncols) {
+        const int s = cz / (2 * B), b = (cz - s * 2 * B) >> 1;
+        double *row = a.out[s] + (((size_t)b * a.mcount + m) * a.nn + ni) * L * 2;
+        for (int l = qz; l < nz; l += tpp) {
+            row[2 * l] = 0.0;
+            row[2 * l + 1] = 0.0;
+        }
     }
 }
 
