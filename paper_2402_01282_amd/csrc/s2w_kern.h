@@ -89,7 +89,7 @@ struct GammaArgs {
 };
 
 struct CombineTerm {
-    const double *P;             // [B][L][nn][L] complex
+    const double *P;             // [B][L][nn][L] complex, read at l >= m only
     int L, nn;
     double phr, phi;
 };
@@ -109,7 +109,7 @@ struct MixOut {
 struct MixIn {
     int B;
     const float *h[MAX_NS];      // sigma-grouped rows, FP32
-    double *out[MAX_NS];         // [B][mcount][nn][L] complex FP64
+    double *out[MAX_NS];         // [B][mcount][nn][L] complex FP64, defined for l >= m
 };
 void launch_lsum_mm(const LsumArgs &a, const MixOut &o, int NS, hipStream_t st);
 void launch_tsum_mm(const TsumArgs &a, const MixIn &in, int NS, hipStream_t st);

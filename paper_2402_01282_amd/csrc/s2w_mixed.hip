@@ -288,9 +288,10 @@ __device__ __forceinline__ void tsum_h_slice(const TsumArgs &a, const MixIn &in,
     }
 }
 
-// out[s][b][m][ni][l] = 0 for l < nz (d^l_mn vanishes below max(|m|, |n|)) for this block's
-// 32 column pairs: a pair (re, im of one scale and map) owns a contiguous run of nz (re, im)
-// values, written as 16-byte stores by blockDim / 32 threads
+// out[s][b][m][ni][l] = 0 for m <= l < nz (d^l_mn vanishes below max(|m|, |n|)) for this
+// block's 32 column pairs: a pair (re, im of one scale and map) owns a contiguous run of
+// (re, im) values, written as 16-byte stores by blockDim / 32 threads.  The rows are read
+// only at l >= m (by the sum over n and scales), so entries below m are left as they are.
 __device__ __forceinline__ void tsum_zero_head(const TsumArgs &a, const MixIn &in, int m, int ni, int g, int nz,
                                                int ncols)
 {
@@ -300,7 +301,7 @@ __device__ __forceinline__ void tsum_zero_head(const TsumArgs &a, const MixIn &i
     if (cg >= ncols) return;
     const int s = cg / (2 * in.B), b = (cg - s * 2 * in.B) >> 1;
     double2 *row = reinterpret_cast<double2 *>(in.out[s]) + (((size_t)b * a.mcount + m) * a.nn + ni) * a.L;
-    for (int l = q; l < nz; l += tpp) row[l] = make_double2(0.0, 0.0);
+    for (int l = m + q; l < nz; l += tpp) row[l] = make_double2(0.0, 0.0);
 }
 
 template <int NS>
