@@ -182,9 +182,9 @@ def source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` from the committed PMC summary, if it was taken
-    on the current sources and the same workload (else None)."""
+def recorded_traffic_entry(kernel, workload):
+    """The committed PMC record of `kernel` (bytes per launch, launches in the profiled
+    round trip), if it was taken on the current sources and the same workload (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -197,7 +197,13 @@ def recorded_traffic(kernel, workload):
     ent = rec.get("kernels", {}).get(kernel)
     if not ent or ent.get("workload") != workload:
         return None
-    return ent.get("bytes_per_launch")
+    return ent
+
+
+def recorded_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed PMC summary, or None."""
+    ent = recorded_traffic_entry(kernel, workload)
+    return ent.get("bytes_per_launch") if ent else None
 
 
 def run_form(args, precision, B):
@@ -268,6 +274,26 @@ def run_form(args, precision, B):
                            "algorithmic_flop_per_launch": flop / max(cnt, 1)}
         out["kernel_breakdown_ms_per_step"] = {k: v[0] / args.steps for k, v in
                                                sorted(kern.items(), key=lambda kv: -kv[1][0])}
+        # every timed kernel against its compute peak (algorithmic flops as for the dominant
+        # one; the DFT figure is FFT-equivalent) and, where PMC traffic was recorded for this
+        # workload on the current sources, against HBM
+        per = {}
+        for k, (kms, kcnt, kflop) in sorted(kern.items(), key=lambda kv: -kv[1][0]):
+            if kms <= 0:
+                continue
+            kpk = PEAKS["fp32_mfma"] if (k.endswith("_mm") or k.endswith("_f32")) else PEAKS["fp64_valu"]
+            rate = kflop / (kms * 1e-3)
+            e = {"ms_per_step": kms / args.steps, "tflops": rate / 1e12, "frac_of_compute_peak": rate / kpk}
+            # only where the profiled round trip had the same launches as a timed step (the
+            # FP64 l-sum record also counts the syntheses of the input maps)
+            ent = recorded_traffic_entry(k, workload)
+            tb = ent.get("bytes_per_launch") if ent else None
+            if tb and ent.get("launches") * args.steps == kcnt:
+                bw = tb * kcnt / (kms * 1e-3)
+                e["hbm_gbps"] = bw / 1e9
+                e["frac_of_hbm_peak"] = bw / PEAKS["hbm"]
+            per[k] = e
+        out["kernel_rooflines"] = per
         out["kernel_time_fraction_of_step"] = tot / (1e3 * dt)
         if dropped:
             out["kernel_timing_dropped_launches"] = dropped
@@ -324,7 +350,7 @@ def main():
         "coefficients_per_s": head["coefficients_per_s"],
         "round_trip_rel_err": head["round_trip_rel_err"],
     }
-    for k in ("roofline", "kernel_breakdown_ms_per_step", "kernel_time_fraction_of_step",
+    for k in ("roofline", "kernel_breakdown_ms_per_step", "kernel_rooflines", "kernel_time_fraction_of_step",
               "kernel_timing_dropped_launches"):
         if k in head:
             out[k] = head[k]
