@@ -438,14 +438,14 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
     tsum_zero_head(a, in, m, ni, g, l0 < L ? l0 : L, ncols);
 }
 
-// 16-wave form (L > 960) with the phases of consecutive chunks overlapped.  Per chunk a
-// wave reads its 16 A operands of d in two halves; the matrix-core products of the
-// first half are issued between the FP64 cross-wave sum of the previous chunk's
-// partials, and those of the second half, once both halves are in registers, between
-// the recursion steps of the next chunk, which overwrite the wave's d rows.  The
-// partials have their own LDS buffer: one barrier before they are written (every
-// wave has finished summing the previous ones) and one after.  Same arithmetic and
-// summation order as k_tsum_mm.
+// 16-wave form (L > 960) with the phases of consecutive chunks overlapped.  Per chunk the
+// matrix-core products of k steps 0-7 are issued between the reads and FP64 additions of
+// the cross-wave sum of the previous chunk's partials; k steps 8-11 follow; the A operands
+// of k steps 12-15 are then read together, after which their products are issued between
+// the recursion steps of the next chunk, which overwrite the wave's d rows.  The partials
+// have their own LDS buffer: one barrier before they are written (every wave has finished
+// summing the previous ones) and one after.  Same arithmetic and summation order as
+// k_tsum_mm.
 
 constexpr int TS16_CPAD = 32;          // coefficient entries past L (zero): the recursion runs for
                                        // every chunk, including the one after the last
