@@ -257,34 +257,44 @@ __device__ __forceinline__ void wave_lds_sync()
 }
 
 // wave w's h slice as MFMA B operands: hb[ks][j] = h[theta = 64 w + 4 ks + lane / 16][col =
-// 64 g + 16 j + lane % 16], zero for theta >= L or col >= 2 B NS
+// 64 g + 16 j + lane % 16], zero for theta >= L or col >= 2 B NS.  A column's h row is
+// contiguous in theta, so each 16-column group is read one row per load (lane = theta,
+// 256 bytes per row), written to the wave's LDS slice T [16][65] and read back in the
+// operand layout.  T (at least 1040 floats) is the wave's own slice, not yet in use.
 template <int NS>
 __device__ __forceinline__ void tsum_h_slice(const TsumArgs &a, const MixIn &in, int m, int ni, int g, int w,
-                                             int lane, float (&hb)[16][4])
+                                             int lane, float (&hb)[16][4], float *T)
 {
     const int L = a.L, B = in.B, ncols = 2 * B * NS;
     const int sig = (m + a.npar) & 1;
     const int mp = m >> 1;
     const size_t sigoff = (sig == 0 ? 0 : (size_t)B * a.M0 * a.nn * 2);
     const int Msig = (sig == 0 ? a.M0 : a.M1);
+    const int th = w * 64 + lane;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int cg = g * 64 + 16 * j + (lane & 15);
-        int s = 0, b = 0, cc = 0;
-        const bool cok = cg < ncols;
-        if (cok) {
-            s = cg / (2 * B);
-            const int rem = cg - s * 2 * B;
-            b = rem >> 1;
-            cc = rem & 1;
-        }
-        const float *hs = in.h[s < NS ? s : 0];
-        const size_t row = sigoff + (((size_t)b * Msig + mp) * a.nn + ni) * 2 + cc;
+        float t[16];
+        // wave-uniform column cg = 64 g + 16 j + c: scale s, and rem = 2 (map) + part, stepped
+        int s = (g * 64 + 16 * j) / (2 * B), rem = g * 64 + 16 * j - s * 2 * B;
 #pragma unroll
-        for (int ks = 0; ks < 16; ++ks) {
-            const int t2 = w * 64 + 4 * ks + (lane >> 4);
-            hb[ks][j] = (cok && t2 < L) ? hs[row * L + t2] : 0.f;
+        for (int c = 0; c < 16; ++c) {
+            const int cg = g * 64 + 16 * j + c;
+            t[c] = 0.f;
+            if (cg < ncols && th < L) {
+                const size_t row = sigoff + (((size_t)(rem >> 1) * Msig + mp) * a.nn + ni) * 2 + (rem & 1);
+                t[c] = in.h[s][row * L + th];
+            }
+            if (++rem == 2 * B) {
+                rem = 0;
+                ++s;
+            }
         }
+#pragma unroll
+        for (int c = 0; c < 16; ++c) T[c * 65 + lane] = t[c];
+        wave_lds_sync();
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) hb[ks][j] = T[(lane & 15) * 65 + 4 * ks + (lane >> 4)];
+        wave_lds_sync();               // read before the next group overwrites T
     }
 }
 
@@ -321,12 +331,12 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
     const int th = w * 64 + lane;
     const bool valid = th < L;
 
+    float *sm = reinterpret_cast<float *>(smc + L + TS_CPAD);
     float hb[16][4];
-    tsum_h_slice<NS>(a, in, m, ni, g, w, lane, hb);
+    tsum_h_slice<NS>(a, in, m, ni, g, w, lane, hb, sm + (size_t)w * TS_RS);
 
     const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
     double2 *cf = smc;
-    float *sm = reinterpret_cast<float *>(smc + L + TS_CPAD);
     for (int l = l0 + (int)threadIdx.x; l < L + TS_CPAD; l += blockDim.x) {
         double2 v = {0.0, 0.0};
         if (l < L) {
@@ -467,12 +477,12 @@ __global__ __launch_bounds__(1024) void k_tsum_mm16(const TsumArgs a, const MixI
     const int th = w * 64 + lane;
     const bool valid = th < L;
 
+    float *Dw = reinterpret_cast<float *>(smc + L + TS16_CPAD) + w * TS_RS;
     float hb[16][4];
-    tsum_h_slice<NS>(a, in, m, ni, g, w, lane, hb);
+    tsum_h_slice<NS>(a, in, m, ni, g, w, lane, hb, Dw);
 
     const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
     double2 *cf = smc;
-    float *Dw = reinterpret_cast<float *>(smc + L + TS16_CPAD) + w * TS_RS;
     const float *P = reinterpret_cast<const float *>(smc + L + TS16_CPAD) + NW * TS_RS;
     float *Pw = reinterpret_cast<float *>(smc + L + TS16_CPAD) + (NW + w) * TS_RS;
     for (int l = l0 + (int)threadIdx.x; l < L + TS16_CPAD; l += 64 * NW) {
