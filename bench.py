@@ -72,6 +72,30 @@ KERNEL_NAMES = [("tsum_mm", ["k_tsum_mm<", "k_tsum_mm16<"]), ("lsum_mm", ["k_lsu
                 ("lsum", ["k_lsum_mm64<", "k_lsum<"])]
 
 
+def is_mixed_kernel(name):
+    """Kernels of the mixed form whose contractions run on FP32 matrix cores."""
+    return name.endswith("_mm") or name.endswith("_f32")
+
+
+def end_to_end(kern, steps, ms_step, L, B, nwav, scal_shape, esz):
+    """The whole step against its roofline: the algorithmic work of one step on each unit
+    (FP64: every flop of the FP64 kernels and the recursion inside the mixed kernels; FP32
+    matrix cores: the rest of the mixed kernels' flops; HBM: reading the maps and writing
+    the coefficients in analysis, reading them and writing the maps in synthesis), each
+    over that unit's peak; the largest of these times over the measured step time."""
+    fp64 = sum(v[3] if is_mixed_kernel(k) else v[2] for k, v in kern.items()) / steps
+    mfma = sum(v[2] - v[3] for k, v in kern.items() if is_mixed_kernel(k)) / steps
+    nmap = L * (2 * L - 1)
+    nscal = scal_shape[1] * scal_shape[2]
+    hbm = B * (2 * 8 * nmap + 2 * esz * nwav + 2 * 8 * nscal)
+    t = {"fp64": fp64 / PEAKS["fp64_valu"], "fp32_mfma": mfma / PEAKS["fp32_mfma"], "hbm": hbm / PEAKS["hbm"]}
+    unit = max(t, key=t.get)
+    return {"bound": unit, "min_ms_per_step": 1e3 * t[unit], "ms_per_step": ms_step,
+            "frac": 1e3 * t[unit] / ms_step,
+            "min_ms_per_unit": {k: 1e3 * v for k, v in t.items()},
+            "work_per_step": {"fp64_flop": fp64, "fp32_mfma_flop": mfma, "hbm_bytes": hbm}}
+
+
 def record_traffic(fetch_dir, write_dir, args):
     """HBM bytes per launch from FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by
     what the same counter reads for the 1 GiB device copy of --copy-calibration."""
@@ -119,12 +143,8 @@ def record_traffic(fetch_dir, write_dir, args):
 
 
 def cpu_baseline(L, N, lam, J0):
-    """Time the oracle on a bounded sample of the workload: the spherical-harmonic
-    transform pair at full size plus the analysis and synthesis of one wavelet scale,
-    scaled to one full round trip by the oracle's own cost model sum_j L_j^3 N_j over
-    the scales.  The scale is the largest with L_j <= L/2, or the top scale when that
-    one is projected to take under 30 s on this host; it is repeated until the sample
-    holds at least 10 s of CPU work."""
+    """Time the oracle on one map of the workload: its full round trip (forward SHT,
+    analysis of every scale, synthesis), the unit the metric counts, on this host's cores."""
     import numpy as np
 
     import synthetic
@@ -133,40 +153,16 @@ def cpu_baseline(L, N, lam, J0):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     P = wavelets.Plan(L, N, lam, J0)
     flm = synthetic.sphere_flm(L, synthetic.stream_key(4))
+    f = np.real(mw.sht_inverse(flm, L))
     mw.delta_table(L)
     t0 = time.perf_counter()
-    f = np.real(mw.sht_inverse(flm, L))
-    flm2 = mw.sht_forward(f, L)
-    t_sht = time.perf_counter() - t0
-    cost = [P.Lj[i] ** 3 * P.Nj[i] for i in range(len(P.scales))]
-
-    def scale_round_trip(k):
-        Lj, Nj = P.Lj[k], P.Nj[k]
-        fl = flm2[:Lj, L - Lj:L + Lj - 1]
-        lj = np.arange(Lj)
-        what = (8 * np.pi ** 2 / (2 * lj + 1))[None, :, None] * fl[None] * np.conj(P.psi(k)).T[:, :, None]
-        t = time.perf_counter()
-        w = mw.wigner_inverse(what, Lj, Nj)
-        _ = mw.wigner_forward(np.real(w), Lj, Nj)
-        return time.perf_counter() - t
-
-    ks = [i for i in range(len(P.scales)) if P.Lj[i] <= max(L // 2, 1)]
-    k = ks[-1] if ks else len(P.scales) - 1
-    t_s = scale_round_trip(k)
-    top = len(P.scales) - 1
-    if k != top and t_s * cost[top] / cost[k] < 30.0:
-        k = top
-        t_s = scale_round_trip(k)
-    # repeat the scale until the sample holds at least 10 s of CPU work; use the mean
-    reps = [t_s]
-    while t_sht + sum(reps) < 10.0:
-        reps.append(scale_round_trip(k))
-    t_s = sum(reps) / len(reps)
-    t_round = t_sht + t_s * sum(cost) / cost[k]
-    return {"value": 1.0 / t_round, "unit": "maps/s", "cores": threads, "kind": "oracle",
-            "sample": (f"oracle SHT pair at L={L} ({t_sht:.1f} s) plus analysis+synthesis of the scale "
-                       f"L_j={P.Lj[k]}, N_j={P.Nj[k]} ({len(reps)} x {t_s:.1f} s), scaled to the full round "
-                       f"trip by sum_j L_j^3 N_j / (L_j^3 N_j) = {sum(cost) / cost[k]:.2f}")}
+    wav, scal = wavelets.analysis(f, P)
+    f2 = wavelets.synthesis(wav, scal, P)
+    t = time.perf_counter() - t0
+    err = float(np.linalg.norm(f2 - f) / np.linalg.norm(f))
+    return {"value": 1.0 / t, "unit": "maps/s", "cores": threads, "kind": "oracle",
+            "sample": (f"one map at L={L}, N={N}, lambda={lam:g}, J0={J0}: the oracle's full analysis + synthesis "
+                       f"round trip ({t:.1f} s, round trip rel err {err:.1e})")}
 
 
 def source_hash():
@@ -254,16 +250,34 @@ def run_form(args, precision, B):
         plan.profile(0)
     err = (torch.linalg.norm(f2 - f) / torch.linalg.norm(f)).item()
     maps_per_s = B * args.steps / dt
+    # gradient of sum_j sum (W^j)^2 with respect to the maps: analysis, then the transpose of
+    # the analysis applied to the cotangent 2 W (timed as a separate loop of the same length)
+    gf = torch.empty_like(f)
+    gscal = torch.zeros_like(scal)
+
+    def grad_step():
+        plan.analysis(f, wav, scal)
+        plan.analysis_adjoint(wav, gscal, gf)
+
+    grad_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        grad_step()
+    torch.cuda.synchronize()
+    dtg = time.perf_counter() - t0
     workload = (f"sphere directional wavelets analysis+synthesis, "
                 f"{'mixed FP32/FP64 batched' if mixed else 'FP64'}, L={L}, N={N}, lambda={lam:g}, J0={J0}, batch={B}")
     out = {"value": maps_per_s, "ms_per_step": 1e3 * dt / args.steps,
            "dtype": "f32+f64" if mixed else "f64", "workload": workload, "batch": B,
-           "coefficients_per_s": maps_per_s * (plan.wav_offset[-1] // B), "round_trip_rel_err": err}
+           "coefficients_per_s": maps_per_s * (plan.wav_offset[-1] // B), "round_trip_rel_err": err,
+           "gradient": {"maps_per_s": B * args.steps / dtg, "ms_per_step": 1e3 * dtg / args.steps,
+                        "what": "analysis + transpose of the analysis (gradient of sum_j sum (W^j)^2)"}}
     if kern:
         tot = sum(v[0] for v in kern.values())
-        name, (ms, cnt, flop) = max(kern.items(), key=lambda kv: kv[1][0])
+        name, (ms, cnt, flop, flop64, dense) = max(kern.items(), key=lambda kv: kv[1][0])
         achieved = flop / (ms * 1e-3) if ms > 0 else 0.0
-        if name.endswith("_mm") or name.endswith("_f32"):
+        if is_mixed_kernel(name):
             peak, bound = PEAKS["fp32_mfma"], "mfma"
         else:
             peak, bound = PEAKS["fp64_valu"], "alu"
@@ -271,19 +285,23 @@ def run_form(args, precision, B):
                            "unit": "TFLOP/s", "frac": achieved / peak,
                            "traffic": recorded_traffic(name, workload),
                            "avg_launch_ms": ms / max(cnt, 1), "launches": cnt,
-                           "algorithmic_flop_per_launch": flop / max(cnt, 1)}
+                           "algorithmic_flop_per_launch": flop / max(cnt, 1),
+                           "dense_flop_per_launch": (dense / max(cnt, 1)) or None,
+                           "dense_tflops": (dense / (ms * 1e-3) / 1e12) if dense and ms > 0 else None}
         out["kernel_breakdown_ms_per_step"] = {k: v[0] / args.steps for k, v in
                                                sorted(kern.items(), key=lambda kv: -kv[1][0])}
         # every timed kernel against its compute peak (algorithmic flops as for the dominant
-        # one; the DFT figure is FFT-equivalent) and, where PMC traffic was recorded for this
-        # workload on the current sources, against HBM
+        # one) and, where PMC traffic was recorded for this workload on the current sources,
+        # against HBM
         per = {}
-        for k, (kms, kcnt, kflop) in sorted(kern.items(), key=lambda kv: -kv[1][0]):
+        for k, (kms, kcnt, kflop, kf64, kdense) in sorted(kern.items(), key=lambda kv: -kv[1][0]):
             if kms <= 0:
                 continue
-            kpk = PEAKS["fp32_mfma"] if (k.endswith("_mm") or k.endswith("_f32")) else PEAKS["fp64_valu"]
+            kpk = PEAKS["fp32_mfma"] if is_mixed_kernel(k) else PEAKS["fp64_valu"]
             rate = kflop / (kms * 1e-3)
             e = {"ms_per_step": kms / args.steps, "tflops": rate / 1e12, "frac_of_compute_peak": rate / kpk}
+            if kdense:
+                e["dense_tflops"] = kdense / (kms * 1e-3) / 1e12
             # only where the profiled round trip had the same launches as a timed step (the
             # FP64 l-sum record also counts the syntheses of the input maps)
             ent = recorded_traffic_entry(k, workload)
@@ -295,6 +313,8 @@ def run_form(args, precision, B):
             per[k] = e
         out["kernel_rooflines"] = per
         out["kernel_time_fraction_of_step"] = tot / (1e3 * dt)
+        out["end_to_end"] = end_to_end(kern, args.steps, 1e3 * dt / args.steps, L, B,
+                                       plan.wav_offset[-1] // B, plan.scal_shape, 4 if mixed else 8)
         if dropped:
             out["kernel_timing_dropped_launches"] = dropped
     del plan, wav, scal, f, f2
@@ -349,9 +369,10 @@ def main():
                    "batch": head["batch"], "form": forms[0], "tuned": not args.no_tune, "graph": args.graph},
         "coefficients_per_s": head["coefficients_per_s"],
         "round_trip_rel_err": head["round_trip_rel_err"],
+        "gradient": head["gradient"],
     }
-    for k in ("roofline", "kernel_breakdown_ms_per_step", "kernel_rooflines", "kernel_time_fraction_of_step",
-              "kernel_timing_dropped_launches"):
+    for k in ("roofline", "end_to_end", "kernel_breakdown_ms_per_step", "kernel_rooflines",
+              "kernel_time_fraction_of_step", "kernel_timing_dropped_launches"):
         if k in head:
             out[k] = head[k]
     if "fp64" in res and forms[0] != "fp64":

@@ -46,7 +46,8 @@ typedef enum {
     S2W_ENOMEM = -2,        /* device or host allocation failed at plan creation */
     S2W_EHIP = -3,          /* HIP runtime error */
     S2W_EUNSUPPORTED = -4,  /* valid but unsupported configuration */
-    S2W_ESTATE = -5         /* plan destroyed or used inconsistently */
+    S2W_ESTATE = -5         /* handle is not a live plan (destroyed, destroyed twice, or never
+                               created); a handle whose memory a later plan reuses is that plan */
 } s2w_status;
 
 typedef enum {
@@ -90,13 +91,30 @@ s2w_status s2w_analysis(s2w_plan plan, const double *f, void *wav, double *scal,
 /* Wavelet synthesis (Algorithm 1, synthesis): coefficients -> real maps. */
 s2w_status s2w_synthesis(s2w_plan plan, const void *wav, const double *scal, double *f, void *stream);
 
-/* Transpose of the analysis map under the real inner product of the sample arrays
- * (the gradient of a loss with respect to f, given its gradient with respect to the
- * coefficients).  It is not the synthesis: MW sampling oversamples, so A^T A != I.
- * gwav has the plan's coefficient type (FP32 for S2W_MIXED plans); the adjoint is
- * evaluated in FP64 with the Wigner d recomputed. */
+/* Wavelet analysis from harmonic coefficients (Algorithm 1 without its first Y; Section
+ * 4.1, eq:wigner_wav_coeffs and eq:harmonic_scal_coeffs): flm -> wavelet and scaling
+ * coefficients.  flm: device, complex interleaved [B][L][2L-1] in the "lm" layout above,
+ * describing real maps (f_{l,-m} = (-1)^m conj(f_lm)); only the m >= 0 entries are read.
+ * wav, scal as for s2w_analysis. */
+s2w_status s2w_analysis_lm(s2w_plan plan, const double *flm, void *wav, double *scal, void *stream);
+
+/* Gradients.  The paper differentiates its transforms automatically (Section 4.3, and
+ * Section 5.2 for the adjoint transforms the ball library provides); here each transform
+ * has a hand-written transpose under the real inner product of the sample arrays (the
+ * gradient of a loss with respect to the transform's input, given its gradient with
+ * respect to the output).  The transposes recompute Wigner d, never store it, and run in
+ * the plan's precision split: FP64 end to end for S2W_FP64 plans; for S2W_MIXED plans the
+ * wavelet-coefficient cotangents are FP32 and their contractions and DFTs run on FP32
+ * matrix cores with the FP64 recursion, harmonic transforms and scale sums, as in the
+ * forward maps.  Buffers and errors as for the forward entry points.
+ *
+ * s2w_analysis_adjoint: (gwav, gscal) -> gf [B][L][2L-1]: transpose of s2w_analysis.  It
+ * is not the synthesis: MW sampling oversamples, so A^T A != I.
+ * s2w_synthesis_adjoint: gf -> (gwav, gscal): transpose of s2w_synthesis. */
 s2w_status s2w_analysis_adjoint(s2w_plan plan, const void *gwav, const double *gscal, double *gf,
                                 void *stream);
+s2w_status s2w_synthesis_adjoint(s2w_plan plan, const double *gf, void *gwav, double *gscal,
+                                 void *stream);
 
 /* Spin-0 spherical-harmonic transforms on the plan's grid (Section 2.1,
  * eq:fswsh / eq:iswsh; the S^2 case of the Wigner transforms).  flm is complex
@@ -108,17 +126,26 @@ s2w_status s2w_sht_inverse(s2w_plan plan, const double *flm, double *f, void *st
 /* Kernel timing (for measurement).  s2w_plan_profile(plan, capacity) with capacity > 0
  * creates `capacity` pairs of HIP events and from then on records one pair around
  * every kernel launch of the transform entry points, on the stream of the call, together
- * with the launch's algorithmic floating-point operation count (the per-unit figures
- * are: 6 flop per Wigner-d recursion step and 4 per complex-by-real multiply-add of a
- * contraction; 5 n log2 n per length-n complex DFT; 2 per multiply-add of a dense product);
- * capacity 0 stops recording and releases the events.  Not to be used under graph capture.
+ * with the launch's algorithmic work; capacity 0 stops recording and releases the events.
+ * Not to be used under graph capture.  Algorithmic work counts what the method needs:
+ * 6 FP64 flop per Wigner-d recursion step (theta, l, m, n), once for all maps and scales of
+ * a launch; 4 flop per complex-by-real multiply-add of a contraction, per map, only at the
+ * degrees inside the scale's filter support; 5 n log2 n per length-n complex DFT (2.5 n
+ * log2 n per real row); for the exact MW theta quadrature, its Fourier route per complex
+ * column (a DFT of the extended column, the Hankel product with the quadrature weights as
+ * a convolution through two FFTs of twice the length, the inverse DFT).  flop64 is the part
+ * on the FP64 units in a mixed-precision kernel (the recursion); dense is what a dense
+ * product issues in place of a cheaper algorithm (2 flop per multiply-add of the theta-
+ * quadrature matrix product; 0 for other kernels).
  * s2w_plan_profile_read synchronises the device, then reports per kernel name (up to `max`
  * names, each at most 31 characters, written to names + 32*i): total milliseconds, launch
- * count and total algorithmic flop since profiling started, and clears the record.
- * Launches beyond the capacity are not recorded (dropped reports their number). */
+ * count, total flop, flop64 and dense since profiling started, and clears the record.  Any
+ * output pointer may be NULL.  Launches beyond the capacity are not recorded (dropped
+ * reports their number). */
 s2w_status s2w_plan_profile(s2w_plan plan, int capacity);
 s2w_status s2w_plan_profile_read(s2w_plan plan, int max, char *names, double *total_ms,
-                                 int64_t *launches, double *flop, int *count, int64_t *dropped);
+                                 int64_t *launches, double *flop, double *flop64, double *dense,
+                                 int *count, int64_t *dropped);
 
 /* ---- ball B^3 = R+ x S^2 (Section 3.2, Section 5: eq:forward_ball_wavelet,
  * eq:synthesis_b3; radial Laguerre basis of Section 2.3; filters of Appendix A.3-A.4) ----
@@ -158,9 +185,19 @@ s2w_status b3w_plan_destroy(b3w_plan plan);
 s2w_status b3w_plan_layout(b3w_plan plan, int *nang, int *nrad, int *Lk, int *Nk, int *Pk,
                            int64_t *wav_offset, double *nodes);
 
-/* Ball wavelet analysis and synthesis (device buffers as laid out above). */
+/* Ball wavelet analysis and synthesis (Algorithm 2; device buffers as laid out above). */
 s2w_status b3w_analysis(b3w_plan plan, const double *f, void *wav, double *scal, void *stream);
 s2w_status b3w_synthesis(b3w_plan plan, const void *wav, const double *scal, double *f, void *stream);
+
+/* Transposes of b3w_analysis and b3w_synthesis under the real inner product of the
+ * sample arrays (the adjoint ball transforms of Section 5.2; gradients as for the sphere
+ * entry points above): b3w_analysis_adjoint (gwav, gscal) -> gf, b3w_synthesis_adjoint
+ * gf -> (gwav, gscal).  Radial stages FP64; the angular stages in the plan's precision
+ * split.  Buffers and errors as for b3w_analysis / b3w_synthesis. */
+s2w_status b3w_analysis_adjoint(b3w_plan plan, const void *gwav, const double *gscal, double *gf,
+                                void *stream);
+s2w_status b3w_synthesis_adjoint(b3w_plan plan, const double *gf, void *gwav, double *gscal,
+                                 void *stream);
 
 /* Spherical-Laguerre transform on the plan's grid (Section 2.3, eq:forward_spherical_laguerre
  * and eq:inverse_spherical_laguerre): f on the P radial nodes, [B][P][L][2L-1] FP64, and
@@ -174,7 +211,8 @@ s2w_status b3w_sl_inverse(b3w_plan plan, const double *flmp, double *f, void *st
 /* Kernel timing for ball transforms: as s2w_plan_profile / s2w_plan_profile_read. */
 s2w_status b3w_plan_profile(b3w_plan plan, int capacity);
 s2w_status b3w_plan_profile_read(b3w_plan plan, int max, char *names, double *total_ms,
-                                 int64_t *launches, double *flop, int *count, int64_t *dropped);
+                                 int64_t *launches, double *flop, double *flop64, double *dense,
+                                 int *count, int64_t *dropped);
 
 /* Message for the last failure on the calling thread. */
 const char *s2w_last_error(void);

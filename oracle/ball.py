@@ -222,3 +222,67 @@ def synthesis_lmp(wav, scal, BP: BallPlan) -> np.ndarray:
 def synthesis(wav, scal, BP: BallPlan) -> np.ndarray:
     """(W^{jj'}, W^Phi) -> real ball map f [P, L, 2L-1]."""
     return sl_inverse(synthesis_lmp(wav, scal, BP), BP)
+
+
+# ------------------------------------------------------------- adjoints ----
+# Literal transposes of the real-linear ball maps above (the adjoint transforms of
+# Section 5.2), stage by stage in reverse order, for the real inner product of the
+# sample arrays.
+
+def _sl_forward_adjoint(g: np.ndarray, BP: BallPlan) -> np.ndarray:
+    """Transpose of sl_forward: cotangent of f_lmp [P, L, 2L-1] -> real map cotangent on the nodes."""
+    L = BP.L
+    y = np.tensordot((BP.rad.K * BP.rad.W[None, :]).T, g, axes=(1, 0))     # [k, L, 2L-1]
+    return np.real(np.stack([mw.sht_forward_adjoint(y[k], L) for k in range(BP.P)]))
+
+
+def _sl_inverse_adjoint(g: np.ndarray, BP: BallPlan) -> np.ndarray:
+    """Transpose of sl_inverse (real maps): map cotangent on the nodes -> cotangent of f_lmp."""
+    L = BP.L
+    gl = np.stack([mw.sht_inverse_adjoint(np.asarray(g[k], dtype=np.complex128), L) for k in range(BP.P)])
+    return np.tensordot(BP.rad.K, gl, axes=(1, 0))
+
+
+def analysis_adjoint(gwav, gscal, BP: BallPlan) -> np.ndarray:
+    """Transpose of analysis(): (g W^{jj'}, g W^Phi) -> g f [P, L, 2L-1]."""
+    L, P = BP.L, BP.P
+    A = BP.ang
+    gflmp = BP.phi[:, :, None] * _sl_inverse_adjoint(gscal, BP)
+    for i in range(len(BP.rscales)):
+        Pj = BP.Pj[i]
+        gg = np.zeros((Pj, L, 2 * L - 1), dtype=np.complex128)     # cotangent of g^{j'}_lm(r'_k)
+        for k in range(len(A.scales)):
+            Lj, Nj = A.Lj[k], A.Nj[k]
+            lj = np.arange(Lj)
+            psi = A.psi(k)
+            for s in range(Pj):
+                ga = mw.wigner_inverse_adjoint(np.asarray(gwav[(i, k)][s], dtype=np.complex128), Lj, Nj)
+                gg[s, :Lj, L - Lj:L + Lj - 1] += np.einsum("nlm,ln->lm", ga, psi) \
+                    * (8 * np.pi ** 2 / (2 * lj + 1))[:, None]
+        Kb = BP.rad_j[i].basis(P)                                   # [p, k]
+        gflmp += np.tensordot(Kb * BP.kappa_p[i][:, None], gg, axes=(1, 0))
+    return _sl_forward_adjoint(gflmp, BP)
+
+
+def synthesis_adjoint(gf, BP: BallPlan):
+    """Transpose of synthesis(): g f [P, L, 2L-1] -> (g W^{jj'}, g W^Phi)."""
+    L, P = BP.L, BP.P
+    A = BP.ang
+    gflmp = _sl_inverse_adjoint(gf, BP)
+    gscal = _sl_forward_adjoint(BP.phi[:, :, None] * gflmp, BP)
+    gwav = {}
+    for i in range(len(BP.rscales)):
+        Pj = BP.Pj[i]
+        Kb = BP.rad_j[i].basis(P)                                   # [p, k]
+        M = Kb * BP.rad_j[i].W[None, :] * BP.kappa_p[i][:, None]
+        gacc = np.tensordot(M.T, gflmp, axes=(1, 0))               # [Pj, L, 2L-1]
+        for k in range(len(A.scales)):
+            Lj, Nj = A.Lj[k], A.Nj[k]
+            psi = A.psi(k)
+            out = []
+            for s in range(Pj):
+                gk = gacc[s, :Lj, L - Lj:L + Lj - 1]
+                g_nlm = np.conj(psi).T[:, :, None] * gk[None, :, :]
+                out.append(np.real(mw.wigner_forward_adjoint(g_nlm, Lj, Nj)))
+            gwav[(i, k)] = np.stack(out)
+    return gwav, gscal

@@ -119,3 +119,25 @@ def analysis_adjoint(gwav, gscal, P: Plan) -> np.ndarray:
         contrib = np.einsum("nlm,ln->lm", ga, psi) * (8 * np.pi ** 2 / (2 * lj + 1))[:, None]
         gflm += _extend(contrib, Lj, L)
     return np.real(mw.sht_forward_adjoint(gflm, L))
+
+
+def synthesis_adjoint(gf, P: Plan):
+    """Transpose of the real-linear synthesis map: g f [L, 2L-1] -> (list of g W^j, g W^Phi).
+
+    Literal transposes of each stage of synthesis(), in reverse order:
+    f = Re Y^{-1} flm,  flm = sqrt(4pi/(2l+1)) Phi_l Y_{L_phi} W^Phi + sum_j sum_n Psi^j_ln (D_j W^j)^l_mn.
+    """
+    L = P.L
+    ls = np.arange(L)
+    Lp = P.Lphi
+    gflm = mw.sht_inverse_adjoint(np.asarray(gf, dtype=np.complex128), L)
+    gs = np.sqrt(4 * np.pi / (2 * ls + 1))[:, None] * P.Phi[:, None] * gflm
+    gscal = np.real(mw.sht_forward_adjoint(_embed(gs, L, Lp), Lp))
+    gwav = []
+    for k in range(len(P.scales)):
+        Lj, Nj = P.Lj[k], P.Nj[k]
+        psi = P.psi(k)                                             # [l, n]
+        gk = _embed(gflm, L, Lj)                                   # [l, m]
+        g_nlm = np.conj(psi).T[:, :, None] * gk[None, :, :]        # transpose of the sum over n
+        gwav.append(np.real(mw.wigner_forward_adjoint(g_nlm, Lj, Nj)))
+    return gwav, gscal

@@ -48,10 +48,12 @@ def _load():
         "s2w_analysis": [vp, vp, vp, vp, vp],
         "s2w_synthesis": [vp, vp, vp, vp, vp],
         "s2w_analysis_adjoint": [vp, vp, vp, vp, vp],
+        "s2w_synthesis_adjoint": [vp, vp, vp, vp, vp],
+        "s2w_analysis_lm": [vp, vp, vp, vp, vp],
         "s2w_sht_forward": [vp, vp, vp, vp],
         "s2w_sht_inverse": [vp, vp, vp, vp],
         "s2w_plan_profile": [vp, ctypes.c_int],
-        "s2w_plan_profile_read": [vp, ctypes.c_int, ctypes.c_char_p, dp, i64p, dp, ip, i64p],
+        "s2w_plan_profile_read": [vp, ctypes.c_int, ctypes.c_char_p, dp, i64p, dp, dp, dp, ip, i64p],
         "s2w_host_scales": [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ip, ip, ip, ip],
         "s2w_host_filters": [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp],
         "s2w_host_theta_matrix": [ctypes.c_int, ctypes.c_int, dp],
@@ -64,10 +66,12 @@ def _load():
         "b3w_plan_layout": [vp, ip, ip, ip, ip, ip, i64p, dp],
         "b3w_analysis": [vp, vp, vp, vp, vp],
         "b3w_synthesis": [vp, vp, vp, vp, vp],
+        "b3w_analysis_adjoint": [vp, vp, vp, vp, vp],
+        "b3w_synthesis_adjoint": [vp, vp, vp, vp, vp],
         "b3w_sl_forward": [vp, vp, vp, vp],
         "b3w_sl_inverse": [vp, vp, vp, vp],
         "b3w_plan_profile": [vp, ctypes.c_int],
-        "b3w_plan_profile_read": [vp, ctypes.c_int, ctypes.c_char_p, dp, i64p, dp, ip, i64p],
+        "b3w_plan_profile_read": [vp, ctypes.c_int, ctypes.c_char_p, dp, i64p, dp, dp, dp, ip, i64p],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -82,12 +86,12 @@ _lib = _load()
 
 # every symbol the header declares (checked by the tests)
 EXPORTS = ["s2w_plan_create", "s2w_plan_destroy", "s2w_plan_layout", "s2w_analysis", "s2w_synthesis",
-           "s2w_analysis_adjoint", "s2w_sht_forward", "s2w_sht_inverse",
+           "s2w_analysis_lm", "s2w_analysis_adjoint", "s2w_synthesis_adjoint", "s2w_sht_forward", "s2w_sht_inverse",
            "s2w_plan_profile", "s2w_plan_profile_read",
            "s2w_last_error", "s2w_host_scales", "s2w_host_filters", "s2w_host_theta_matrix",
            "s2w_host_wigner_d", "s2w_host_laguerre_rule",
            "b3w_plan_create", "b3w_plan_destroy", "b3w_plan_layout", "b3w_analysis", "b3w_synthesis",
-           "b3w_sl_forward", "b3w_sl_inverse", "b3w_plan_profile", "b3w_plan_profile_read"]
+           "b3w_analysis_adjoint", "b3w_synthesis_adjoint", "b3w_sl_forward", "b3w_sl_inverse", "b3w_plan_profile", "b3w_plan_profile_read"]
 
 
 def lib():
@@ -143,6 +147,26 @@ def host_laguerre_rule(P, tau=1.0):
 
 
 # --------------------------------------------------------------- GPU plans
+
+def _require(t, what, dtype, shape, device):
+    """Raise ValueError unless t is a contiguous tensor of dtype and shape on cuda:device.
+
+    Every tensor handed to the library is checked here first: the kernels index it by
+    the plan's sizes, so a short, mistyped or strided buffer would be read or written
+    out of bounds."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{what}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise ValueError(f"{what}: expected dtype {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: expected a contiguous tensor")
+    if not t.is_cuda or t.device.index != device:
+        raise ValueError(f"{what}: expected a tensor on cuda:{device}, got {t.device}")
+    return t
+
 
 def _stream_ptr(torch, device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
@@ -205,10 +229,24 @@ class Plan:
     def empty_wav(self):
         return self._torch.empty(self.wav_offset[-1], dtype=self.wav_dtype, device=self._dev())
 
-    def _check_map(self, t):
+    def _check_map(self, t, what="f"):
+        return _require(t, what, self._torch.float64, self.map_shape, self.device)
+
+    def _check_wav(self, t, what="wav"):
+        return _require(t, what, self.wav_dtype, (self.wav_offset[-1],), self.device)
+
+    def _check_scal(self, t, what="scal"):
+        return _require(t, what, self._torch.float64, self.scal_shape, self.device)
+
+    def _check_flm(self, t, what="flm"):
+        """flm as a contiguous float64 [B, L, 2L-1, 2] (re, im) tensor."""
+        return _require(t, what, self._torch.float64, self.map_shape + (2,), self.device)
+
+    def _out(self, t, shape, dtype, what):
         torch = self._torch
-        if t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != self.map_shape or not t.is_contiguous():
-            raise ValueError(f"expected a contiguous float64 CUDA tensor of shape {self.map_shape}")
+        if t is None:
+            return torch.empty(shape, dtype=dtype, device=self._dev())
+        return _require(t, what, dtype, shape, self.device)
 
     def _p(self, t):
         return ctypes.c_void_p(t.data_ptr())
@@ -217,25 +255,51 @@ class Plan:
     def analysis(self, f, wav=None, scal=None):
         torch = self._torch
         self._check_map(f)
-        wav = self.empty_wav() if wav is None else wav
-        scal = torch.empty(self.scal_shape, dtype=torch.float64, device=self._dev()) if scal is None else scal
+        wav = self._out(wav, (self.wav_offset[-1],), self.wav_dtype, "wav")
+        scal = self._out(scal, self.scal_shape, torch.float64, "scal")
         _check(_lib.s2w_analysis(self._h, self._p(f), self._p(wav), self._p(scal),
                                  _stream_ptr(torch, self.device)))
         return wav, scal
 
+    def analysis_lm(self, flm, wav=None, scal=None):
+        """Analysis from harmonic coefficients flm [B, L, 2L-1] (complex, real maps)."""
+        torch = self._torch
+        if tuple(flm.shape) != self.map_shape or not flm.is_complex():
+            raise ValueError(f"flm: expected complex coefficients of shape {self.map_shape}")
+        x = self._check_flm(torch.view_as_real(flm.to(torch.complex128)).contiguous())
+        wav = self._out(wav, (self.wav_offset[-1],), self.wav_dtype, "wav")
+        scal = self._out(scal, self.scal_shape, torch.float64, "scal")
+        _check(_lib.s2w_analysis_lm(self._h, self._p(x), self._p(wav), self._p(scal),
+                                    _stream_ptr(torch, self.device)))
+        return wav, scal
+
     def synthesis(self, wav, scal, f=None):
         torch = self._torch
-        f = torch.empty(self.map_shape, dtype=torch.float64, device=self._dev()) if f is None else f
+        self._check_wav(wav)
+        self._check_scal(scal)
+        f = self._out(f, self.map_shape, torch.float64, "f")
         _check(_lib.s2w_synthesis(self._h, self._p(wav), self._p(scal), self._p(f),
                                   _stream_ptr(torch, self.device)))
         return f
 
     def analysis_adjoint(self, gwav, gscal, gf=None):
         torch = self._torch
-        gf = torch.empty(self.map_shape, dtype=torch.float64, device=self._dev()) if gf is None else gf
+        self._check_wav(gwav, "gwav")
+        self._check_scal(gscal, "gscal")
+        gf = self._out(gf, self.map_shape, torch.float64, "gf")
         _check(_lib.s2w_analysis_adjoint(self._h, self._p(gwav), self._p(gscal), self._p(gf),
                                          _stream_ptr(torch, self.device)))
         return gf
+
+    def synthesis_adjoint(self, gf, gwav=None, gscal=None):
+        """Transpose of synthesis: map cotangent gf -> (gwav, gscal)."""
+        torch = self._torch
+        self._check_map(gf, "gf")
+        gwav = self._out(gwav, (self.wav_offset[-1],), self.wav_dtype, "gwav")
+        gscal = self._out(gscal, self.scal_shape, torch.float64, "gscal")
+        _check(_lib.s2w_synthesis_adjoint(self._h, self._p(gf), self._p(gwav), self._p(gscal),
+                                          _stream_ptr(torch, self.device)))
+        return gwav, gscal
 
     # kernel timing ------------------------------------------------------
     def profile(self, capacity):
@@ -243,7 +307,8 @@ class Plan:
         _check(_lib.s2w_plan_profile(self._h, int(capacity)))
 
     def profile_read(self):
-        """{kernel name: (total ms, launches, algorithmic flop)} since profiling started."""
+        """{kernel name: (total ms, launches, flop, flop64, dense)} since profiling started
+        (algorithmic work as counted by the library, see include/s2w.h)."""
         return _profile_read(_lib.s2w_plan_profile_read, self._h)
 
     def sht_forward(self, f):
@@ -255,25 +320,30 @@ class Plan:
 
     def sht_inverse(self, flm):
         torch = self._torch
-        flm = torch.view_as_real(flm.to(torch.complex128)).contiguous()
+        if tuple(flm.shape) != self.map_shape or not flm.is_complex():
+            raise ValueError(f"flm: expected complex coefficients of shape {self.map_shape}")
+        x = self._check_flm(torch.view_as_real(flm.to(torch.complex128)).contiguous())
         f = torch.empty(self.map_shape, dtype=torch.float64, device=self._dev())
-        _check(_lib.s2w_sht_inverse(self._h, self._p(flm), self._p(f), _stream_ptr(torch, self.device)))
+        _check(_lib.s2w_sht_inverse(self._h, self._p(x), self._p(f), _stream_ptr(torch, self.device)))
         return f
 
 
 def _profile_read(fn, h):
+    """{kernel name: (total ms, launches, flop, flop64, dense)} and the dropped-launch count."""
     mx = 64
     names = ctypes.create_string_buffer(32 * mx)
     ms = (ctypes.c_double * mx)()
     cnt = (ctypes.c_int64 * mx)()
     fl = (ctypes.c_double * mx)()
+    f64 = (ctypes.c_double * mx)()
+    dn = (ctypes.c_double * mx)()
     k = ctypes.c_int()
     dropped = ctypes.c_int64()
-    _check(fn(h, mx, names, ms, cnt, fl, ctypes.byref(k), ctypes.byref(dropped)))
+    _check(fn(h, mx, names, ms, cnt, fl, f64, dn, ctypes.byref(k), ctypes.byref(dropped)))
     out = {}
     for i in range(k.value):
         name = names.raw[32 * i:32 * (i + 1)].split(b"\0", 1)[0].decode()
-        out[name] = (ms[i], cnt[i], fl[i])
+        out[name] = (ms[i], cnt[i], fl[i], f64[i], dn[i])
     return out, dropped.value
 
 
@@ -338,28 +408,59 @@ class BallPlan:
     def empty_wav(self):
         return self._torch.empty(self.wav_offset[-1], dtype=self.wav_dtype, device=self._dev())
 
+    def _map(self, t, what):
+        return _require(t, what, self._torch.float64, self.map_shape, self.device)
+
+    def _wav(self, t, what):
+        return _require(t, what, self.wav_dtype, (self.wav_offset[-1],), self.device)
+
+    def _out(self, t, shape, dtype, what):
+        if t is None:
+            return self._torch.empty(shape, dtype=dtype, device=self._dev())
+        return _require(t, what, dtype, shape, self.device)
+
     def analysis(self, f, wav=None, scal=None):
         torch = self._torch
-        if f.dtype != torch.float64 or not f.is_cuda or tuple(f.shape) != self.map_shape or not f.is_contiguous():
-            raise ValueError(f"expected a contiguous float64 CUDA tensor of shape {self.map_shape}")
-        wav = self.empty_wav() if wav is None else wav
-        scal = torch.empty(self.map_shape, dtype=torch.float64, device=self._dev()) if scal is None else scal
+        self._map(f, "f")
+        wav = self._out(wav, (self.wav_offset[-1],), self.wav_dtype, "wav")
+        scal = self._out(scal, self.map_shape, torch.float64, "scal")
         _check(_lib.b3w_analysis(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(wav.data_ptr()),
                                  ctypes.c_void_p(scal.data_ptr()), _stream_ptr(torch, self.device)))
         return wav, scal
 
     def synthesis(self, wav, scal, f=None):
         torch = self._torch
-        f = torch.empty(self.map_shape, dtype=torch.float64, device=self._dev()) if f is None else f
+        self._wav(wav, "wav")
+        self._map(scal, "scal")
+        f = self._out(f, self.map_shape, torch.float64, "f")
         _check(_lib.b3w_synthesis(self._h, ctypes.c_void_p(wav.data_ptr()), ctypes.c_void_p(scal.data_ptr()),
                                   ctypes.c_void_p(f.data_ptr()), _stream_ptr(torch, self.device)))
         return f
 
+    def analysis_adjoint(self, gwav, gscal, gf=None):
+        """Transpose of analysis: (gwav, gscal) -> gf."""
+        torch = self._torch
+        self._wav(gwav, "gwav")
+        self._map(gscal, "gscal")
+        gf = self._out(gf, self.map_shape, torch.float64, "gf")
+        _check(_lib.b3w_analysis_adjoint(self._h, ctypes.c_void_p(gwav.data_ptr()), ctypes.c_void_p(gscal.data_ptr()),
+                                         ctypes.c_void_p(gf.data_ptr()), _stream_ptr(torch, self.device)))
+        return gf
+
+    def synthesis_adjoint(self, gf, gwav=None, gscal=None):
+        """Transpose of synthesis: gf -> (gwav, gscal)."""
+        torch = self._torch
+        self._map(gf, "gf")
+        gwav = self._out(gwav, (self.wav_offset[-1],), self.wav_dtype, "gwav")
+        gscal = self._out(gscal, self.map_shape, torch.float64, "gscal")
+        _check(_lib.b3w_synthesis_adjoint(self._h, ctypes.c_void_p(gf.data_ptr()), ctypes.c_void_p(gwav.data_ptr()),
+                                          ctypes.c_void_p(gscal.data_ptr()), _stream_ptr(torch, self.device)))
+        return gwav, gscal
+
     def sl_forward(self, f):
         """Spherical-Laguerre coefficients f_lmp [B, P, L, 2L-1] (complex128) of maps on the nodes."""
         torch = self._torch
-        if f.dtype != torch.float64 or not f.is_cuda or tuple(f.shape) != self.map_shape or not f.is_contiguous():
-            raise ValueError(f"expected a contiguous float64 CUDA tensor of shape {self.map_shape}")
+        self._map(f, "f")
         flmp = torch.empty(self.map_shape + (2,), dtype=torch.float64, device=self._dev())
         _check(_lib.b3w_sl_forward(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(flmp.data_ptr()),
                                    _stream_ptr(torch, self.device)))
@@ -368,9 +469,10 @@ class BallPlan:
     def sl_inverse(self, flmp):
         """Maps on the radial nodes from real-map spherical-Laguerre coefficients [B, P, L, 2L-1]."""
         torch = self._torch
-        if tuple(flmp.shape) != self.map_shape:
-            raise ValueError(f"expected coefficients of shape {self.map_shape}")
+        if tuple(flmp.shape) != self.map_shape or not flmp.is_complex():
+            raise ValueError(f"flmp: expected complex coefficients of shape {self.map_shape}")
         x = torch.view_as_real(flmp.to(device=self._dev(), dtype=torch.complex128)).contiguous()
+        _require(x, "flmp", torch.float64, self.map_shape + (2,), self.device)
         f = torch.empty(self.map_shape, dtype=torch.float64, device=self._dev())
         _check(_lib.b3w_sl_inverse(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(f.data_ptr()),
                                    _stream_ptr(torch, self.device)))

@@ -6,8 +6,10 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/s2w.h"
@@ -22,6 +24,32 @@ s2w_status fail(s2w_status st, const std::string &msg)
 {
     g_err = msg;
     return st;
+}
+
+// Live plan handles.  A handle is looked up here before it is dereferenced, so a
+// destroyed (or never created) handle is reported as S2W_ESTATE instead of being
+// read.  A handle whose memory was reused by a later plan is indistinguishable
+// from that plan.
+std::mutex g_reg_mu;
+std::unordered_set<const void *> g_live;
+
+void reg_add(const void *h)
+{
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    g_live.insert(h);
+}
+
+bool reg_has(const void *h)
+{
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    return g_live.count(h) != 0;
+}
+
+// removes h; false when it was not live
+bool reg_remove(const void *h)
+{
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    return g_live.erase(h) != 0;
 }
 
 struct DevDft {
@@ -90,11 +118,10 @@ struct s2w_plan_s {
     double *Pphi = nullptr;
     std::vector<Group> groups;
     std::vector<void *> allocs;
-    bool alive = true;
     // kernel timing
     std::vector<hipEvent_t> ev0, ev1;
     std::vector<int> rec_name;
-    std::vector<double> rec_flop;
+    std::vector<double> rec_flop, rec_flop64, rec_dense;
     std::vector<std::string> prof_names;
     int64_t prof_dropped = 0;
     int prof_cap = 0;
@@ -121,11 +148,12 @@ struct b3w_plan_s {
     std::vector<int64_t> wav_off;            // [nrad * nang + 1]
     std::vector<double> nodes;
     double *Zf = nullptr, *Zi = nullptr;     // [P][P]: W_k K_p(r_k) and K_p(r_k) (as [k][p])
+    double *Zft = nullptr, *Zit = nullptr;   // their transposes (adjoints)
     double *phi = nullptr;                   // [P][L]: sqrt(4pi/(2l+1)) Phi_l0p
     std::vector<double *> G, H;              // per radial scale: [P_j'][P], [P][P_j']
+    std::vector<double *> Gt, Ht;            // their transposes: [P][P_j'], [P_j'][P]
     double *flmp = nullptr, *shell = nullptr, *shell2 = nullptr;
     std::vector<void *> allocs;
-    bool alive = true;
 };
 
 namespace {
@@ -136,12 +164,21 @@ using s2w::GammaArgs;
 using s2w::LsumArgs;
 using s2w::TsumArgs;
 
+// Algorithmic work of a launch: all floating-point operations the method needs
+// (flop), the part of them that runs on the FP64 units in a mixed-precision kernel
+// (flop64: the Wigner-d recursion), and the operations of a dense product that stands in
+// for a cheaper algorithm (dense: the theta-quadrature matrix product; 0 elsewhere).
+struct Work {
+    double flop = 0.0, flop64 = 0.0, dense = 0.0;
+};
+
 // One HIP event pair around a kernel launch when profiling is on.
 struct Prof {
     s2w_plan p;
     hipStream_t st;
     int idx = -1;
-    Prof(s2w_plan p_, const char *name, double flop, hipStream_t st_) : p(p_), st(st_)
+    Prof(s2w_plan p_, const char *name, double flop, hipStream_t st_) : Prof(p_, name, Work{flop, 0.0, 0.0}, st_) {}
+    Prof(s2w_plan p_, const char *name, const Work &wk, hipStream_t st_) : p(p_), st(st_)
     {
         if (p->prof_cap == 0 || p->capturing) return;
         if ((int)p->rec_name.size() >= p->prof_cap) { ++p->prof_dropped; return; }
@@ -151,7 +188,9 @@ struct Prof {
         if (id < 0) { p->prof_names.push_back(name); id = (int)p->prof_names.size() - 1; }
         idx = (int)p->rec_name.size();
         p->rec_name.push_back(id);
-        p->rec_flop.push_back(flop);
+        p->rec_flop.push_back(wk.flop);
+        p->rec_flop64.push_back(wk.flop64);
+        p->rec_dense.push_back(wk.dense);
         (void)hipEventRecord(p->ev0[idx], st);
     }
     ~Prof()
@@ -160,18 +199,59 @@ struct Prof {
     }
 };
 
-// algorithmic flop of a recursion + contraction pass: sum over (m, n) of
-// (L - l0) steps x L theta samples x (6 for the recursion step, needed once for
-// all maps, + 4 per scale and map for the complex x real multiply-add)
-double rec_flop(int L, int mcount, const std::vector<int> &ns, int NS, int B)
+// Algorithmic work of one recursion + contraction launch on the theta grid of band
+// limit L (L samples): 6 FP64 flop per Wigner-d recursion step (theta, l, m, n; l from
+// max(m, |n|) to L - 1), counted once for all maps and scales of the launch, plus 4 flop
+// per complex-by-real multiply-add, per map, at the degrees where the scale's weight is
+// nonzero (the filter's support; products with zero coefficients are not counted).
+// wt(s, i, l): weight of scale s, n index i, degree l.
+template <class Wt>
+Work rec_work(int L, int mcount, const std::vector<int> &ns, int NS, int B, Wt wt)
 {
-    double steps = 0.0;
-    for (int n : ns)
+    double steps = 0.0, macs = 0.0;
+    for (size_t i = 0; i < ns.size(); ++i) {
+        const int an = std::abs(ns[i]);
         for (int m = 0; m < mcount; ++m) {
-            const int l0 = std::max(m, std::abs(n));
+            const int l0 = std::max(m, an);
             if (l0 < L) steps += (double)(L - l0);
         }
-    return steps * L * (6.0 + 4.0 * NS * B);
+        for (int s = 0; s < NS; ++s)
+            for (int l = an; l < L; ++l)
+                if (wt(s, (int)i, l) != 0.0) macs += (double)std::min(l + 1, mcount);
+    }
+    Work w;
+    w.flop64 = 6.0 * steps * L;
+    w.flop = w.flop64 + 4.0 * macs * L * B;
+    return w;
+}
+
+// ... with the wavelet filters of the given scales (one group: same n set)
+Work rec_work_psi(s2w_plan p, const std::vector<int> &scales, int L, int mcount, const std::vector<int> &ns, int B)
+{
+    const int nn = (int)ns.size();
+    return rec_work(L, mcount, ns, (int)scales.size(), B, [&](int s, int i, int l) {
+        return p->F.psi_mag[scales[s]][(size_t)l * nn + i];
+    });
+}
+
+// ... for n = 0 with the weights of a harmonic transform: wt the device table p->wphi
+// (scaling filter) or p->wsht (no zero weights)
+Work rec_work_n0(s2w_plan p, const double *wt, int L, int mcount, int B)
+{
+    const bool phi = wt == p->wphi;
+    return rec_work(L, mcount, std::vector<int>{0}, 1, B, [&](int, int, int l) {
+        return phi ? p->F.phi[l] : 1.0;
+    });
+}
+
+// The theta quadrature by its Fourier route, per complex column (m, n, map) on the grid
+// of band limit L: the length-(2L-1) DFT of the extended column, the Hankel product with
+// the weights w(p+q) as a linear convolution through two FFTs of length 2(2L-1) and a
+// pointwise product, and the inverse length-(2L-1) DFT (5 n log2 n per complex FFT).
+double theta_fft_flop(int L)
+{
+    const double n = 2.0 * L - 1.0;
+    return 10.0 * n * std::log2(n) + 10.0 * (2.0 * n) * std::log2(2.0 * n) + 12.0 * n;
 }
 
 double dft_flop(int n, long rows) { return n > 1 ? 2.5 * n * std::log2((double)n) * (double)rows : 0.0; }
@@ -406,11 +486,11 @@ void theta_quadrature(s2w_plan p, const DevGrid &g, const double *F, double *H, 
     sig_counts(M, npar, M0, M1);
     const size_t r0 = (size_t)p->B * M0 * nn * 2, r1 = (size_t)p->B * M1 * nn * 2;
     {
-        Prof pr_(p, "gemm_theta", 2.0 * (double)r0 * g.L * g.L, st);
+        Prof pr_(p, "gemm_theta", Work{theta_fft_flop(g.L) * (r0 / 2), 0.0, 2.0 * (double)r0 * g.L * g.L}, st);
         s2w::launch_gemm(F, g.T[0], H, (int)r0, g.L, g.L, st);
     }
     {
-        Prof pr_(p, "gemm_theta", 2.0 * (double)r1 * g.L * g.L, st);
+        Prof pr_(p, "gemm_theta", Work{theta_fft_flop(g.L) * (r1 / 2), 0.0, 2.0 * (double)r1 * g.L * g.L}, st);
         s2w::launch_gemm(F + r0 * g.L, g.T[1], H + r0 * g.L, (int)r1, g.L, g.L, st);
     }
 }
@@ -435,8 +515,7 @@ void sht_forward_internal(s2w_plan p, const double *f, double *flm_out, hipStrea
     ta.wstride = 0;
     ta.out[0] = flm_out;
     {
-        std::vector<int> ns_(ta.nval, ta.nval + ta.nn);
-        Prof pr_(p, "tsum", rec_flop(ta.L, ta.mcount, ns_, 1, p->B), st);
+        Prof pr_(p, "tsum", rec_work_n0(p, p->wsht, ta.L, ta.mcount, p->B), st);
         s2w::launch_tsum(ta, 1, p->B, st);
     }
 }
@@ -455,8 +534,7 @@ void sht_inverse_internal(s2w_plan p, const double *flm_in, double *f, hipStream
     la.wstride = 0;
     la.out[0] = p->bufA;
     {
-        std::vector<int> ns_(la.nval, la.nval + la.nn);
-        Prof pr_(p, "lsum", rec_flop(la.L, la.mcount, ns_, 1, p->B), st);
+        Prof pr_(p, "lsum", rec_work_n0(p, p->wsht, la.L, la.mcount, p->B), st);
         s2w::launch_lsum(la, 1, p->B, st);
     }
     GammaArgs ga = gamma_args(p, L, L, L, L, n0, 1);
@@ -475,11 +553,11 @@ void theta_quadrature32(s2w_plan p, const DevGrid &g, const float *F, float *H, 
     sig_counts(M, npar, M0, M1);
     const size_t r0 = (size_t)p->B * M0 * nn * 2, r1 = (size_t)p->B * M1 * nn * 2;
     {
-        Prof pr_(p, "gemm_theta_f32", 2.0 * (double)r0 * g.L * g.L, st);
+        Prof pr_(p, "gemm_theta_f32", Work{theta_fft_flop(g.L) * (r0 / 2), 0.0, 2.0 * (double)r0 * g.L * g.L}, st);
         s2w::launch_gemm_f32(F, g.T32[0], H, (int)r0, g.L, g.L, st);
     }
     {
-        Prof pr_(p, "gemm_theta_f32", 2.0 * (double)r1 * g.L * g.L, st);
+        Prof pr_(p, "gemm_theta_f32", Work{theta_fft_flop(g.L) * (r1 / 2), 0.0, 2.0 * (double)r1 * g.L * g.L}, st);
         s2w::launch_gemm_f32(F + r0 * g.L, g.T32[1], H + r0 * g.L, (int)r1, g.L, g.L, st);
     }
 }
@@ -600,7 +678,14 @@ void autotune(s2w_plan p)
 s2w_status check_plan(s2w_plan p)
 {
     if (!p) return fail(S2W_EINVAL, "null plan");
-    if (!p->alive) return fail(S2W_ESTATE, "plan used after destroy");
+    if (!reg_has(p)) return fail(S2W_ESTATE, "not a live plan (destroyed, or never created)");
+    return S2W_OK;
+}
+
+s2w_status check_ball(b3w_plan p)
+{
+    if (!p) return fail(S2W_EINVAL, "null plan");
+    if (!reg_has(p)) return fail(S2W_ESTATE, "not a live ball plan (destroyed, or never created)");
     return S2W_OK;
 }
 
@@ -790,6 +875,7 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
         delete p;
         return fail(S2W_EHIP, "device synchronisation failed during plan creation");
     }
+    reg_add(p);
     *out = p;
     return S2W_OK;
 }
@@ -797,7 +883,7 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
 s2w_status s2w_plan_destroy(s2w_plan p)
 {
     if (!p) return S2W_OK;
-    if (!p->alive) return fail(S2W_ESTATE, "plan destroyed twice");
+    if (!reg_remove(p)) return fail(S2W_ESTATE, "not a live plan (destroyed twice, or never created)");
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
     for (auto &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
@@ -805,7 +891,6 @@ s2w_status s2w_plan_destroy(s2w_plan p)
     for (auto e : p->ev0) (void)hipEventDestroy(e);
     for (auto e : p->ev1) (void)hipEventDestroy(e);
     free_plan(p);
-    p->alive = false;
     delete p;
     return S2W_OK;
 }
@@ -865,7 +950,7 @@ static void analysis_from_flm(s2w_plan p, const double *flm, void *wav_, double 
         la.w[0] = p->wphi;
         la.wstride = 0;
         la.out[0] = p->bufA;
-        { std::vector<int> ns_(la.nval, la.nval + la.nn); Prof pr_(p, "lsum", rec_flop(la.L, la.mcount, ns_, 1, B), st); s2w::launch_lsum(la, 1, B, st); }
+        { Prof pr_(p, "lsum", rec_work_n0(p, p->wphi, la.L, la.mcount, B), st); s2w::launch_lsum(la, 1, B, st); }
         GammaArgs ga = gamma_args(p, Lp, Lp, Lp, Lp, n0, 1);
         ga.src = p->bufA;
         ga.dst = p->bufB;
@@ -894,7 +979,7 @@ static void analysis_from_flm(s2w_plan p, const double *flm, void *wav_, double 
                 mo.out[s] = A32 + s * cstride;
             }
             {
-                Prof pr_(p, "lsum_mm", rec_flop(la.L, la.mcount, si.n, NS, B), st);
+                Prof pr_(p, "lsum_mm", rec_work_psi(p, grp.scales, la.L, la.mcount, si.n, B), st);
                 s2w::launch_lsum_mm(la, mo, NS, st);
             }
             for (int s = 0; s < NS; ++s) {
@@ -929,7 +1014,7 @@ static void analysis_from_flm(s2w_plan p, const double *flm, void *wav_, double 
             la.w[s] = p->wpsi[grp.scales[s]];
             la.out[s] = p->bufA + s * cstride;
         }
-        { std::vector<int> ns_(la.nval, la.nval + la.nn); Prof pr_(p, "lsum", rec_flop(la.L, la.mcount, ns_, NS, B), st); s2w::launch_lsum(la, NS, B, st); }
+        { Prof pr_(p, "lsum", rec_work_psi(p, grp.scales, la.L, la.mcount, si.n, B), st); s2w::launch_lsum(la, NS, B, st); }
         for (int s = 0; s < NS; ++s) {
             const int k = grp.scales[s];
             GammaArgs ga = gamma_args(p, Lk, Lk, Lk, Lk, si.n, ng);
@@ -1003,7 +1088,7 @@ static void synthesis_to_fhat(s2w_plan p, const void *wav_, const double *scal, 
             mi.h[s] = C32 + s * cstride;
             mi.out[s] = p->P[k];
         }
-        Prof pr_(p, "tsum_mm", rec_flop(ta.L, ta.mcount, si.n, NS, B), st);
+        Prof pr_(p, "tsum_mm", rec_work_psi(p, grp.scales, ta.L, ta.mcount, si.n, B), st);
         s2w::launch_tsum_mm(ta, mi, NS, st);
     }
     for (auto &grp : p->groups) {
@@ -1031,7 +1116,7 @@ static void synthesis_to_fhat(s2w_plan p, const void *wav_, const double *scal, 
             ta.w[s] = p->wpsi[k];
             ta.out[s] = p->P[k];
         }
-        { std::vector<int> ns_(ta.nval, ta.nval + ta.nn); Prof pr_(p, "tsum", rec_flop(ta.L, ta.mcount, ns_, NS, B), st); s2w::launch_tsum(ta, NS, B, st); }
+        { Prof pr_(p, "tsum", rec_work_psi(p, grp.scales, ta.L, ta.mcount, si.n, B), st); s2w::launch_tsum(ta, NS, B, st); }
     }
     // scaling: Phi * Y(W^Phi)
     if (scal) {
@@ -1051,7 +1136,7 @@ static void synthesis_to_fhat(s2w_plan p, const void *wav_, const double *scal, 
         ta.w[0] = p->wphi;
         ta.wstride = 0;
         ta.out[0] = p->Pphi;
-        { std::vector<int> ns_(ta.nval, ta.nval + ta.nn); Prof pr_(p, "tsum", rec_flop(ta.L, ta.mcount, ns_, 1, B), st); s2w::launch_tsum(ta, 1, B, st); }
+        { Prof pr_(p, "tsum", rec_work_n0(p, p->wphi, ta.L, ta.mcount, B), st); s2w::launch_tsum(ta, 1, B, st); }
     }
     CombineArgs ca{};
     ca.out = fhat;
@@ -1091,73 +1176,149 @@ s2w_status s2w_synthesis(s2w_plan p, const void *wav_, const double *scal, doubl
     return post_launch("s2w_synthesis");
 }
 
-s2w_status s2w_analysis_adjoint(s2w_plan p, const void *gwav_, const double *gscal, double *gf, void *stream)
+// ---- transposes (gradients) -----------------------------------------------
+// Each stage below is the transpose, under the real inner product of the stored
+// real and imaginary parts, of a stage of the forward maps; the internal harmonic
+// arrays [B][m >= 0][l] carry cotangents of their stored entries (l >= m).
+
+// Transpose of Y^{-1} on the grid of band limit Lg with degree weights wt (n = 0):
+// map cotangent [B][Lg][2Lg-1] -> out [B][Lg][1][Lg] (defined at l >= m).  The
+// transpose of the Hermitian c2r is an unweighted r2c with the m >= 1 terms doubled;
+// the sum over theta is taken against d directly (no quadrature matrix).
+static void sht_inverse_T(s2w_plan p, int Lg, const double *wt, const double *gmap, double *out, hipStream_t st)
 {
-    if (s2w_status st = check_plan(p)) return st;
-    if (!gf || !gwav_ || !gscal) return fail(S2W_EINVAL, "null buffer");
-    hipStream_t st = (hipStream_t)stream;
-    // mixed plans take FP32 cotangents of the wavelet coefficients; the adjoint itself
-    // runs in FP64 (its first stage reads the FP32 rows)
+    const DevGrid &g = p->grids[Lg];
+    const int B = p->B;
+    std::vector<int> n0{0};
+    {
+        const DftArgs da_ = dft_args(g, gmap, 2 * Lg - 1, p->bufB, Lg, B * Lg, 1.0);
+        Prof pr_(p, "dft_r2c", dft_flop(da_.n, da_.nrows), st);
+        s2w::launch_dft_r2c(da_, st);
+    }
+    GammaArgs ga = gamma_args(p, Lg, Lg, Lg, Lg, n0, 1);
+    ga.src = p->bufB;
+    ga.dst = p->bufA;
+    ga.sgn = -1.0;
+    ga.fm0 = 1.0;
+    ga.fm1 = 2.0;
+    sig_counts(Lg, 0, ga.M0, ga.M1);
+    { Prof pr_(p, "gamma_r2c", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_r2c(ga, st); }
+    TsumArgs ta = tsum_args(p, g, Lg, n0, 0);
+    ta.h[0] = p->bufA;
+    ta.w[0] = wt;
+    ta.wstride = 0;
+    ta.out[0] = out;
+    { Prof pr_(p, "tsum", rec_work_n0(p, wt, ta.L, ta.mcount, B), st); s2w::launch_tsum(ta, 1, B, st); }
+}
+
+// Transpose of the forward SHT (Y, weights wt) on the grid of band limit Lg: cotangent
+// of an internal harmonic array ([B][flm_m][flm_l], read at m <= l < Lg) -> map
+// cotangent [B][Lg][2Lg-1].  Sum over l against d (n = 0), the quadrature matrix
+// (symmetric, so its own transpose), then the transpose of the weighted phi r2c: a
+// c2r with the m >= 1 terms halved.
+static void sht_forward_T(s2w_plan p, int Lg, const double *wt, const double *flm, int flm_m, int flm_l,
+                          double *gmap, hipStream_t st)
+{
+    const DevGrid &g = p->grids[Lg];
+    const int B = p->B, na = 2 * Lg - 1;
+    std::vector<int> n0{0};
+    LsumArgs la = lsum_args(p, g, Lg, n0);
+    la.flm = flm;
+    la.flm_m = flm_m;
+    la.flm_l = flm_l;
+    la.w[0] = wt;
+    la.wstride = 0;
+    la.out[0] = p->bufA;
+    { Prof pr_(p, "lsum", rec_work_n0(p, wt, la.L, la.mcount, B), st); s2w::launch_lsum(la, 1, B, st); }
+    int M0, M1;
+    sig_counts(Lg, 0, M0, M1);
+    { Prof pr_(p, "pack_sigma", 0.0, st); s2w::launch_pack_sigma(p->bufA, p->bufB, B, 1, Lg, Lg, 0, M0, M1, 0, st); }
+    theta_quadrature(p, g, p->bufB, p->bufC, Lg, 1, 0, st);
+    { Prof pr_(p, "pack_sigma", 0.0, st); s2w::launch_pack_sigma(p->bufC, p->bufA, B, 1, Lg, Lg, 0, M0, M1, 1, st); }
+    GammaArgs ga = gamma_args(p, Lg, Lg, Lg, Lg, n0, 1);
+    ga.src = p->bufA;
+    ga.dst = p->bufB;
+    ga.fm0 = 1.0;
+    ga.fm1 = 0.5;
+    { Prof pr_(p, "gamma_c2r", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_c2r(ga, st); }
+    {
+        const DftArgs da_ = dft_args(g, p->bufB, Lg, gmap, na, B * Lg, 2.0 * M_PI / na);
+        Prof pr_(p, "dft_c2r", dft_flop(da_.n, da_.nrows), st);
+        s2w::launch_dft_c2r(da_, st);
+    }
+}
+
+// Transpose of analysis_from_flm: cotangents of the wavelet coefficients (and of the
+// scaling coefficients when gscal is not null) -> cotangent of the internal harmonic
+// array fhat [B][L][L].  Per scale: unweighted r2c over alpha (m >= 1 doubled), the
+// gamma sum with the filter phase xi, the sum over theta against d with the filter
+// weights (d recomputed, no quadrature matrix); FP64 sum over n and scales.  Mixed
+// plans take FP32 cotangents and run the DFTs and the theta sum in the precision split
+// of their forward maps (FP32 matrix cores, FP64 recursion and sums).
+static void analysis_from_flm_T(s2w_plan p, const void *gwav_, const double *gscal, double *fhat, hipStream_t st)
+{
     const bool mixed = p->prec == S2W_MIXED;
-    const size_t wesz = mixed ? sizeof(float) : sizeof(double);
     const int B = p->B;
     const int npar = (p->N - 1) & 1;
-    // wavelet scales: transpose of (c2r, gamma, l-sum)
     for (auto &grp : p->groups) {
         const DevGrid &g = p->grids[grp.L];
         const int Lk = grp.L, NS = (int)grp.scales.size();
         const auto &si = p->S.s[grp.scales[0]];
         const int nn = (int)si.n.size(), ng = 2 * si.N - 1;
-        const size_t cstride = (size_t)B * nn * Lk * Lk * 2;
+        const size_t cstride = (size_t)B * nn * Lk * Lk * 2;   // elements of the coefficient type
         TsumArgs ta = tsum_args(p, g, Lk, si.n, npar);
         ta.wstride = Lk;
+        s2w::MixIn mi{};
+        mi.B = B;
         for (int s = 0; s < NS; ++s) {
             const int k = grp.scales[s];
-            {
-                const DftArgs da_ = dft_args(g, (const char *)gwav_ + wesz * p->wav_off[k], 2 * Lk - 1, p->bufB, Lk,
-                                             B * ng * Lk, 1.0);
-                Prof pr_(p, "dft_r2c", dft_flop(da_.n, da_.nrows), st);
-                s2w::launch_dft_r2c(da_, st, false, true, mixed);
-            }
             GammaArgs ga = gamma_args(p, Lk, Lk, Lk, Lk, si.n, ng);
-            ga.src = p->bufB;
-            ga.dst = p->bufA + s * cstride;
             ga.sgn = -1.0;
             ga.fm0 = 1.0;
             ga.fm1 = 2.0;
             if (p->F.xi_imag) { ga.phr = 0.0; ga.phi = 1.0; }   // xi = i
             ga.npar = npar;
             sig_counts(Lk, npar, ga.M0, ga.M1);
-            { Prof pr_(p, "gamma_r2c", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_r2c(ga, st); }
-            ta.h[s] = p->bufA + s * cstride;
-            ta.w[s] = p->wpsi[k];
-            ta.out[s] = p->P[k];
+            if (mixed) {
+                const float *gw32 = (const float *)gwav_ + p->wav_off[k];
+                float *A32 = (float *)p->bufA, *B32 = (float *)p->bufB;
+                {
+                    const DftArgs da = dft_args(g, gw32, 2 * Lk - 1, B32, Lk, B * ng * Lk, 1.0);
+                    Prof pr_(p, "dft_r2c_f32", dft_flop(da.n, da.nrows), st);
+                    s2w::launch_dft_r2c(da, st, true, false);
+                }
+                ga.src = B32;
+                ga.dst = A32 + s * cstride;
+                { Prof pr_(p, "gamma_r2c_f32", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_r2c(ga, st, true); }
+                ta.w[s] = p->wpsi[k];
+                mi.h[s] = A32 + s * cstride;
+                mi.out[s] = p->P[k];
+            } else {
+                const double *gw = (const double *)gwav_ + p->wav_off[k];
+                {
+                    const DftArgs da_ = dft_args(g, gw, 2 * Lk - 1, p->bufB, Lk, B * ng * Lk, 1.0);
+                    Prof pr_(p, "dft_r2c", dft_flop(da_.n, da_.nrows), st);
+                    s2w::launch_dft_r2c(da_, st);
+                }
+                ga.src = p->bufB;
+                ga.dst = p->bufA + s * cstride;
+                { Prof pr_(p, "gamma_r2c", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_r2c(ga, st); }
+                ta.h[s] = p->bufA + s * cstride;
+                ta.w[s] = p->wpsi[k];
+                ta.out[s] = p->P[k];
+            }
         }
-        { std::vector<int> ns_(ta.nval, ta.nval + ta.nn); Prof pr_(p, "tsum", rec_flop(ta.L, ta.mcount, ns_, NS, B), st); s2w::launch_tsum(ta, NS, B, st); }
+        if (mixed) {
+            Prof pr_(p, "tsum_mm", rec_work_psi(p, grp.scales, ta.L, ta.mcount, si.n, B), st);
+            s2w::launch_tsum_mm(ta, mi, NS, st);
+        } else {
+            Prof pr_(p, "tsum", rec_work_psi(p, grp.scales, ta.L, ta.mcount, si.n, B), st);
+            s2w::launch_tsum(ta, NS, B, st);
+        }
     }
-    // scaling part
-    {
-        const DevGrid &g = p->grids[p->Lphi];
-        const int Lp = p->Lphi;
-        std::vector<int> n0{0};
-        { const DftArgs da_ = dft_args(g, gscal, 2 * Lp - 1, p->bufB, Lp, B * Lp, 1.0); Prof pr_(p, "dft_r2c", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_r2c(da_, st); }
-        GammaArgs ga = gamma_args(p, Lp, Lp, Lp, Lp, n0, 1);
-        ga.src = p->bufB;
-        ga.dst = p->bufA;
-        ga.sgn = -1.0;
-        ga.fm0 = 1.0;
-        ga.fm1 = 2.0;
-        sig_counts(Lp, 0, ga.M0, ga.M1);
-        { Prof pr_(p, "gamma_r2c", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_r2c(ga, st); }
-        TsumArgs ta = tsum_args(p, g, Lp, n0, 0);
-        ta.h[0] = p->bufA;
-        ta.w[0] = p->wphi;
-        ta.wstride = 0;
-        ta.out[0] = p->Pphi;
-        { std::vector<int> ns_(ta.nval, ta.nval + ta.nn); Prof pr_(p, "tsum", rec_flop(ta.L, ta.mcount, ns_, 1, B), st); s2w::launch_tsum(ta, 1, B, st); }
-    }
+    if (gscal) sht_inverse_T(p, p->Lphi, p->wphi, gscal, p->Pphi, st);
     CombineArgs ca{};
-    ca.out = p->fhat;
+    ca.out = fhat;
     ca.L = p->L;
     for (size_t k = 0; k < p->S.s.size(); ++k) {
         auto &t = ca.t[ca.nterms++];
@@ -1167,7 +1328,7 @@ s2w_status s2w_analysis_adjoint(s2w_plan p, const void *gwav_, const double *gsc
         t.phr = 1.0;
         t.phi = 0.0;
     }
-    {
+    if (gscal) {
         auto &t = ca.t[ca.nterms++];
         t.P = p->Pphi;
         t.L = p->Lphi;
@@ -1176,33 +1337,120 @@ s2w_status s2w_analysis_adjoint(s2w_plan p, const void *gwav_, const double *gsc
         t.phi = 0.0;
     }
     { Prof pr_(p, "combine", 0.0, st); s2w::launch_combine(ca, B, st); }
-    // transpose of the forward SHT: l-sum (n = 0), T_sigma, then the phi transpose
-    {
-        const DevGrid &g = p->grids[p->L];
-        const int L = p->L, na = 2 * L - 1;
-        std::vector<int> n0{0};
-        LsumArgs la = lsum_args(p, g, L, n0);
-        la.flm = p->fhat;
-        la.flm_m = L;
-        la.flm_l = L;
-        la.w[0] = p->wsht;
-        la.wstride = 0;
-        la.out[0] = p->bufA;
-        { std::vector<int> ns_(la.nval, la.nval + la.nn); Prof pr_(p, "lsum", rec_flop(la.L, la.mcount, ns_, 1, B), st); s2w::launch_lsum(la, 1, B, st); }
+}
+
+// Transpose of synthesis_to_fhat: cotangent of the internal harmonic array fhat
+// ([B][L][L], read at l >= m) -> cotangents of the wavelet coefficients (and of the
+// scaling coefficients when gscal is not null).  Per scale: the sum over l against d
+// with the filter weights (the transpose of the theta sum; the same fhat row serves
+// every n, since the scale sum adds the n rows), the quadrature matrix, the gamma sum
+// with conj(xi) and the alpha c2r, both with the forward DFT weights and the m >= 1
+// terms halved.  Mixed plans run it in the precision split of the forward maps.
+static void synthesis_to_fhat_T(s2w_plan p, const double *fhat, void *gwav_, double *gscal, hipStream_t st)
+{
+    const bool mixed = p->prec == S2W_MIXED;
+    const int B = p->B;
+    const int npar = (p->N - 1) & 1;
+    for (auto &grp : p->groups) {
+        const DevGrid &g = p->grids[grp.L];
+        const int Lk = grp.L, NS = (int)grp.scales.size();
+        const auto &si = p->S.s[grp.scales[0]];
+        const int nn = (int)si.n.size(), ng = 2 * si.N - 1;
+        const size_t cstride = (size_t)B * nn * Lk * Lk * 2;
         int M0, M1;
-        sig_counts(L, 0, M0, M1);
-        { Prof pr_(p, "pack_sigma", 0.0, st); s2w::launch_pack_sigma(p->bufA, p->bufB, B, 1, L, L, 0, M0, M1, 0, st); }
-        theta_quadrature(p, g, p->bufB, p->bufC, L, 1, 0, st);
-        { Prof pr_(p, "pack_sigma", 0.0, st); s2w::launch_pack_sigma(p->bufC, p->bufA, B, 1, L, L, 0, M0, M1, 1, st); }
-        GammaArgs ga = gamma_args(p, L, L, L, L, n0, 1);
-        ga.src = p->bufA;
-        ga.dst = p->bufB;
-        ga.fm0 = 1.0;
-        ga.fm1 = 0.5;
-        { Prof pr_(p, "gamma_c2r", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_c2r(ga, st); }
-        { const DftArgs da_ = dft_args(g, p->bufB, L, gf, na, B * L, 2.0 * M_PI / na); Prof pr_(p, "dft_c2r", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_c2r(da_, st); }
+        sig_counts(Lk, npar, M0, M1);
+        LsumArgs la = lsum_args(p, g, Lk, si.n);
+        la.flm = fhat;
+        la.flm_m = p->L;
+        la.flm_l = p->L;
+        la.wstride = Lk;
+        if (mixed) {
+            float *A32 = (float *)p->bufA, *B32 = (float *)p->bufB, *C32 = (float *)p->bufC;
+            s2w::MixOut mo{};
+            mo.B = B;
+            for (int s = 0; s < NS; ++s) {
+                la.w[s] = p->wpsi[grp.scales[s]];
+                mo.out[s] = A32 + s * cstride;
+            }
+            { Prof pr_(p, "lsum_mm", rec_work_psi(p, grp.scales, la.L, la.mcount, si.n, B), st); s2w::launch_lsum_mm(la, mo, NS, st); }
+            for (int s = 0; s < NS; ++s) {
+                const int k = grp.scales[s];
+                { Prof pr_(p, "pack_sigma_f32", 0.0, st); s2w::launch_pack_sigma_f32(A32 + s * cstride, C32, B, nn, Lk, Lk, npar, M0, M1, 0, st); }
+                theta_quadrature32(p, g, C32, B32, Lk, nn, npar, st);
+                { Prof pr_(p, "pack_sigma_f32", 0.0, st); s2w::launch_pack_sigma_f32(B32, C32, B, nn, Lk, Lk, npar, M0, M1, 1, st); }
+                GammaArgs ga = gamma_args(p, Lk, Lk, Lk, Lk, si.n, ng);
+                ga.src = C32;
+                ga.dst = B32;
+                ga.wscale = (2.0 * M_PI / (2 * Lk - 1)) * (2.0 * M_PI / ng);
+                ga.fm0 = 1.0;
+                ga.fm1 = 0.5;
+                if (p->F.xi_imag) { ga.phr = 0.0; ga.phi = -1.0; }   // conj(xi) = -i
+                { Prof pr_(p, "gamma_c2r_f32", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_c2r(ga, st, true); }
+                const DftArgs da = dft_args(g, B32, Lk, (float *)gwav_ + p->wav_off[k], 2 * Lk - 1, B * ng * Lk, 1.0);
+                Prof pr_(p, "dft_c2r_f32", dft_flop(da.n, da.nrows), st);
+                s2w::launch_dft_c2r(da, st, true);
+            }
+        } else {
+            for (int s = 0; s < NS; ++s) {
+                la.w[s] = p->wpsi[grp.scales[s]];
+                la.out[s] = p->bufA + s * cstride;
+            }
+            { Prof pr_(p, "lsum", rec_work_psi(p, grp.scales, la.L, la.mcount, si.n, B), st); s2w::launch_lsum(la, NS, B, st); }
+            for (int s = 0; s < NS; ++s) {
+                const int k = grp.scales[s];
+                { Prof pr_(p, "pack_sigma", 0.0, st); s2w::launch_pack_sigma(p->bufA + s * cstride, p->bufC, B, nn, Lk, Lk, npar, M0, M1, 0, st); }
+                theta_quadrature(p, g, p->bufC, p->bufB, Lk, nn, npar, st);
+                { Prof pr_(p, "pack_sigma", 0.0, st); s2w::launch_pack_sigma(p->bufB, p->bufC, B, nn, Lk, Lk, npar, M0, M1, 1, st); }
+                GammaArgs ga = gamma_args(p, Lk, Lk, Lk, Lk, si.n, ng);
+                ga.src = p->bufC;
+                ga.dst = p->bufB;
+                ga.wscale = (2.0 * M_PI / (2 * Lk - 1)) * (2.0 * M_PI / ng);
+                ga.fm0 = 1.0;
+                ga.fm1 = 0.5;
+                if (p->F.xi_imag) { ga.phr = 0.0; ga.phi = -1.0; }
+                { Prof pr_(p, "gamma_c2r", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_c2r(ga, st); }
+                const DftArgs da_ = dft_args(g, p->bufB, Lk, (double *)gwav_ + p->wav_off[k], 2 * Lk - 1, B * ng * Lk, 1.0);
+                Prof pr_(p, "dft_c2r", dft_flop(da_.n, da_.nrows), st);
+                s2w::launch_dft_c2r(da_, st);
+            }
+        }
     }
+    if (gscal) sht_forward_T(p, p->Lphi, p->wphi, fhat, p->L, p->L, gscal, st);
+}
+
+s2w_status s2w_analysis_adjoint(s2w_plan p, const void *gwav_, const double *gscal, double *gf, void *stream)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (!gf || !gwav_ || !gscal) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    analysis_from_flm_T(p, gwav_, gscal, p->fhat, st);
+    sht_forward_T(p, p->L, p->wsht, p->fhat, p->L, p->L, gf, st);
     return post_launch("s2w_analysis_adjoint");
+}
+
+s2w_status s2w_synthesis_adjoint(s2w_plan p, const double *gf, void *gwav_, double *gscal, void *stream)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (!gf || !gwav_ || !gscal) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    sht_inverse_T(p, p->L, p->wsht, gf, p->fhat, st);
+    synthesis_to_fhat_T(p, p->fhat, gwav_, gscal, st);
+    return post_launch("s2w_synthesis_adjoint");
+}
+
+s2w_status s2w_analysis_lm(s2w_plan p, const double *flm, void *wav_, double *scal, void *stream)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (!flm || !wav_ || !scal) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    if (p->graph && !p->capturing)
+        return run_graph(p, 2, flm, wav_, scal, st, [&](hipStream_t cs) {
+            s2w::launch_flm_from_ext(flm, p->flm, p->L, p->B, cs);
+            analysis_from_flm(p, p->flm, wav_, scal, cs);
+        });
+    s2w::launch_flm_from_ext(flm, p->flm, p->L, p->B, st);
+    analysis_from_flm(p, p->flm, wav_, scal, st);
+    return post_launch("s2w_analysis_lm");
 }
 
 s2w_status s2w_plan_profile(s2w_plan p, int capacity)
@@ -1217,6 +1465,8 @@ s2w_status s2w_plan_profile(s2w_plan p, int capacity)
     p->ev1.clear();
     p->rec_name.clear();
     p->rec_flop.clear();
+    p->rec_flop64.clear();
+    p->rec_dense.clear();
     p->prof_names.clear();
     p->prof_dropped = 0;
     p->prof_cap = 0;
@@ -1232,19 +1482,22 @@ s2w_status s2w_plan_profile(s2w_plan p, int capacity)
 }
 
 s2w_status s2w_plan_profile_read(s2w_plan p, int max, char *names, double *total_ms, int64_t *launches,
-                                 double *flop, int *count, int64_t *dropped)
+                                 double *flop, double *flop64, double *dense, int *count, int64_t *dropped)
 {
     if (s2w_status st = check_plan(p)) return st;
     if (hipDeviceSynchronize() != hipSuccess) return fail(S2W_EHIP, "device synchronisation failed");
     const int nn = (int)p->prof_names.size();
-    std::vector<double> ms(nn, 0.0), fl(nn, 0.0);
+    std::vector<double> ms(nn, 0.0), fl(nn, 0.0), f64(nn, 0.0), dn(nn, 0.0);
     std::vector<int64_t> cnt(nn, 0);
     for (size_t i = 0; i < p->rec_name.size(); ++i) {
         float t = 0.0f;
         if (hipEventElapsedTime(&t, p->ev0[i], p->ev1[i]) != hipSuccess) return fail(S2W_EHIP, "event timing failed");
-        ms[p->rec_name[i]] += t;
-        fl[p->rec_name[i]] += p->rec_flop[i];
-        cnt[p->rec_name[i]] += 1;
+        const int id = p->rec_name[i];
+        ms[id] += t;
+        fl[id] += p->rec_flop[i];
+        f64[id] += p->rec_flop64[i];
+        dn[id] += p->rec_dense[i];
+        cnt[id] += 1;
     }
     const int k = std::min(nn, max);
     for (int i = 0; i < k; ++i) {
@@ -1255,11 +1508,15 @@ s2w_status s2w_plan_profile_read(s2w_plan p, int max, char *names, double *total
         if (total_ms) total_ms[i] = ms[i];
         if (launches) launches[i] = cnt[i];
         if (flop) flop[i] = fl[i];
+        if (flop64) flop64[i] = f64[i];
+        if (dense) dense[i] = dn[i];
     }
     if (count) *count = k;
     if (dropped) *dropped = p->prof_dropped;
     p->rec_name.clear();
     p->rec_flop.clear();
+    p->rec_flop64.clear();
+    p->rec_dense.clear();
     p->prof_dropped = 0;
     return S2W_OK;
 }
@@ -1292,6 +1549,15 @@ static bool ball_upload(b3w_plan p, double *&ptr, const std::vector<double> &h)
     p->allocs.push_back(v);
     ptr = (double *)v;
     return hipMemcpy(ptr, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+// [c][r] from a row-major [r][c] matrix
+static std::vector<double> transpose(const std::vector<double> &a, int r, int c)
+{
+    std::vector<double> t((size_t)r * c);
+    for (int i = 0; i < r; ++i)
+        for (int j = 0; j < c; ++j) t[(size_t)j * r + i] = a[(size_t)i * c + j];
+    return t;
 }
 
 static bool ball_alloc(b3w_plan p, double *&ptr, size_t count)
@@ -1362,8 +1628,12 @@ s2w_status b3w_plan_create(b3w_plan *out, int L, int N, int P, double lambda, do
             zi[(size_t)k * P + q] = K[(size_t)q * P + k];
         }
     if (!ball_upload(p, p->Zf, zf) || !ball_upload(p, p->Zi, zi)) return oom("radial tables");
+    if (!ball_upload(p, p->Zft, transpose(zf, P, P)) || !ball_upload(p, p->Zit, transpose(zi, P, P)))
+        return oom("radial tables");
     p->G.assign(p->nrad, nullptr);
     p->H.assign(p->nrad, nullptr);
+    p->Gt.assign(p->nrad, nullptr);
+    p->Ht.assign(p->nrad, nullptr);
     for (int i = 0; i < p->nrad; ++i) {
         const int jp = J0p + i, Pi = p->Pj[i];
         std::vector<double> kap(P);
@@ -1379,6 +1649,8 @@ s2w_status b3w_plan_create(b3w_plan *out, int L, int N, int P, double lambda, do
                 h[(size_t)q * Pi + k] = kap[q] * Ri.W[k] * Ki[(size_t)q * Pi + k];
             }
         if (!ball_upload(p, p->G[i], g) || !ball_upload(p, p->H[i], h)) return oom("radial tables");
+        if (!ball_upload(p, p->Gt[i], transpose(g, Pi, P)) || !ball_upload(p, p->Ht[i], transpose(h, P, Pi)))
+            return oom("radial tables");
     }
     {
         std::vector<double> ph((size_t)P * L);
@@ -1399,6 +1671,7 @@ s2w_status b3w_plan_create(b3w_plan *out, int L, int N, int P, double lambda, do
         delete p;
         return fail(S2W_EHIP, "device synchronisation failed during plan creation");
     }
+    reg_add(p);
     *out = p;
     return S2W_OK;
 }
@@ -1406,8 +1679,7 @@ s2w_status b3w_plan_create(b3w_plan *out, int L, int N, int P, double lambda, do
 s2w_status b3w_plan_destroy(b3w_plan p)
 {
     if (!p) return S2W_OK;
-    if (!p->alive) return fail(S2W_ESTATE, "plan destroyed twice");
-    p->alive = false;
+    if (!reg_remove(p)) return fail(S2W_ESTATE, "not a live ball plan (destroyed twice, or never created)");
     free_ball(p);
     delete p;
     return S2W_OK;
@@ -1416,7 +1688,7 @@ s2w_status b3w_plan_destroy(b3w_plan p)
 s2w_status b3w_plan_layout(b3w_plan p, int *nang, int *nrad, int *Lk, int *Nk, int *Pk, int64_t *wav_offset,
                            double *nodes)
 {
-    if (!p || !p->alive) return fail(S2W_EINVAL, "invalid plan");
+    if (s2w_status st = check_ball(p)) return st;
     if (nang) *nang = p->nang;
     if (nrad) *nrad = p->nrad;
     for (int k = 0; k < p->nang; ++k) {
@@ -1445,7 +1717,7 @@ static void ball_radial(b3w_plan p, const double *A, const double *in, int kin, 
 
 s2w_status b3w_analysis(b3w_plan p, const double *f, void *wav, double *scal, void *stream)
 {
-    if (!p || !p->alive) return fail(S2W_EINVAL, "invalid plan");
+    if (s2w_status st = check_ball(p)) return st;
     if (!f || !wav || !scal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
     s2w_plan sp = p->sp;
@@ -1470,7 +1742,7 @@ s2w_status b3w_analysis(b3w_plan p, const double *f, void *wav, double *scal, vo
 
 s2w_status b3w_synthesis(b3w_plan p, const void *wav, const double *scal, double *f, void *stream)
 {
-    if (!p || !p->alive) return fail(S2W_EINVAL, "invalid plan");
+    if (s2w_status st = check_ball(p)) return st;
     if (!f || !wav || !scal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
     s2w_plan sp = p->sp;
@@ -1496,11 +1768,75 @@ s2w_status b3w_synthesis(b3w_plan p, const void *wav, const double *scal, double
     return post_launch("b3w_synthesis");
 }
 
+// Transpose of b3w_analysis (the gradient with respect to f): scaling part (transposes of
+// Y^{-1}, Z^{-1} and the scaling filter), then per radial scale the transpose of the
+// sphere analysis on its shells and of the radial projection onto its nodes, accumulated
+// into the cotangent of f_lmp; finally the transposes of the radial forward and of Y.
+s2w_status b3w_analysis_adjoint(b3w_plan p, const void *gwav, const double *gscal, double *gf, void *stream)
+{
+    if (s2w_status st = check_ball(p)) return st;
+    if (!gf || !gwav || !gscal) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    s2w_plan sp = p->sp;
+    const int B = p->B, P = p->P, L = p->L;
+    const size_t esz = p->prec == S2W_MIXED ? sizeof(float) : sizeof(double);
+    {
+        BatchScope bs(sp, B * P);
+        sht_inverse_T(sp, L, sp->wsht, gscal, p->shell, st);
+        ball_radial(p, p->Zit, p->shell, P, p->shell2, P, false, st);
+        { Prof pr_(sp, "scale_pl", 0.0, st); s2w::launch_scale_pl(p->shell2, p->flmp, p->phi, P, L, (size_t)B * P * L * L, st); }
+    }
+    for (int i = 0; i < p->nrad; ++i) {
+        const int Pi = p->Pj[i];
+        BatchScope bs(sp, B * Pi);
+        analysis_from_flm_T(sp, (const char *)gwav + esz * p->wav_off[(size_t)i * p->nang], nullptr, p->shell, st);
+        ball_radial(p, p->Gt[i], p->shell, Pi, p->flmp, P, true, st);
+    }
+    {
+        BatchScope bs(sp, B * P);
+        ball_radial(p, p->Zft, p->flmp, P, p->shell, P, false, st);
+        sht_forward_T(sp, L, sp->wsht, p->shell, L, L, gf, st);
+    }
+    return post_launch("b3w_analysis_adjoint");
+}
+
+// Transpose of b3w_synthesis: transposes of Y^{-1} and of the radial inverse give the
+// cotangent of f_lmp; per radial scale, the transpose of its radial synthesis matrix and
+// of the sphere synthesis on its shells; the scaling part through the scaling filter and
+// the transposes of the radial forward and of Y.
+s2w_status b3w_synthesis_adjoint(b3w_plan p, const double *gf, void *gwav, double *gscal, void *stream)
+{
+    if (s2w_status st = check_ball(p)) return st;
+    if (!gf || !gwav || !gscal) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    s2w_plan sp = p->sp;
+    const int B = p->B, P = p->P, L = p->L;
+    const size_t esz = p->prec == S2W_MIXED ? sizeof(float) : sizeof(double);
+    {
+        BatchScope bs(sp, B * P);
+        sht_inverse_T(sp, L, sp->wsht, gf, p->shell, st);
+        ball_radial(p, p->Zit, p->shell, P, p->flmp, P, false, st);
+    }
+    for (int i = 0; i < p->nrad; ++i) {
+        const int Pi = p->Pj[i];
+        BatchScope bs(sp, B * Pi);
+        ball_radial(p, p->Ht[i], p->flmp, P, p->shell, Pi, false, st);
+        synthesis_to_fhat_T(sp, p->shell, (char *)gwav + esz * p->wav_off[(size_t)i * p->nang], nullptr, st);
+    }
+    {
+        BatchScope bs(sp, B * P);
+        { Prof pr_(sp, "scale_pl", 0.0, st); s2w::launch_scale_pl(p->flmp, p->shell2, p->phi, P, L, (size_t)B * P * L * L, st); }
+        ball_radial(p, p->Zft, p->shell2, P, p->shell, P, false, st);
+        sht_forward_T(sp, L, sp->wsht, p->shell, L, L, gscal, st);
+    }
+    return post_launch("b3w_synthesis_adjoint");
+}
+
 // Z and Z^{-1}: per-shell spherical-harmonic transforms (B P shells at a time) and the
 // radial projection onto the Laguerre basis (quadrature weights folded into Zf)
 s2w_status b3w_sl_forward(b3w_plan p, const double *f, double *flmp, void *stream)
 {
-    if (!p || !p->alive) return fail(S2W_EINVAL, "invalid plan");
+    if (s2w_status st = check_ball(p)) return st;
     if (!f || !flmp) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
     s2w_plan sp = p->sp;
@@ -1516,7 +1852,7 @@ s2w_status b3w_sl_forward(b3w_plan p, const double *f, double *flmp, void *strea
 
 s2w_status b3w_sl_inverse(b3w_plan p, const double *flmp, double *f, void *stream)
 {
-    if (!p || !p->alive) return fail(S2W_EINVAL, "invalid plan");
+    if (s2w_status st = check_ball(p)) return st;
     if (!f || !flmp) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
     s2w_plan sp = p->sp;
@@ -1532,15 +1868,15 @@ s2w_status b3w_sl_inverse(b3w_plan p, const double *flmp, double *f, void *strea
 
 s2w_status b3w_plan_profile(b3w_plan p, int capacity)
 {
-    if (!p || !p->alive) return fail(S2W_EINVAL, "invalid plan");
+    if (s2w_status st = check_ball(p)) return st;
     return s2w_plan_profile(p->sp, capacity);
 }
 
 s2w_status b3w_plan_profile_read(b3w_plan p, int max, char *names, double *total_ms, int64_t *launches,
-                                 double *flop, int *count, int64_t *dropped)
+                                 double *flop, double *flop64, double *dense, int *count, int64_t *dropped)
 {
-    if (!p || !p->alive) return fail(S2W_EINVAL, "invalid plan");
-    return s2w_plan_profile_read(p->sp, max, names, total_ms, launches, flop, count, dropped);
+    if (s2w_status st = check_ball(p)) return st;
+    return s2w_plan_profile_read(p->sp, max, names, total_ms, launches, flop, flop64, dense, count, dropped);
 }
 
 }  // extern "C"

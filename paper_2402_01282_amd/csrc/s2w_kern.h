@@ -133,6 +133,8 @@ void launch_convert(const void *in, void *out, size_t n, bool to_f32, hipStream_
 void launch_combine(const CombineArgs &a, int B, hipStream_t st);
 void launch_pack_sigma(const double *in, double *out, int B, int nn, int M, int L, int npar, int M0,
                        int M1, int dir, hipStream_t st);
+void launch_pack_sigma_f32(const float *in, float *out, int B, int nn, int M, int L, int npar, int M0,
+                           int M1, int dir, hipStream_t st);
 void launch_flm_to_ext(const double *in, double *out, int L, int B, hipStream_t st);
 void launch_flm_from_ext(const double *in, double *out, int L, int B, hipStream_t st);
 

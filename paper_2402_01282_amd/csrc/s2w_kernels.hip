@@ -895,14 +895,12 @@ __global__ __launch_bounds__(256) void k_gemm(const Tp *__restrict__ A, const Tp
 // holds at most one such task per stage, a stage reads its buffer, waits at a
 // barrier and overwrites it in place (one LDS buffer of n per row pair).
 // Rows are paired as z = x1 + i x2 (two real rows per complex DFT).  Tr is the
-// arithmetic type (double; float in the mixed-precision path).
+// arithmetic type; only FP64 is defined (DftBlk has no other specialisation, so
+// the paired kernels cannot be instantiated for FP32: the FP32 path uses the
+// matrix-core DFT and the direct prime-factor kernels below).
 
 template <typename Tr>
 struct DftBlk;
-template <>
-struct DftBlk<float> {
-    static constexpr int J = 4, C = 3;
-};
 template <>
 struct DftBlk<double> {
     static constexpr int J = 2, C = 3;
@@ -1812,6 +1810,13 @@ void launch_pack_sigma(const double *in, double *out, int B, int nn, int M, int 
 {
     dim3 grid((L + 255) / 256, M, B * nn);
     hipLaunchKernelGGL(k_pack_sigma<double>, grid, dim3(256), 0, st, in, out, B, nn, M, L, npar, M0, M1, dir);
+}
+
+void launch_pack_sigma_f32(const float *in, float *out, int B, int nn, int M, int L, int npar, int M0,
+                           int M1, int dir, hipStream_t st)
+{
+    dim3 grid((L + 255) / 256, M, B * nn);
+    hipLaunchKernelGGL(k_pack_sigma<float>, grid, dim3(256), 0, st, in, out, B, nn, M, L, npar, M0, M1, dir);
 }
 
 void launch_flm_to_ext(const double *in, double *out, int L, int B, hipStream_t st)

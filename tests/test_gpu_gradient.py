@@ -84,9 +84,10 @@ def test_gradient_L1024_N8_directional_derivative():
 
 @pytest.mark.parametrize("L,N,B", [(16, 3, 2), (64, 4, 3)])
 def test_mixed_gradient(L, N, B):
-    """Mixed plans: the adjoint (FP64 arithmetic on the FP32 cotangents) equals the
-    oracle's adjoint of the same cotangents to 1e-12, and the gradient of the FP32
-    loss is within 1e-6 of the exact FP64 gradient."""
+    """Mixed plans: the adjoint (in the forward precision split: FP32 matrix-core DFTs
+    and theta sum on the FP32 cotangents, FP64 recursion and sums) is within 1e-6 of the
+    oracle's adjoint of the same cotangents, and the gradient of the FP32 loss is within
+    1e-6 of the exact FP64 gradient."""
     torch = _torch()
     import paper_2402_01282_amd as s2w
     plan = s2w.Plan(L, N, 2.0, 0, batch=B, precision=s2w.S2W_MIXED, device=0)
@@ -100,7 +101,7 @@ def test_mixed_gradient(L, N, B):
     for b in range(B):
         gw = [2 * v[b].double().cpu().numpy() for v in views]
         ref = wavelets.analysis_adjoint(gw, np.zeros(plan.scal_shape[1:]), P)
-        assert np.linalg.norm(got[b] - ref) / np.linalg.norm(ref) < 1e-12
+        assert np.linalg.norm(got[b] - ref) / np.linalg.norm(ref) < 1e-6
         wex, sex = wavelets.analysis(maps[b], P)
         exact = wavelets.analysis_adjoint([2 * w for w in wex], np.zeros_like(sex), P)
         assert np.linalg.norm(got[b] - exact) / np.linalg.norm(exact) < 1e-6

@@ -105,3 +105,23 @@ def test_separable_input_factorises_into_sphere_wavelets():
         for k in range(len(BP.ang.scales)):
             ref = prof[:, None, None, None] * wsph[k][None]
             np.testing.assert_allclose(wav[(i, k)], ref, atol=1e-13 * (np.abs(ref).max() + 1e-300))
+
+
+@pytest.mark.parametrize("L,N,P,J0,J0p,tau", [(6, 3, 5, 0, 0, 1.0), (8, 2, 6, 1, 1, 0.8)])
+def test_ball_adjoints_dot(L, N, P, J0, J0p, tau):
+    """<A x, y> = <x, A^T y> for the ball analysis, and <S y, x> = <y, S^T x> for the
+    ball synthesis, on random non-band-limited arrays."""
+    BP = ball.BallPlan(L, N, P, 2.0, 2.0, J0, J0p, tau)
+    rng = np.random.default_rng(L * P + N)
+    x = rng.normal(size=(P, L, 2 * L - 1))
+    Aw, As = ball.analysis(x, BP)
+    yw = {k: rng.normal(size=v.shape) for k, v in Aw.items()}
+    ys = rng.normal(size=As.shape)
+    lhs = sum(np.sum(Aw[k] * yw[k]) for k in Aw) + np.sum(As * ys)
+    ATy = ball.analysis_adjoint(yw, ys, BP)
+    assert abs(lhs - np.sum(x * ATy)) < 1e-11 * abs(lhs)
+    Sy = ball.synthesis(yw, ys, BP)
+    gw, gs = ball.synthesis_adjoint(x, BP)
+    lhs2 = np.sum(Sy * x)
+    rhs2 = sum(np.sum(yw[k] * gw[k]) for k in yw) + np.sum(ys * gs)
+    assert abs(lhs2 - rhs2) < 1e-11 * abs(lhs2)

@@ -161,3 +161,23 @@ def test_gradient_central_differences():
         e[i, j] = h
         fd = (loss(f + e) - loss(f - e)) / (2 * h)
         assert abs(fd - g[i, j]) < 1e-9 * max(1.0, abs(g[i, j]))
+
+
+@pytest.mark.parametrize("L,N,J0", [(8, 3, 0), (16, 4, 1), (12, 2, 0), (9, 5, 0)])
+def test_synthesis_adjoint_dot(L, N, J0):
+    """<S(w, s), g> = <w, S^T_w g> + <s, S^T_s g> on random, non-band-limited arrays
+    (S the synthesis, a real-linear map of the sample arrays)."""
+    P = wavelets.Plan(L, N, 2.0, J0)
+    rng = np.random.default_rng(7 * L + N)
+    f0 = rng.normal(size=(L, 2 * L - 1))
+    w0, s0 = wavelets.analysis(f0, P)
+    w = [rng.normal(size=a.shape) for a in w0]
+    s = rng.normal(size=s0.shape)
+    g = rng.normal(size=(L, 2 * L - 1))
+    lhs = np.sum(wavelets.synthesis(w, s, P) * g)
+    gw, gs = wavelets.synthesis_adjoint(g, P)
+    rhs = sum(np.sum(a * b) for a, b in zip(w, gw)) + np.sum(s * gs)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    # S^T is not the analysis (MW oversamples)
+    aw, _ = wavelets.analysis(g, P)
+    assert max(np.abs(a - b).max() for a, b in zip(aw, gw)) > 1e-3
