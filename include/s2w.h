@@ -61,11 +61,18 @@ typedef struct s2w_plan_s *s2w_plan;
 enum {
     S2W_PLAN_TUNE = 1,      /* time the l-contraction tile shapes on the device at creation and
                                keep the fastest per grid (creation then synchronises the device) */
-    S2W_PLAN_GRAPH = 2      /* s2w_analysis / s2w_synthesis capture their launches into a HIP graph
+    S2W_PLAN_GRAPH = 2,     /* s2w_analysis / s2w_synthesis capture their launches into a HIP graph
                                on the first call with a given (input, output, output) pointer triple
                                and replay it afterwards (up to 16 triples per plan; kernel timing is
                                not recorded for graph replays) */
+    S2W_PLAN_NO_WORKSPACE = 4  /* allocate no workspace (tables only): the plan runs only through
+                               s2w_analysis_noalloc; other transform entry points return S2W_ESTATE.
+                               Excludes S2W_PLAN_TUNE and S2W_PLAN_GRAPH. */
 };
+
+/* Size of the static device scratch that s2w_analysis_noalloc works in (one copy per
+ * device, held until the process ends). */
+#define S2W_SCRATCH_BYTES (64ull << 20)
 
 /* Create a plan for band limit L >= 2, azimuthal band limit 1 <= N <= L, dilation
  * lambda > 1, lowest wavelet scale 0 <= J0 <= J, batch >= 1 maps per call, on HIP
@@ -87,6 +94,18 @@ s2w_status s2w_plan_layout(s2w_plan plan, int *nscales, int *J0, int *Lk, int *N
  * coefficients.  f: device [B][L][2L-1]; wav: device, packed (see above);
  * scal: device [B][L_phi][2L_phi-1]. */
 s2w_status s2w_analysis(s2w_plan plan, const double *f, void *wav, double *scal, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): s2w_analysis with its workspace in a
+ * static device array of S2W_SCRATCH_BYTES instead of the plan's own buffers.  It calls no
+ * hipMalloc, hipFree or allocating routine; the caller passes inputs and outputs as for
+ * s2w_analysis, on any plan (typically one created with S2W_PLAN_NO_WORKSPACE).  Plans
+ * whose workspace exceeds the scratch are rejected with S2W_EUNSUPPORTED (the batch-1 FP64
+ * plan at L = 256, N = 4 needs about 37 MB; L = 512, N = 8 needs more than 64 MiB).  Every
+ * call on a device shares that device's scratch and leaves its contents behind: calls that
+ * overlap on one device (on different streams, or host threads) race and must be ordered
+ * by the caller.  Runs eagerly (no graph replay). */
+s2w_status s2w_analysis_noalloc(s2w_plan plan, const double *f, void *wav, double *scal, void *stream);
 
 /* Wavelet synthesis (Algorithm 1, synthesis): coefficients -> real maps. */
 s2w_status s2w_synthesis(s2w_plan plan, const void *wav, const double *scal, double *f, void *stream);

@@ -22,6 +22,8 @@ S2W_FP64 = 0
 S2W_MIXED = 1
 S2W_PLAN_TUNE = 1
 S2W_PLAN_GRAPH = 2
+S2W_PLAN_NO_WORKSPACE = 4
+S2W_SCRATCH_BYTES = 64 << 20
 
 _STATUS = {0: "S2W_OK", -1: "S2W_EINVAL", -2: "S2W_ENOMEM", -3: "S2W_EHIP",
            -4: "S2W_EUNSUPPORTED", -5: "S2W_ESTATE"}
@@ -50,6 +52,7 @@ def _load():
         "s2w_analysis_adjoint": [vp, vp, vp, vp, vp],
         "s2w_synthesis_adjoint": [vp, vp, vp, vp, vp],
         "s2w_analysis_lm": [vp, vp, vp, vp, vp],
+        "s2w_analysis_noalloc": [vp, vp, vp, vp, vp],
         "s2w_sht_forward": [vp, vp, vp, vp],
         "s2w_sht_inverse": [vp, vp, vp, vp],
         "s2w_plan_profile": [vp, ctypes.c_int],
@@ -86,7 +89,7 @@ _lib = _load()
 
 # every symbol the header declares (checked by the tests)
 EXPORTS = ["s2w_plan_create", "s2w_plan_destroy", "s2w_plan_layout", "s2w_analysis", "s2w_synthesis",
-           "s2w_analysis_lm", "s2w_analysis_adjoint", "s2w_synthesis_adjoint", "s2w_sht_forward", "s2w_sht_inverse",
+           "s2w_analysis_lm", "s2w_analysis_noalloc", "s2w_analysis_adjoint", "s2w_synthesis_adjoint", "s2w_sht_forward", "s2w_sht_inverse",
            "s2w_plan_profile", "s2w_plan_profile_read",
            "s2w_last_error", "s2w_host_scales", "s2w_host_filters", "s2w_host_theta_matrix",
            "s2w_host_wigner_d", "s2w_host_laguerre_rule",
@@ -259,6 +262,17 @@ class Plan:
         scal = self._out(scal, self.scal_shape, torch.float64, "scal")
         _check(_lib.s2w_analysis(self._h, self._p(f), self._p(wav), self._p(scal),
                                  _stream_ptr(torch, self.device)))
+        return wav, scal
+
+    def analysis_noalloc(self, f, wav, scal):
+        """s2w_analysis with the workspace in the library's static device scratch (no
+        allocation in the call; outputs must be given)."""
+        torch = self._torch
+        self._check_map(f)
+        self._check_wav(wav)
+        self._check_scal(scal)
+        _check(_lib.s2w_analysis_noalloc(self._h, self._p(f), self._p(wav), self._p(scal),
+                                         _stream_ptr(torch, self.device)))
         return wav, scal
 
     def analysis_lm(self, flm, wav=None, scal=None):

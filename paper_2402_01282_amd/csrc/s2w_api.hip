@@ -16,6 +16,13 @@
 #include "s2w_host.h"
 #include "s2w_kern.h"
 
+// Static scratch for s2w_analysis_noalloc: the workspace of a plan created with
+// S2W_PLAN_NO_WORKSPACE is carved out of this array, one copy per device, held until
+// the process ends.  In host code `scratch` names a host-side stand-in; its device
+// address is resolved once per device (hipGetSymbolAddress with that device current, at
+// plan creation) and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[S2W_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
@@ -50,6 +57,33 @@ bool reg_remove(const void *h)
 {
     std::lock_guard<std::mutex> lk(g_reg_mu);
     return g_live.erase(h) != 0;
+}
+
+// device address of the static scratch per device (resolved at plan creation)
+std::mutex g_scr_mu;
+std::map<int, unsigned char *> g_scr;
+
+// Resolves the current device's scratch address once; false on failure.
+bool scratch_resolve(int device)
+{
+    std::lock_guard<std::mutex> lk(g_scr_mu);
+    auto it = g_scr.find(device);
+    if (it != g_scr.end()) return it->second != nullptr;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        ptr = nullptr;
+    }
+    g_scr[device] = (unsigned char *)ptr;
+    return ptr != nullptr;
+}
+
+unsigned char *scratch_ptr(int device)
+{
+    std::lock_guard<std::mutex> lk(g_scr_mu);
+    auto it = g_scr.find(device);
+    return it == g_scr.end() ? nullptr : it->second;
 }
 
 struct DevDft {
@@ -114,6 +148,11 @@ struct s2w_plan_s {
     double *flm = nullptr, *fhat = nullptr;
     double *bufA = nullptr, *bufB = nullptr, *bufC = nullptr;
     size_t szA = 0, szB = 0, szC = 0;
+    // every workspace buffer (its pointer in this plan, size in doubles), in layout order;
+    // ws_bytes: their total with each start rounded up to 256 bytes
+    std::vector<std::pair<double **, size_t>> ws;
+    size_t ws_bytes = 0;
+    bool no_ws = false;                      // created with S2W_PLAN_NO_WORKSPACE
     std::vector<double *> P;                 // per scale [B][L_k][nn][L_k] complex
     double *Pphi = nullptr;
     std::vector<Group> groups;
@@ -682,6 +721,14 @@ s2w_status check_plan(s2w_plan p)
     return S2W_OK;
 }
 
+// transform entry points that use the plan's own workspace
+s2w_status check_ws(s2w_plan p)
+{
+    if (p->no_ws)
+        return fail(S2W_ESTATE, "plan created with S2W_PLAN_NO_WORKSPACE: only s2w_analysis_noalloc runs on it");
+    return S2W_OK;
+}
+
 s2w_status check_ball(b3w_plan p)
 {
     if (!p) return fail(S2W_EINVAL, "null plan");
@@ -769,7 +816,10 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
     if (!out) return fail(S2W_EINVAL, "null output pointer");
     *out = nullptr;
     if (batch < 1) return fail(S2W_EINVAL, "batch must be >= 1");
-    if (flags & ~(unsigned)(S2W_PLAN_TUNE | S2W_PLAN_GRAPH)) return fail(S2W_EINVAL, "unknown flags");
+    if (flags & ~(unsigned)(S2W_PLAN_TUNE | S2W_PLAN_GRAPH | S2W_PLAN_NO_WORKSPACE))
+        return fail(S2W_EINVAL, "unknown flags");
+    if ((flags & S2W_PLAN_NO_WORKSPACE) && (flags & (S2W_PLAN_TUNE | S2W_PLAN_GRAPH)))
+        return fail(S2W_EINVAL, "S2W_PLAN_NO_WORKSPACE excludes S2W_PLAN_TUNE and S2W_PLAN_GRAPH");
     if (precision != S2W_FP64 && precision != S2W_MIXED) return fail(S2W_EINVAL, "unknown precision");
     s2w::Scales S;
     std::string err;
@@ -779,6 +829,8 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(S2W_EHIP, "no HIP device");
     if (device < 0 || device >= ndev) return fail(S2W_EINVAL, "bad device index");
     if (hipSetDevice(device) != hipSuccess) return fail(S2W_EHIP, "hipSetDevice failed");
+    if (!scratch_resolve(device) && (flags & S2W_PLAN_NO_WORKSPACE))
+        return fail(S2W_EHIP, "hipGetSymbolAddress of the static scratch failed");
 
     s2w_plan p = new (std::nothrow) s2w_plan_s;
     if (!p) return fail(S2W_ENOMEM, "host allocation failed");
@@ -858,15 +910,19 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
             c = std::max(c, cbuf);
         }
         p->szA = a; p->szB = bsz; p->szC = c;
-        if (!dalloc(p, p->bufA, a) || !dalloc(p, p->bufB, bsz) || !dalloc(p, p->bufC, c)) return oom("workspace");
-        if (!dalloc(p, p->flm, (size_t)batch * L * L * 2) || !dalloc(p, p->fhat, (size_t)batch * L * L * 2))
-            return oom("workspace");
         p->P.assign(K, nullptr);
+        p->ws = {{&p->bufA, a}, {&p->bufB, bsz}, {&p->bufC, c}, {&p->flm, (size_t)batch * L * L * 2},
+                 {&p->fhat, (size_t)batch * L * L * 2}};
         for (int k = 0; k < K; ++k) {
             const int Lk = S.s[k].L, nn = (int)S.s[k].n.size();
-            if (!dalloc(p, p->P[k], (size_t)batch * Lk * nn * Lk * 2)) return oom("workspace");
+            p->ws.push_back({&p->P[k], (size_t)batch * Lk * nn * Lk * 2});
         }
-        if (!dalloc(p, p->Pphi, (size_t)batch * p->Lphi * p->Lphi * 2)) return oom("workspace");
+        p->ws.push_back({&p->Pphi, (size_t)batch * p->Lphi * p->Lphi * 2});
+        for (auto &it : p->ws) p->ws_bytes += (it.second * sizeof(double) + 255) / 256 * 256;
+        p->no_ws = (flags & S2W_PLAN_NO_WORKSPACE) != 0;
+        if (!p->no_ws)
+            for (auto &it : p->ws)
+                if (!dalloc(p, *it.first, it.second)) return oom("workspace");
     }
     if (flags & S2W_PLAN_TUNE) autotune(p);
     p->graph = (flags & S2W_PLAN_GRAPH) != 0;
@@ -914,6 +970,7 @@ s2w_status s2w_plan_layout(s2w_plan p, int *nscales, int *J0, int *Lk, int *Nk, 
 s2w_status s2w_sht_forward(s2w_plan p, const double *f, double *flm, void *stream)
 {
     if (s2w_status st = check_plan(p)) return st;
+    if (s2w_status st = check_ws(p)) return st;
     if (!f || !flm) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
     sht_forward_internal(p, f, p->flm, st);
@@ -924,6 +981,7 @@ s2w_status s2w_sht_forward(s2w_plan p, const double *f, double *flm, void *strea
 s2w_status s2w_sht_inverse(s2w_plan p, const double *flm, double *f, void *stream)
 {
     if (s2w_status st = check_plan(p)) return st;
+    if (s2w_status st = check_ws(p)) return st;
     if (!f || !flm) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
     s2w::launch_flm_from_ext(flm, p->flm, p->L, p->B, st);
@@ -1030,6 +1088,7 @@ static void analysis_from_flm(s2w_plan p, const double *flm, void *wav_, double 
 s2w_status s2w_analysis(s2w_plan p, const double *f, void *wav_, double *scal, void *stream)
 {
     if (s2w_status st = check_plan(p)) return st;
+    if (s2w_status st = check_ws(p)) return st;
     if (!f || !wav_ || !scal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
     // the forward SHT of the input map runs in FP64 in both forms: it is shared by every
@@ -1042,6 +1101,44 @@ s2w_status s2w_analysis(s2w_plan p, const double *f, void *wav_, double *scal, v
     sht_forward_internal(p, f, p->flm, st);
     analysis_from_flm(p, p->flm, wav_, scal, st);
     return post_launch("s2w_analysis");
+}
+
+// Points the plan's workspace buffers at consecutive 256-byte aligned slices of the
+// device scratch while the scope lives (kernel arguments are taken at launch, so the
+// plan's own pointers are restored on exit).
+struct ScratchScope {
+    s2w_plan p;
+    std::vector<double *> saved;
+    ScratchScope(s2w_plan p_, unsigned char *base) : p(p_)
+    {
+        size_t off = 0;
+        for (auto &it : p->ws) {
+            saved.push_back(*it.first);
+            *it.first = reinterpret_cast<double *>(base + off);
+            off += (it.second * sizeof(double) + 255) / 256 * 256;
+        }
+    }
+    ~ScratchScope()
+    {
+        for (size_t i = 0; i < saved.size(); ++i) *p->ws[i].first = saved[i];
+    }
+};
+
+s2w_status s2w_analysis_noalloc(s2w_plan p, const double *f, void *wav_, double *scal, void *stream)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (!f || !wav_ || !scal) return fail(S2W_EINVAL, "null buffer");
+    if (p->ws_bytes > S2W_SCRATCH_BYTES)
+        return fail(S2W_EUNSUPPORTED, "this plan needs " + std::to_string(p->ws_bytes) +
+                                          " bytes of workspace, more than the static scratch (" +
+                                          std::to_string((size_t)S2W_SCRATCH_BYTES) + " bytes)");
+    unsigned char *base = scratch_ptr(p->device);
+    if (!base) return fail(S2W_ESTATE, "the device scratch address was not resolved at plan creation");
+    hipStream_t st = (hipStream_t)stream;
+    ScratchScope sc(p, base);
+    sht_forward_internal(p, f, p->flm, st);
+    analysis_from_flm(p, p->flm, wav_, scal, st);
+    return post_launch("s2w_analysis_noalloc");
 }
 
 // Harmonic coefficients fhat (internal layout) of the synthesis before the
@@ -1164,6 +1261,7 @@ static void synthesis_to_fhat(s2w_plan p, const void *wav_, const double *scal, 
 s2w_status s2w_synthesis(s2w_plan p, const void *wav_, const double *scal, double *f, void *stream)
 {
     if (s2w_status st = check_plan(p)) return st;
+    if (s2w_status st = check_ws(p)) return st;
     if (!f || !wav_ || !scal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
     if (p->graph && !p->capturing)
@@ -1421,6 +1519,7 @@ static void synthesis_to_fhat_T(s2w_plan p, const double *fhat, void *gwav_, dou
 s2w_status s2w_analysis_adjoint(s2w_plan p, const void *gwav_, const double *gscal, double *gf, void *stream)
 {
     if (s2w_status st = check_plan(p)) return st;
+    if (s2w_status st = check_ws(p)) return st;
     if (!gf || !gwav_ || !gscal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
     analysis_from_flm_T(p, gwav_, gscal, p->fhat, st);
@@ -1431,6 +1530,7 @@ s2w_status s2w_analysis_adjoint(s2w_plan p, const void *gwav_, const double *gsc
 s2w_status s2w_synthesis_adjoint(s2w_plan p, const double *gf, void *gwav_, double *gscal, void *stream)
 {
     if (s2w_status st = check_plan(p)) return st;
+    if (s2w_status st = check_ws(p)) return st;
     if (!gf || !gwav_ || !gscal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
     sht_inverse_T(p, p->L, p->wsht, gf, p->fhat, st);
@@ -1441,6 +1541,7 @@ s2w_status s2w_synthesis_adjoint(s2w_plan p, const double *gf, void *gwav_, doub
 s2w_status s2w_analysis_lm(s2w_plan p, const double *flm, void *wav_, double *scal, void *stream)
 {
     if (s2w_status st = check_plan(p)) return st;
+    if (s2w_status st = check_ws(p)) return st;
     if (!flm || !wav_ || !scal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
     if (p->graph && !p->capturing)
