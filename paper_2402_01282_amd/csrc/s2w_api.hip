@@ -113,6 +113,37 @@ std::vector<float> dft_fragments(int p, const std::vector<double> &w)
     return f;
 }
 
+// BF16 bits of f, rounded to nearest (ties to even)
+uint16_t bf16_bits(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+double bf16_value(uint16_t h)
+{
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// x = x0 + x1 + x2 + O(2^-27 x) in BF16 parts, each the rounding of what the previous leave
+void bf16_split3(const std::vector<double> &x, std::vector<uint16_t> (&part)[3])
+{
+    for (auto &v : part) v.resize(x.size());
+    for (size_t i = 0; i < x.size(); ++i) {
+        double r = x[i];
+        for (int k = 0; k < 3; ++k) {
+            part[k][i] = bf16_bits((float)r);
+            r -= bf16_value(part[k][i]);
+        }
+    }
+}
+
 struct DevGrid {
     int L = 0;
     double *pol = nullptr;
@@ -120,6 +151,7 @@ struct DevGrid {
     double *cth = nullptr, *ctl = nullptr, *ch = nullptr, *sh = nullptr, *ceps = nullptr, *seps = nullptr;
     double *T[2] = {nullptr, nullptr};
     float *T32[2] = {nullptr, nullptr};
+    uint16_t *T3[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};   // BF16 parts of T
     DevDft dft;
 };
 
@@ -349,6 +381,12 @@ bool make_grid(s2w_plan p, int L)
         if (p->prec == S2W_MIXED) {
             std::vector<float> T32(T.begin(), T.end());
             if (!upload(p, g.T32[si], T32)) return false;
+            if (s2w::gemm_bf3_ok(L)) {
+                std::vector<uint16_t> parts[3];
+                bf16_split3(T, parts);   // T_sigma is applied as h = T F with T stored [theta][theta']
+                for (int k = 0; k < 3; ++k)
+                    if (!upload(p, g.T3[si][k], parts[k])) return false;
+            }
         }
     }
     const int n = 2 * L - 1;
@@ -591,6 +629,18 @@ void theta_quadrature32(s2w_plan p, const DevGrid &g, const float *F, float *H, 
     int M0, M1;
     sig_counts(M, npar, M0, M1);
     const size_t r0 = (size_t)p->B * M0 * nn * 2, r1 = (size_t)p->B * M1 * nn * 2;
+    if (g.T3[0][0]) {
+        // BF16x3 split on BF16 matrix cores (FP32 accuracy or better)
+        {
+            Prof pr_(p, "gemm_theta_bf3", Work{theta_fft_flop(g.L) * (r0 / 2), 0.0, 2.0 * (double)r0 * g.L * g.L}, st);
+            s2w::launch_gemm_bf3(F, g.T3[0][0], g.T3[0][1], g.T3[0][2], H, (int)r0, g.L, g.L, st);
+        }
+        {
+            Prof pr_(p, "gemm_theta_bf3", Work{theta_fft_flop(g.L) * (r1 / 2), 0.0, 2.0 * (double)r1 * g.L * g.L}, st);
+            s2w::launch_gemm_bf3(F + r0 * g.L, g.T3[1][0], g.T3[1][1], g.T3[1][2], H + r0 * g.L, (int)r1, g.L, g.L, st);
+        }
+        return;
+    }
     {
         Prof pr_(p, "gemm_theta_f32", Work{theta_fft_flop(g.L) * (r0 / 2), 0.0, 2.0 * (double)r0 * g.L * g.L}, st);
         s2w::launch_gemm_f32(F, g.T32[0], H, (int)r0, g.L, g.L, st);

@@ -120,6 +120,11 @@ void launch_gemm(const double *A, const double *Bm, double *C, int M, int N, int
                  bool accum = false);
 void launch_scale_pl(const double *in, double *out, const double *phi, int P, int L, size_t total, hipStream_t st);
 void launch_gemm_f32(const float *A, const float *Bm, float *C, int M, int N, int K, hipStream_t st);
+// C[M][N] = A[M][K] Bt[N][K]^T in FP32 on BF16 matrix cores, Bt given as its three BF16
+// parts (each [N][K], 16-bit words); needs K % 8 == 0 (gemm_bf3_ok)
+bool gemm_bf3_ok(int K);
+void launch_gemm_bf3(const float *A, const void *B0, const void *B1, const void *B2, float *C, int M, int N, int K,
+                     hipStream_t st);
 void launch_dft_c2r(DftArgs a, hipStream_t st, bool f32 = false);
 // f32: FP32 arithmetic (in64: FP64 input rows); otherwise FP64 arithmetic (in32: FP32 input rows)
 void launch_dft_r2c(DftArgs a, hipStream_t st, bool f32 = false, bool in64 = true, bool in32 = false);

@@ -977,6 +977,159 @@ static void launch_dft_mm_dir(DftArgs a, hipStream_t st)
     }
 }
 
+// ------------------------------------------------------- k_gemm_bf3 -------
+// C[M][N] = sum_k A[M][k] Bt[N][k] (FP32 in, FP32 out) on BF16 matrix cores.  Every
+// operand is split into three BF16 parts x = x0 + x1 + x2, each the round-to-nearest
+// BF16 value of what the previous parts leave (exact FP32 differences), so that
+// |x - x0 - x1 - x2| <= 2^-27 |x|; the products x0 y0 + x0 y1 + x1 y0 + x0 y2 + x2 y0 +
+// x1 y1 are exact in FP32 and accumulate in FP32 on 16x16x32 BF16 MFMA (the omitted
+// terms x1 y2, x2 y1, x2 y2 are below 2^-26 of a product).  Bt comes pre-split (three
+// [N][K] BF16 matrices); A is split as it is staged.  Six 16x16x32 BF16 products take
+// 96 matrix-core cycles where the FP32 product of the same 16x16x32 tile takes 256.
+//
+// Workgroup tile 128 x 128, four waves of 64 x 64 (4 x 4 tiles of 16 x 16); K in slices
+// of 32 through one LDS buffer per part ([row][k] with rows of 40 BF16, k contiguous, so
+// that a lane's 8 consecutive k of one row are a 16-byte read and the 8 lanes served
+// together hit distinct banks); the next slice is fetched into registers while the
+// current one feeds the matrix cores; two workgroups per CU (60 KB of LDS each).  A
+// fragment lane holds row lane % 16 and 8 consecutive k from 8 (lane / 16); the B
+// fragment pairs the same k with column lane % 16, so the product sums over every k of
+// the slice whatever order the instruction takes them in; result register r of a lane
+// is row 4 (lane / 16) + r, column lane % 16.  XCD-aware tile order as in k_gemm.
+// Requires K % 8 == 0 (whole 16-byte vectors along k); rows and columns are bounded.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+constexpr int G3_BM = 128, G3_BN = 128, G3_BK = 32, G3_RS = 40;
+
+// three BF16 parts of four FP32 values
+__device__ __forceinline__ void split3(const float4 &x, bf16x4 &p0, bf16x4 &p1, bf16x4 &p2)
+{
+    const float v[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const __bf16 a = (__bf16)v[e];
+        const float r1 = v[e] - (float)a;
+        const __bf16 b = (__bf16)r1;
+        const float r2 = r1 - (float)b;
+        p0[e] = a;
+        p1[e] = b;
+        p2[e] = (__bf16)r2;
+    }
+}
+
+__global__ __launch_bounds__(256, 2) void k_gemm_bf3(const float *__restrict__ A, const __bf16 *__restrict__ B0,
+                                                     const __bf16 *__restrict__ B1, const __bf16 *__restrict__ B2,
+                                                     float *__restrict__ C, int M, int N, int K, int mt, int nt)
+{
+    __shared__ __align__(16) __bf16 As[3][G3_BM * G3_RS];
+    __shared__ __align__(16) __bf16 Bs[3][G3_BN * G3_RS];
+    const int bid = blockIdx.x, kx = bid >> 3;
+    const int mtile = (bid & 7) + 8 * (kx / nt), ntile = kx % nt;
+    if (mtile >= mt) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int row0 = mtile * G3_BM, col0 = ntile * G3_BN;
+    const __bf16 *Bp[3] = {B0, B1, B2};
+    // staging: A 128 rows x 8 float4 (thread: rows tid / 8 + 32 r, float4 tid % 8);
+    // B per part 128 rows x 4 vectors of 8 BF16 (thread: rows tid / 4 + 64 r, vector tid % 4)
+    const int aq = tid & 7, ar = tid >> 3;
+    const int bq = tid & 3, br = tid >> 2;
+    float4 ra[4];
+    bf16x8 rb[3][2];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int gr = row0 + ar + 32 * r, gk = k0 + aq * 4;
+            ra[r] = (gr < M && gk < K) ? *reinterpret_cast<const float4 *>(A + (size_t)gr * K + gk)
+                                        : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int gn = col0 + br + 64 * r, gk = k0 + bq * 8;
+                if (gn < N && gk < K) rb[p][r] = *reinterpret_cast<const bf16x8 *>(Bp[p] + (size_t)gn * K + gk);
+                else
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) rb[p][r][e] = (__bf16)0.f;
+            }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            bf16x4 p0, p1, p2;
+            split3(ra[r], p0, p1, p2);
+            const int o = (ar + 32 * r) * G3_RS + aq * 4;
+            *reinterpret_cast<bf16x4 *>(&As[0][o]) = p0;
+            *reinterpret_cast<bf16x4 *>(&As[1][o]) = p1;
+            *reinterpret_cast<bf16x4 *>(&As[2][o]) = p2;
+        }
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+                *reinterpret_cast<bf16x8 *>(&Bs[p][(br + 64 * r) * G3_RS + bq * 8]) = rb[p][r];
+    };
+    f4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4{0, 0, 0, 0};
+    const int nk = (K + G3_BK - 1) / G3_BK;
+    const int fo = (lane & 15) * G3_RS + (lane >> 4) * 8;   // this lane's fragment offset in a 16-row tile
+    gload(0);
+    for (int t = 0; t < nk; ++t) {
+        __syncthreads();               // the previous slice's fragment reads are done
+        sstore();
+        __syncthreads();
+        if (t + 1 < nk) gload((t + 1) * G3_BK);
+        bf16x8 bf[3][4];
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                bf[p][j] = *reinterpret_cast<const bf16x8 *>(&Bs[p][(wc * 64 + j * 16) * G3_RS + fo]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bf16x8 af[3];
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+                af[p] = *reinterpret_cast<const bf16x8 *>(&As[p][(wr * 64 + i * 16) * G3_RS + fo]);
+            // small terms first; consecutive products go to the four independent accumulators
+            constexpr int PA[6] = {1, 0, 2, 0, 1, 0}, PB[6] = {1, 2, 0, 1, 0, 0};
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[PA[q]], bf[PB[q]][j], acc[i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gr = row0 + wr * 64 + i * 16 + 4 * (lane >> 4) + r;
+                const int gc = col0 + wc * 64 + j * 16 + (lane & 15);
+                if (gr < M && gc < N) C[(size_t)gr * N + gc] = acc[i][j][r];
+            }
+}
+
+bool gemm_bf3_ok(int K) { return K % 8 == 0; }
+
+void launch_gemm_bf3(const float *A, const void *B0, const void *B1, const void *B2, float *C, int M, int N, int K,
+                     hipStream_t st)
+{
+    if (M <= 0 || N <= 0) return;
+    const int mt = (M + G3_BM - 1) / G3_BM, nt = (N + G3_BN - 1) / G3_BN;
+    const unsigned blocks = 8u * (unsigned)nt * (unsigned)((mt + 7) / 8);
+    hipLaunchKernelGGL(k_gemm_bf3, dim3(blocks), dim3(256), 0, st, A, (const __bf16 *)B0, (const __bf16 *)B1,
+                       (const __bf16 *)B2, C, M, N, K, mt, nt);
+}
+
 void launch_dft_mm_c2r(DftArgs a, hipStream_t st) { launch_dft_mm_dir<1>(a, st); }
 
 void launch_dft_mm_r2c(DftArgs a, hipStream_t st) { launch_dft_mm_dir<-1>(a, st); }
