@@ -176,6 +176,7 @@ struct s2w_plan_s {
     double *A = nullptr, *Bt = nullptr, *S_ = nullptr, *smant = nullptr;
     int *sexp = nullptr;
     std::vector<double *> wpsi;              // per scale [nn][L_k]
+    std::vector<int> lmin;                   // per scale: first degree with a nonzero filter weight
     double *wphi = nullptr, *wsht = nullptr;
     double *flm = nullptr, *fhat = nullptr;
     double *bufA = nullptr, *bufB = nullptr, *bufC = nullptr;
@@ -927,11 +928,17 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
         for (int l = 0; l < p->Lphi; ++l) wp[l] = p->F.phi[l];
         if (!upload(p, p->wsht, ws) || !upload(p, p->wphi, wp)) return oom("weights");
         p->wpsi.assign(K, nullptr);
+        p->lmin.assign(K, 0);
         for (int k = 0; k < K; ++k) {
             const int Lk = S.s[k].L, nn = (int)S.s[k].n.size();
             std::vector<double> w((size_t)nn * Lk);
+            int lm = Lk;
             for (int i = 0; i < nn; ++i)
-                for (int l = 0; l < Lk; ++l) w[(size_t)i * Lk + l] = p->F.psi_mag[k][(size_t)l * nn + i];
+                for (int l = 0; l < Lk; ++l) {
+                    w[(size_t)i * Lk + l] = p->F.psi_mag[k][(size_t)l * nn + i];
+                    if (w[(size_t)i * Lk + l] != 0.0) lm = std::min(lm, l);
+                }
+            p->lmin[k] = lm;
             if (!upload(p, p->wpsi[k], w)) return oom("weights");
         }
     }
@@ -1084,6 +1091,7 @@ static void analysis_from_flm(s2w_plan p, const double *flm, void *wav_, double 
             mo.B = B;
             for (int s = 0; s < NS; ++s) {
                 la.w[s] = p->wpsi[grp.scales[s]];
+                la.lmin[s] = p->lmin[grp.scales[s]];
                 mo.out[s] = A32 + s * cstride;
             }
             {
@@ -1518,6 +1526,7 @@ static void synthesis_to_fhat_T(s2w_plan p, const double *fhat, void *gwav_, dou
             mo.B = B;
             for (int s = 0; s < NS; ++s) {
                 la.w[s] = p->wpsi[grp.scales[s]];
+                la.lmin[s] = p->lmin[grp.scales[s]];
                 mo.out[s] = A32 + s * cstride;
             }
             { Prof pr_(p, "lsum_mm", rec_work_psi(p, grp.scales, la.L, la.mcount, si.n, B), st); s2w::launch_lsum_mm(la, mo, NS, st); }

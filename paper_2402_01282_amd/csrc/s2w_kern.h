@@ -32,6 +32,8 @@ struct LsumArgs {
     double *out[MAX_NS];         // [B][nn][mcount][L] complex
     int tileT;                   // theta samples per lane of k_lsum (1, 2, 4, 8; 0: default)
     int tileW;                   // waves per block of k_lsum_mm (1, 2, 4; 0: default)
+    int lmin[MAX_NS];            // mixed kernels: first degree of each scale's filter support (the
+                                 // weights are zero below it; 0 when unknown)
 };
 
 // sum over theta (reduction across lanes)

@@ -19,6 +19,8 @@
 namespace s2w {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f4 mfma16(float a, float b, f4 c)
 {
@@ -602,10 +604,319 @@ __global__ __launch_bounds__(1024) void k_tsum_mm16(const TsumArgs a, const MixI
     tsum_zero_head(a, in, m, ni, g, l0 < L ? l0 : L, ncols);
 }
 
+// ----------------------------------------------------------- k_lsum_bf3 ----
+// The mixed l-contraction on BF16 matrix cores.  Same work split and output as
+// k_lsum_mm (unit = (m, n, 64 columns), W waves per block each owning a 64-theta tile,
+// the block sharing one staged coefficient tile per chunk), with d and the coefficients
+// split into three BF16 parts (x0 + x1 + x2 = x to 2^-27 |x|, from the FP32 value) and
+// contracted as x0 y0 + x0 y1 + x1 y0 + x0 y2 + x2 y0 + x1 y1 on 32x32x16 BF16 MFMA
+// with FP32 accumulation, 16 degrees per chunk: 6 x 32 matrix-core cycles per 32 x 32
+// tile and chunk where the FP32 16x16x4 form takes 4 x 4 x 32.  A wave's 64 x 64 output
+// is 2 x 2 tiles of 32 x 32.  d parts are written by each lane to its own row of the
+// wave's LDS slice ([theta][l], 16 degrees + 8 of padding, so that a lane's 8 degrees
+// of one row are a 16-byte read and the 8 lanes served together hit distinct banks);
+// the wave reads its A operands into registers before the recursion of the next chunk
+// overwrites the slice.  The coefficient tile [column][l] is split as it is staged and
+// double-buffered across the block (one barrier per chunk).  Chunks that lie below the
+// filter support of every scale in the column group (zero coefficients) issue no
+// products; the recursion runs through them.  Operand layout of the 32x32x16 BF16
+// instruction: A lane l holds row l % 32 and 8 consecutive k of block l / 32, B the same
+// k for column l % 32; result register r of lane l is column l % 32, row
+// 8 (r / 4) + 4 (l / 32) + r % 4 (checked on the device).
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+constexpr int LB_RS = 24;              // bf16 per LDS row (16 degrees + padding)
+constexpr int LB_SLICE = 3 * 64 * LB_RS;   // bf16 per wave slice (three parts of 64 rows)
+
+__device__ __forceinline__ void bsplit(float x, __bf16 &p0, __bf16 &p1, __bf16 &p2)
+{
+    p0 = (__bf16)x;
+    const float r1 = x - (float)p0;
+    p1 = (__bf16)r1;
+    p2 = (__bf16)(r1 - (float)p1);
+}
+
+__device__ __forceinline__ f16v mfma32(const bf16x8 &a, const bf16x8 &b, const f16v &c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+template <int NS, int W>
+__global__ __launch_bounds__(64 * W, 2) void k_lsum_bf3(const LsumArgs a, const MixOut o)
+{
+    constexpr int R = 4 / W;           // staging slots per thread
+    const int L = a.L;
+    const int ntt = (L + 63) >> 6;
+    const int ntb = (ntt + W - 1) / W;
+    const int B = o.B, ncols = 2 * B * NS;
+    const int ngrp = (ncols + 63) >> 6;
+    const int nunit = a.mcount * a.nn * ngrp;
+    // XCD-aware order: the ntb theta blocks of one unit get consecutive slots on one XCD
+    const int bid = blockIdx.x, xcd = bid & 7, kx = bid >> 3;
+    const int tb = kx % ntb, unit = (kx / ntb) * 8 + xcd;
+    if (unit >= nunit) return;
+    const int m = unit % a.mcount, ni = (unit / a.mcount) % a.nn, g = unit / (a.mcount * a.nn);
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int n = a.nval[ni], ng = a.nglob[ni];
+    const int an = n < 0 ? -n : n;
+    const int l0 = m > an ? m : an;
+    const int th = (tb * W + w) * 64 + lane;
+    const bool valid = th < L;
+    // first degree with a nonzero coefficient in this column group
+    int glmin = 1 << 30;
+    {
+        const int s0 = (g * 64) / (2 * B), s1 = min(NS - 1, (min(g * 64 + 63, ncols - 1)) / (2 * B));
+        for (int s = s0; s <= s1; ++s) glmin = min(glmin, a.lmin[s]);
+    }
+
+    __shared__ __align__(16) __bf16 Dp[W * LB_SLICE];       // per wave: [part][theta][l]
+    __shared__ __align__(16) __bf16 Up[2][3 * 64 * LB_RS];  // per buffer: [part][column][l]
+    extern __shared__ double2 lsab[];                        // (A_l, B_l), then S_l
+    double *lss = reinterpret_cast<double *>(lsab + L + LS_CPAD);
+
+    const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
+    for (int l = l0 + tid; l < L + LS_CPAD; l += 64 * W) {
+        double2 v = {0.0, 0.0};
+        double sv = 0.0;
+        if (l < L) {
+            v.x = a.A[tabm + l];
+            v.y = a.B[tabm + l];
+            sv = a.S[tabm + l];
+        }
+        lsab[l] = v;
+        lss[l] = sv;
+    }
+    double c = 0.0, cl = 0.0, e = 0.0, ep = 0.0;
+    int k = 0;
+    if (valid && l0 < L) {
+        c = a.cth[th];
+        cl = a.ctl[th];
+        const int p1 = (m + n) < 0 ? -(m + n) : (m + n);
+        const int p2 = (m - n) < 0 ? -(m - n) : (m - n);
+        start_value(a.smant[(size_t)ng * a.Lrec + m], a.sexp[(size_t)ng * a.Lrec + m], p1, p2, a.ch[th],
+                    a.sh[th], a.ceps[th], a.seps[th], e, k);
+    }
+
+    // staging: slot q = tid + 64 W r of the 32 column pairs x 8 degree pairs of a chunk is
+    // column pair p = q / 8 (re, im of one map and scale), degrees lb + iq, lb + iq + 1
+    int iq[R], pc[R];
+    bool cok[R];
+    const double *wv[R];
+    const double2 *fl[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int q = tid + 64 * W * r;
+        pc[r] = q >> 3;
+        iq[r] = (q & 7) * 2;
+        const int cg = g * 64 + 2 * pc[r];
+        cok[r] = cg < ncols;
+        int cs = 0, cb = 0;
+        if (cok[r]) {
+            cs = cg / (2 * B);
+            cb = (cg - cs * 2 * B) >> 1;
+        }
+        wv[r] = a.w[cs < NS ? cs : 0] + (size_t)ni * a.wstride;
+        fl[r] = reinterpret_cast<const double2 *>(a.flm) + ((size_t)cb * a.flm_m + m) * a.flm_l;
+    }
+    double2 f0[R], f1[R];
+    double w0[R], w1[R];
+    auto fetch = [&](int lb) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int la = lb + iq[r];
+            f0[r] = make_double2(0.0, 0.0);
+            f1[r] = make_double2(0.0, 0.0);
+            w0[r] = 0.0;
+            w1[r] = 0.0;
+            if (cok[r] && la < L) { f0[r] = fl[r][la]; w0[r] = wv[r][la]; }
+            if (cok[r] && la + 1 < L) { f1[r] = fl[r][la + 1]; w1[r] = wv[r][la + 1]; }
+        }
+    };
+    // the (re, im) columns of a slot at two degrees, split into parts: U[part][col][l]
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            __bf16 re0[3], re1[3], im0[3], im1[3];
+            bsplit((float)(w0[r] * f0[r].x), re0[0], re0[1], re0[2]);
+            bsplit((float)(w1[r] * f1[r].x), re1[0], re1[1], re1[2]);
+            bsplit((float)(w0[r] * f0[r].y), im0[0], im0[1], im0[2]);
+            bsplit((float)(w1[r] * f1[r].y), im1[0], im1[1], im1[2]);
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                __bf16 *u = &Up[buf][(p * 64 + 2 * pc[r]) * LB_RS + iq[r]];
+                typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+                bf16x2 vr, vi;
+                vr[0] = re0[p];
+                vr[1] = re1[p];
+                vi[0] = im0[p];
+                vi[1] = im1[p];
+                *reinterpret_cast<bf16x2 *>(u) = vr;
+                *reinterpret_cast<bf16x2 *>(u + LB_RS) = vi;
+            }
+        }
+    };
+    // recursion over the 16 degrees of the chunk at lc; d parts into this lane's rows
+    __bf16 *Dme = Dp + w * LB_SLICE + lane * LB_RS;
+    bf16x8 dq[3];
+    auto rstep = [&](int lc, int i) {
+        const double2 ab = lsab[lc + i];
+        const double S = lss[lc + i];
+        const float x = (valid && k == 0) ? (float)(S * e) : 0.f;
+        __bf16 q0, q1, q2;
+        bsplit(x, q0, q1, q2);
+        dq[0][i & 7] = q0;
+        dq[1][i & 7] = q1;
+        dq[2][i & 7] = q2;
+        if ((i & 7) == 7) {
+#pragma unroll
+            for (int p = 0; p < 3; ++p) *reinterpret_cast<bf16x8 *>(Dme + p * 64 * LB_RS + (i & 8)) = dq[p];
+        }
+        const double en = fma(fma(ab.x, cl, fma(ab.x, c, -ab.y)), e, -ep);
+        ep = e;
+        e = en;
+        if ((i & 7) == 7 && k < 0 && fabs(e) > 0x1p256) {
+            e *= 0x1p-512;
+            ep *= 0x1p-512;
+            k += 1;
+        }
+    };
+
+    f16v acc[2][2], acc2[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                acc[i][j][r] = 0.f;
+                acc2[i][j][r] = 0.f;
+            }
+        }
+
+    if (l0 < L) fetch(l0);
+    __syncthreads();                   // coefficient row staged
+    if (l0 < L) {
+        stage(0);
+        if (l0 + 16 < L) fetch(l0 + 16);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) rstep(l0, i);
+    }
+    __syncthreads();
+    // fragment offsets: A row (theta) lane % 32 of tile i, B row (column) lane % 32 of tile j;
+    // 8 degrees from 8 (lane / 32)
+    const int fo = (lane & 31) * LB_RS + (lane >> 5) * 8;
+    const __bf16 *Dw = Dp + w * LB_SLICE;
+    int chunk = 0;
+    for (int lb = l0; lb < L; lb += 16, ++chunk) {
+        const int cb = chunk & 1, nb = cb ^ 1;
+        const bool nxt = lb + 16 < L;
+        const bool live = lb + 16 > glmin;   // some coefficient of the chunk is nonzero
+        // A operands (this wave's d rows) are all read before the next chunk's recursion
+        // overwrites the rows; B operands are read per column tile (the other coefficient
+        // buffer is the one restaged during this chunk)
+        bf16x8 af[2][3];
+        if (live) {
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+                    af[t][p] = *reinterpret_cast<const bf16x8 *>(Dw + p * 64 * LB_RS + t * 32 * LB_RS + fo);
+        }
+        wave_lds_sync();               // this wave's d rows are read: the next chunk may overwrite them
+        if (nxt) {
+            stage(nb);
+            if (lb + 32 < L) fetch(lb + 32);
+        }
+        if (live) {
+            // per column tile: six products per row tile (small terms first), four steps of the
+            // next chunk's recursion after each row tile's products
+            constexpr int PA[6] = {1, 0, 2, 0, 1, 0}, PB[6] = {1, 2, 0, 1, 0, 0};
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                bf16x8 bfr[3];
+#pragma unroll
+                for (int p = 0; p < 3; ++p)
+                    bfr[p] = *reinterpret_cast<const bf16x8 *>(&Up[cb][(p * 64 + j * 32) * LB_RS + fo]);
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) acc[i][j] = mfma32(af[i][PA[q]], bfr[PB[q]], acc[i][j]);
+                    if (nxt) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) rstep(lb + 16, 4 * (2 * j + i) + r);
+                    }
+                }
+            }
+        } else if (nxt) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) rstep(lb + 16, i);
+        }
+        __syncthreads();
+        if ((chunk & 3) == 3) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    acc2[i][j] += acc[i][j];
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+                }
+        }
+    }
+    // output: one 32-column tile at a time through this wave's slice ([col][theta], rows of
+    // 65 floats), then (re, im) pairs written with theta contiguous
+    float *St = reinterpret_cast<float *>(Dp + w * LB_SLICE);   // 32 x 65 floats fit the slice
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                St[(lane & 31) * 65 + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)] = acc2[i][j][r] + acc[i][j][r];
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int cgp = g * 64 + 32 * j + 2 * q;
+            if (cgp < ncols && valid) {
+                const int s = cgp / (2 * B);
+                const int b = (cgp - s * 2 * B) >> 1;
+                float2 *dst = reinterpret_cast<float2 *>(o.out[s]);
+                dst[(((size_t)b * a.nn + ni) * a.mcount + m) * L + th] =
+                    make_float2(St[(2 * q) * 65 + lane], St[(2 * q + 1) * 65 + lane]);
+            }
+        }
+        wave_lds_sync();
+    }
+}
+
 // ------------------------------------------------------------- launchers ---
+
+void launch_lsum_bf3(const LsumArgs &a, const MixOut &o, int NS, hipStream_t st)
+{
+    const int ntt = (a.L + 63) / 64;
+    const int W = (a.tileW == 2 || ntt < 4) ? 2 : 4;
+    const int ntb = (ntt + W - 1) / W;
+    const int ngrp = (2 * o.B * NS + 63) / 64;
+    const long nunit = (long)a.mcount * a.nn * ngrp;
+    dim3 grid((unsigned)(8L * ntb * ((nunit + 7) / 8)));
+    const dim3 blk(64 * W);
+    const size_t smem = (sizeof(double2) + sizeof(double)) * (size_t)(a.L + LS_CPAD);
+    if (NS == 1) {
+        if (W == 2) hipLaunchKernelGGL((k_lsum_bf3<1, 2>), grid, blk, smem, st, a, o);
+        else hipLaunchKernelGGL((k_lsum_bf3<1, 4>), grid, blk, smem, st, a, o);
+    } else {
+        if (W == 2) hipLaunchKernelGGL((k_lsum_bf3<2, 2>), grid, blk, smem, st, a, o);
+        else hipLaunchKernelGGL((k_lsum_bf3<2, 4>), grid, blk, smem, st, a, o);
+    }
+}
 
 void launch_lsum_mm(const LsumArgs &a, const MixOut &o, int NS, hipStream_t st)
 {
+    if (a.L >= 64) {
+        launch_lsum_bf3(a, o, NS, st);
+        return;
+    }
     const int ntt = (a.L + 63) / 64;
     int W = a.tileW == 1 || a.tileW == 2 || a.tileW == 4 ? a.tileW : 4;
     if (W > ntt) W = ntt < 2 ? 1 : (ntt < 4 ? 2 : 4);
@@ -997,9 +1308,6 @@ static void launch_dft_mm_dir(DftArgs a, hipStream_t st)
 // the slice whatever order the instruction takes them in; result register r of a lane
 // is row 4 (lane / 16) + r, column lane % 16.  XCD-aware tile order as in k_gemm.
 // Requires K % 8 == 0 (whole 16-byte vectors along k); rows and columns are bounded.
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int G3_BM = 128, G3_BN = 128, G3_BK = 32, G3_RS = 40;
 
