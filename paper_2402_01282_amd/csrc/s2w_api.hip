@@ -1240,6 +1240,7 @@ static void synthesis_to_fhat(s2w_plan p, const void *wav_, const double *scal, 
             }
             theta_quadrature32(p, g, A32 + s * cstride, C32 + s * cstride, Lk, nn, npar, st);
             ta.w[s] = p->wpsi[k];
+            ta.lmin[s] = p->lmin[k];
             mi.h[s] = C32 + s * cstride;
             mi.out[s] = p->P[k];
         }
@@ -1447,6 +1448,7 @@ static void analysis_from_flm_T(s2w_plan p, const void *gwav_, const double *gsc
                 ga.dst = A32 + s * cstride;
                 { Prof pr_(p, "gamma_r2c_f32", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_r2c(ga, st, true); }
                 ta.w[s] = p->wpsi[k];
+                ta.lmin[s] = p->lmin[k];
                 mi.h[s] = A32 + s * cstride;
                 mi.out[s] = p->P[k];
             } else {

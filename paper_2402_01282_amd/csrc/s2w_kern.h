@@ -48,6 +48,8 @@ struct TsumArgs {
     int npol;
     int npar;                    // parity of n in this launch: sigma index = (m + npar) & 1
     int M0, M1;                  // number of m with sigma index 0 / 1
+    int lmin[MAX_NS];            // mixed kernels: first degree of each scale's filter support (the
+                                 // weights are zero below it; 0 when unknown)
     const double *h[MAX_NS];     // rows [sig][b][m'][ni][c][L]
     const double *w[MAX_NS];
     int wstride;

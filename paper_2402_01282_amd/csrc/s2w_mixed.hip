@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "s2w_dev.h"
 #include "s2w_kern.h"
@@ -371,8 +372,14 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
 
     __syncthreads();                   // coefficient row staged
 
+    int glmin = 1 << 30;
+    {
+        const int s0 = (g * 64) / (2 * B), s1 = min(NS - 1, (min(g * 64 + 63, ncols - 1)) / (2 * B));
+        for (int s = s0; s <= s1; ++s) glmin = min(glmin, a.lmin[s]);
+    }
     int par = 0;
     for (int lb = l0; lb < L; lb += 16, par ^= 1) {
+        const bool live = lb + 16 > glmin;   // chunks below the filter support issue no products
         float *Dw = sm + (size_t)(par * NW + w) * TS_RS;
         // scale factors of this thread's first output of the chunk, loaded (without a
         // branch, degree clamped) before the chunk's recursion and matrix-core work
@@ -400,11 +407,13 @@ __global__ __launch_bounds__(1024) void k_tsum_mm(const TsumArgs a, const MixIn 
         for (int j = 0; j < 4; ++j) pacc[j] = f4{0, 0, 0, 0};
         // A[l = lane%16][theta = 4 ks + lane/16]
         const float *Da = Dw + (lane >> 4) * 17 + (lane & 15);
+        if (live) {
 #pragma unroll
-        for (int ks = 0; ks < 16; ++ks) {
-            const float av = Da[68 * ks];
+            for (int ks = 0; ks < 16; ++ks) {
+                const float av = Da[68 * ks];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) pacc[j] = mfma16(av, hb[ks][j], pacc[j]);
+                for (int j = 0; j < 4; ++j) pacc[j] = mfma16(av, hb[ks][j], pacc[j]);
+            }
         }
         wave_lds_sync();
         // partial 16 (l) x 64 (col) of this wave, stored [col][l] (stride 17): register r of
@@ -538,7 +547,15 @@ __global__ __launch_bounds__(1024) void k_tsum_mm16(const TsumArgs a, const MixI
     }
 
     const float *Da = Dw + (lane >> 4) * 17 + (lane & 15);   // A[l = lane%16][theta = 4 ks + lane/16]
-    for (int lb = l0; lb < L; lb += 16) {
+    // first degree with a nonzero weight in this column group: chunks below it have zero
+    // outputs and issue no products (their partials are zero)
+    int glmin = 1 << 30;
+    {
+        const int s0 = (g * 64) / (2 * B), s1 = min(NS - 1, (min(g * 64 + 63, ncols - 1)) / (2 * B));
+        for (int s = s0; s <= s1; ++s) glmin = min(glmin, a.lmin[s]);
+    }
+    // one chunk; LIVE: with the matrix-core products
+    auto chunk_body = [&](int lb, auto LIVE) {
         // scale factors of the previous chunk's output, stored after this chunk's first 8 k steps
         // (degree clamped to [0, L): on the first chunk there is no previous output)
         const int lq = lb - 16 + rli;
@@ -553,9 +570,11 @@ __global__ __launch_bounds__(1024) void k_tsum_mm16(const TsumArgs a, const MixI
         double v = 0.0;
 #pragma unroll
         for (int ks = 0; ks < 8; ++ks) {
-            const float av = Da[68 * ks];
+            if constexpr (decltype(LIVE)::value) {
+                const float av = Da[68 * ks];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) pacc[j] = mfma16(av, hb[ks][j], pacc[j]);
+                for (int j = 0; j < 4; ++j) pacc[j] = mfma16(av, hb[ks][j], pacc[j]);
+            }
             v += (double)Pr[(2 * ks) * TS_RS];
             v += (double)Pr[(2 * ks + 1) * TS_RS];
             // keeps each k step's partial reads beside its products (hoisting all of them
@@ -566,22 +585,26 @@ __global__ __launch_bounds__(1024) void k_tsum_mm16(const TsumArgs a, const MixI
             const int l = lb - 16 + rli;
             if (l < L && rok) orow[(size_t)l * 2] = v * (s0 * w0);
         }
-        // k steps 8..11
-#pragma unroll
-        for (int ks = 8; ks < 12; ++ks) {
-            const float av = Da[68 * ks];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) pacc[j] = mfma16(av, hb[ks][j], pacc[j]);
-        }
         float av[4];
+        if constexpr (decltype(LIVE)::value) {
+            // k steps 8..11
 #pragma unroll
-        for (int q = 0; q < 4; ++q) av[q] = Da[68 * (q + 12)];
+            for (int ks = 8; ks < 12; ++ks) {
+                const float a8 = Da[68 * ks];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) pacc[j] = mfma16(a8, hb[ks][j], pacc[j]);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) av[q] = Da[68 * (q + 12)];
+        }
         wave_lds_sync();               // all A operands read: the rows may be overwritten
         // k steps 12..15, with the recursion of the next chunk
 #pragma unroll
         for (int ks = 12; ks < 16; ++ks) {
+            if constexpr (decltype(LIVE)::value) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) pacc[j] = mfma16(av[ks - 12], hb[ks][j], pacc[j]);
+                for (int j = 0; j < 4; ++j) pacc[j] = mfma16(av[ks - 12], hb[ks][j], pacc[j]);
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) rstep(lb + 16, 4 * (ks - 12) + i);
         }
@@ -591,7 +614,11 @@ __global__ __launch_bounds__(1024) void k_tsum_mm16(const TsumArgs a, const MixI
 #pragma unroll
             for (int r = 0; r < 4; ++r) Pw[(16 * j + (lane & 15)) * 17 + 4 * (lane >> 4) + r] = pacc[j][r];
         __syncthreads();               // this chunk's partials are visible
-    }
+    };
+    // the chunks below the support come first: two loops, each with its own body
+    int lb = l0;
+    for (; lb < L && lb + 16 <= glmin; lb += 16) chunk_body(lb, std::integral_constant<bool, false>());
+    for (; lb < L; lb += 16) chunk_body(lb, std::integral_constant<bool, true>());
     if (l0 < L) {
         const int lb = l0 + ((L - 1 - l0) & ~15);  // the last chunk
         const int l = lb + rli;
