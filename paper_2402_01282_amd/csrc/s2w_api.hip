@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -199,6 +200,9 @@ struct s2w_plan_s {
     int prof_cap = 0;
     // tuned tile shapes per grid band limit (S2W_PLAN_TUNE)
     std::map<int, int> tile_lsum, tile_lsum_mm;
+    // mixed plans, per grid band limit: contraction route, 1 = FP64 vector kernels with an
+    // FP32 conversion at the boundary (fastest for very small batches), 0 = matrix cores
+    std::map<int, int> route_lsum, route_tsum;
     // graph replay (S2W_PLAN_GRAPH)
     bool graph = false, capturing = false;
     hipStream_t cap_stream = nullptr;
@@ -709,23 +713,62 @@ s2w_status run_graph(s2w_plan p, int kind, const void *a, const void *b, const v
     return S2W_OK;
 }
 
-// S2W_PLAN_TUNE: for every scale group with band limit >= 128, time each tile shape
-// of the l-contraction kernel (theta samples per lane of k_lsum for FP64 plans, MFMA
-// column tiles per wave of k_lsum_mm for mixed plans) on the plan's own shapes and
-// workspace, and keep the fastest.  Runs at plan creation (synchronises).
+// Mixed plans: does the contraction of the grid of band limit Lk take the FP64 vector route?
+// The autotuner's choice when it timed this grid, else the batch heuristic: the matrix-core
+// kernels work on 64 columns (2 x maps x scales), so at one or two maps they do mostly
+// padding and the vector kernels (one theta sample per lane) are faster.
+bool lsum_vector(s2w_plan p, int Lk)
+{
+    auto it = p->route_lsum.find(Lk);
+    return it != p->route_lsum.end() ? it->second == 1 : p->B <= 2;
+}
+
+bool tsum_vector(s2w_plan p, int Lk)
+{
+    auto it = p->route_tsum.find(Lk);
+    return it != p->route_tsum.end() ? it->second == 1 : p->B <= 1;
+}
+
+// S2W_PLAN_TUNE: time the candidate kernels of every scale group on the plan's own shapes and
+// workspace, and keep the fastest.  FP64 plans (band limit >= 128): theta samples per lane of
+// k_lsum (1, 2, 4, 8).  Mixed plans (band limit >= 64): for the l-contraction the matrix-core
+// kernel with 2 or 4 waves per block, or the FP64 vector kernel plus its conversion to FP32;
+// for the theta contraction the matrix-core kernel, or the conversion of its input to FP64
+// plus the FP64 vector kernel.  Every candidate of a contraction gives the same sums to
+// rounding.  Runs at plan creation (synchronises).
 void autotune(s2w_plan p)
 {
     const bool mixed = p->prec == S2W_MIXED;
     const int B = p->B;
     (void)hipMemset(p->flm, 0, sizeof(double) * (size_t)B * p->L * p->L * 2);
+    (void)hipMemset(p->bufA, 0, sizeof(double) * p->szA);
+    (void)hipMemset(p->bufC, 0, sizeof(double) * p->szC);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return;
+    // best of the candidates (each launched once untimed, then twice timed); 0 if none ran
+    auto pick = [&](const std::vector<int> &cands, const std::function<void(int)> &launch) {
+        int best = 0;
+        float best_ms = 0.0f;
+        for (int c : cands) {
+            launch(c);
+            (void)hipEventRecord(e0, nullptr);
+            launch(c);
+            launch(c);
+            (void)hipEventRecord(e1, nullptr);
+            if (hipEventSynchronize(e1) != hipSuccess) continue;
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (best == 0 || ms < best_ms) { best = c; best_ms = ms; }
+        }
+        return best;
+    };
     for (auto &grp : p->groups) {
         const int Lk = grp.L, NS = (int)grp.scales.size();
-        if (Lk < 128 || (mixed ? p->tile_lsum_mm.count(Lk) : p->tile_lsum.count(Lk))) continue;
+        if (Lk < (mixed ? 64 : 128) || (mixed ? p->route_lsum.count(Lk) : p->tile_lsum.count(Lk))) continue;
         const DevGrid &g = p->grids[Lk];
         const auto &si = p->S.s[grp.scales[0]];
         const int nn = (int)si.n.size();
+        const int npar = (p->N - 1) & 1;
         LsumArgs la = lsum_args(p, g, Lk, si.n);
         la.flm = p->flm;
         la.flm_m = p->L;
@@ -736,29 +779,52 @@ void autotune(s2w_plan p)
         mo.B = B;
         for (int s = 0; s < NS; ++s) {
             la.w[s] = p->wpsi[grp.scales[s]];
-            la.out[s] = p->bufA + s * cstride;
+            la.lmin[s] = p->lmin[grp.scales[s]];
+            la.out[s] = p->bufC + s * cstride;
             mo.out[s] = (float *)p->bufA + s * cstride;
         }
-        // candidates that all give the same sums in the same order (only the work split differs)
-        const std::vector<int> cands = mixed ? std::vector<int>{2, 4} : std::vector<int>{1, 2, 4, 8};
-        int best = 0;
-        float best_ms = 0.0f;
-        for (int c : cands) {
-            auto launch = [&]() {
-                if (mixed) { la.tileW = c; s2w::launch_lsum_mm(la, mo, NS, nullptr); }
-                else { la.tileT = c; s2w::launch_lsum(la, NS, B, nullptr); }
-            };
-            launch();
-            (void)hipEventRecord(e0, nullptr);
-            launch();
-            launch();
-            (void)hipEventRecord(e1, nullptr);
-            if (hipEventSynchronize(e1) != hipSuccess) continue;
-            float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (best == 0 || ms < best_ms) { best = c; best_ms = ms; }
+        if (!mixed) {
+            const int best = pick({1, 2, 4, 8}, [&](int c) { la.tileT = c; s2w::launch_lsum(la, NS, B, nullptr); });
+            if (best) p->tile_lsum[Lk] = best;
+            continue;
         }
-        if (best) (mixed ? p->tile_lsum_mm : p->tile_lsum)[Lk] = best;
+        // l-contraction: 2 or 4 waves per block on matrix cores, or (-1) the vector route
+        const int bl = pick({2, 4, -1}, [&](int c) {
+            if (c > 0) {
+                la.tileW = c;
+                s2w::launch_lsum_mm(la, mo, NS, nullptr);
+            } else {
+                s2w::launch_lsum(la, NS, B, nullptr);
+                s2w::launch_convert(p->bufC, mo.out[0], NS * cstride, true, nullptr);
+            }
+        });
+        if (bl) {
+            p->route_lsum[Lk] = bl < 0 ? 1 : 0;
+            if (bl > 0) p->tile_lsum_mm[Lk] = bl;
+        }
+        // theta contraction on zero quadrature rows: matrix cores (1) or the vector route (-1)
+        TsumArgs ta = tsum_args(p, g, Lk, si.n, npar);
+        ta.wstride = Lk;
+        s2w::MixIn mi{};
+        mi.B = B;
+        for (int s = 0; s < NS; ++s) {
+            const int k = grp.scales[s];
+            ta.w[s] = p->wpsi[k];
+            ta.lmin[s] = p->lmin[k];
+            ta.h[s] = p->bufA + s * cstride;
+            ta.out[s] = p->P[k];
+            mi.h[s] = (const float *)p->bufC + s * cstride;
+            mi.out[s] = p->P[k];
+        }
+        const int bt = pick({1, -1}, [&](int c) {
+            if (c > 0) {
+                s2w::launch_tsum_mm(ta, mi, NS, nullptr);
+            } else {
+                s2w::launch_convert(p->bufC, p->bufA, NS * cstride, false, nullptr);
+                s2w::launch_tsum(ta, NS, B, nullptr);
+            }
+        });
+        if (bt) p->route_tsum[Lk] = bt < 0 ? 1 : 0;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1092,9 +1158,13 @@ static void analysis_from_flm(s2w_plan p, const double *flm, void *wav_, double 
             for (int s = 0; s < NS; ++s) {
                 la.w[s] = p->wpsi[grp.scales[s]];
                 la.lmin[s] = p->lmin[grp.scales[s]];
+                la.out[s] = p->bufC + s * cstride;
                 mo.out[s] = A32 + s * cstride;
             }
-            {
+            if (lsum_vector(p, Lk)) {
+                { Prof pr_(p, "lsum", rec_work_psi(p, grp.scales, la.L, la.mcount, si.n, B), st); s2w::launch_lsum(la, NS, B, st); }
+                { Prof pr_(p, "convert", 0.0, st); s2w::launch_convert(p->bufC, A32, NS * cstride, true, st); }
+            } else {
                 Prof pr_(p, "lsum_mm", rec_work_psi(p, grp.scales, la.L, la.mcount, si.n, B), st);
                 s2w::launch_lsum_mm(la, mo, NS, st);
             }
@@ -1243,9 +1313,18 @@ static void synthesis_to_fhat(s2w_plan p, const void *wav_, const double *scal, 
             ta.lmin[s] = p->lmin[k];
             mi.h[s] = C32 + s * cstride;
             mi.out[s] = p->P[k];
+            ta.h[s] = p->bufA + s * cstride;
+            ta.out[s] = p->P[k];
         }
-        Prof pr_(p, "tsum_mm", rec_work_psi(p, grp.scales, ta.L, ta.mcount, si.n, B), st);
-        s2w::launch_tsum_mm(ta, mi, NS, st);
+        if (tsum_vector(p, Lk)) {
+            // the quadrature rows of every scale are no longer needed in A32: widen them there
+            { Prof pr_(p, "convert", 0.0, st); s2w::launch_convert(C32, p->bufA, NS * cstride, false, st); }
+            Prof pr_(p, "tsum", rec_work_psi(p, grp.scales, ta.L, ta.mcount, si.n, B), st);
+            s2w::launch_tsum(ta, NS, B, st);
+        } else {
+            Prof pr_(p, "tsum_mm", rec_work_psi(p, grp.scales, ta.L, ta.mcount, si.n, B), st);
+            s2w::launch_tsum_mm(ta, mi, NS, st);
+        }
     }
     for (auto &grp : p->groups) {
         if (mixed) continue;
@@ -1451,6 +1530,8 @@ static void analysis_from_flm_T(s2w_plan p, const void *gwav_, const double *gsc
                 ta.lmin[s] = p->lmin[k];
                 mi.h[s] = A32 + s * cstride;
                 mi.out[s] = p->P[k];
+                ta.h[s] = p->bufC + s * cstride;
+                ta.out[s] = p->P[k];
             } else {
                 const double *gw = (const double *)gwav_ + p->wav_off[k];
                 {
@@ -1466,7 +1547,11 @@ static void analysis_from_flm_T(s2w_plan p, const void *gwav_, const double *gsc
                 ta.out[s] = p->P[k];
             }
         }
-        if (mixed) {
+        if (mixed && tsum_vector(p, Lk)) {
+            { Prof pr_(p, "convert", 0.0, st); s2w::launch_convert(p->bufA, p->bufC, NS * cstride, false, st); }
+            Prof pr_(p, "tsum", rec_work_psi(p, grp.scales, ta.L, ta.mcount, si.n, B), st);
+            s2w::launch_tsum(ta, NS, B, st);
+        } else if (mixed) {
             Prof pr_(p, "tsum_mm", rec_work_psi(p, grp.scales, ta.L, ta.mcount, si.n, B), st);
             s2w::launch_tsum_mm(ta, mi, NS, st);
         } else {
@@ -1529,9 +1614,16 @@ static void synthesis_to_fhat_T(s2w_plan p, const double *fhat, void *gwav_, dou
             for (int s = 0; s < NS; ++s) {
                 la.w[s] = p->wpsi[grp.scales[s]];
                 la.lmin[s] = p->lmin[grp.scales[s]];
+                la.out[s] = p->bufC + s * cstride;
                 mo.out[s] = A32 + s * cstride;
             }
-            { Prof pr_(p, "lsum_mm", rec_work_psi(p, grp.scales, la.L, la.mcount, si.n, B), st); s2w::launch_lsum_mm(la, mo, NS, st); }
+            if (lsum_vector(p, Lk)) {
+                { Prof pr_(p, "lsum", rec_work_psi(p, grp.scales, la.L, la.mcount, si.n, B), st); s2w::launch_lsum(la, NS, B, st); }
+                { Prof pr_(p, "convert", 0.0, st); s2w::launch_convert(p->bufC, A32, NS * cstride, true, st); }
+            } else {
+                Prof pr_(p, "lsum_mm", rec_work_psi(p, grp.scales, la.L, la.mcount, si.n, B), st);
+                s2w::launch_lsum_mm(la, mo, NS, st);
+            }
             for (int s = 0; s < NS; ++s) {
                 const int k = grp.scales[s];
                 { Prof pr_(p, "pack_sigma_f32", 0.0, st); s2w::launch_pack_sigma_f32(A32 + s * cstride, C32, B, nn, Lk, Lk, npar, M0, M1, 0, st); }

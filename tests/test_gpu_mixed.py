@@ -28,7 +28,8 @@ def _plan(L, N, J0, B):
     return s2w.Plan(L, N, 2.0, J0, batch=B, precision=s2w.S2W_MIXED, device=0)
 
 
-@pytest.mark.parametrize("L,N,J0,B", [(8, 3, 0, 2), (32, 3, 0, 32), (64, 8, 0, 32), (33, 4, 1, 5), (128, 4, 2, 64)])
+@pytest.mark.parametrize("L,N,J0,B", [(8, 3, 0, 2), (32, 3, 0, 32), (64, 8, 0, 32), (33, 4, 1, 5), (128, 4, 2, 64),
+                                     (64, 4, 0, 1), (130, 3, 1, 1), (96, 5, 0, 2)])
 def test_mixed_analysis_and_synthesis(L, N, J0, B):
     torch = _torch()
     print(f"[mixed L={L} N={N} J0={J0} B={B}]", flush=True)
@@ -124,3 +125,29 @@ def test_mixed_ragged_L1000_N3():
     errs = [(torch.linalg.norm(f2[b] - f[b]) / torch.linalg.norm(f[b])).item() for b in range(B)]
     print(f"  round trip rel err: max {max(errs):.2e}", flush=True)
     assert max(errs) < TOL
+
+
+@pytest.mark.parametrize("L,N,B", [(128, 4, 1), (128, 4, 8), (256, 3, 2)])
+def test_mixed_routes_agree(L, N, B):
+    """The autotuned plan (matrix-core or FP64 vector contractions per degree group, chosen
+    by timing) and the untuned plan (batch heuristic) give the same coefficients and
+    round trip to the precision of the mixed form."""
+    torch = _torch()
+    import paper_2402_01282_amd as s2w
+    print(f"[mixed routes L={L} N={N} B={B}]", flush=True)
+    maps = np.stack([np.real(mw.sht_inverse(S.sphere_flm(L, S.stream_key(8, b)), L)) for b in range(B)])
+    f = torch.from_numpy(maps).cuda()
+    outs = []
+    for flags in (0, s2w.S2W_PLAN_TUNE):
+        plan = _plan_flags(L, N, 0, B, flags)
+        wav, scal = plan.analysis(f)
+        f2 = plan.synthesis(wav, scal)
+        outs.append((wav.double().cpu().numpy(), f2.cpu().numpy()))
+        assert _rel(f2.cpu().numpy(), maps) < TOL
+    assert _rel(outs[1][0], outs[0][0]) < TOL
+    assert _rel(outs[1][1], outs[0][1]) < TOL
+
+
+def _plan_flags(L, N, J0, B, flags):
+    import paper_2402_01282_amd as s2w
+    return s2w.Plan(L, N, 2.0, J0, batch=B, precision=s2w.S2W_MIXED, device=0, flags=flags)
