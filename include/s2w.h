@@ -65,9 +65,16 @@ enum {
                                on the first call with a given (input, output, output) pointer triple
                                and replay it afterwards (up to 16 triples per plan; kernel timing is
                                not recorded for graph replays) */
-    S2W_PLAN_NO_WORKSPACE = 4  /* allocate no workspace (tables only): the plan runs only through
+    S2W_PLAN_NO_WORKSPACE = 4, /* allocate no workspace (tables only): the plan runs only through
                                s2w_analysis_noalloc; other transform entry points return S2W_ESTATE.
                                Excludes S2W_PLAN_TUNE and S2W_PLAN_GRAPH. */
+    S2W_PLAN_PERSISTENT = 8 /* mixed plans: the l-contraction of the analysis runs as one
+                               persistent launch over every degree group of band limit >= 64 on
+                               matrix cores, its work items (degree group, m, n, column group,
+                               theta block) in per-XCD lists sorted by decreasing cost
+                               L_j - max(m, |n|) (Section 3.3: the top scales dominate).  With
+                               S2W_PLAN_TUNE alone the autotuner chooses between this and one
+                               launch per degree group by timing both. */
 };
 
 /* Size of the static device scratch that s2w_analysis_noalloc works in (one copy per

@@ -203,6 +203,17 @@ struct s2w_plan_s {
     // mixed plans, per grid band limit: contraction route, 1 = FP64 vector kernels with an
     // FP32 conversion at the boundary (fastest for very small batches), 0 = matrix cores
     std::map<int, int> route_lsum, route_tsum;
+    // persistent l-contraction of the mixed analysis (one launch over the degree groups in
+    // lgroups, work items in eight per-XCD lists sorted by cost); used when lsum_list is set
+    // and the batch is the one the list was built for
+    bool lsum_list = false;
+    int list_B = 0, list_blocks = 0;
+    std::vector<int> lgroups;                // indices into groups
+    std::vector<size_t> lgroup_off;          // each group's output offset in bufA (floats)
+    size_t list_end = 0;                     // end of those outputs: other groups write from here
+    uint2 *items = nullptr;
+    unsigned *counters = nullptr;
+    int list_cnt[8] = {0}, list_off[8] = {0};
     // graph replay (S2W_PLAN_GRAPH)
     bool graph = false, capturing = false;
     hipStream_t cap_stream = nullptr;
@@ -729,6 +740,111 @@ bool tsum_vector(s2w_plan p, int Lk)
     return it != p->route_tsum.end() ? it->second == 1 : p->B <= 1;
 }
 
+// Work list of the persistent l-contraction (mixed plans): every degree group with band
+// limit >= 64 on the matrix-core route, up to MAX_LGROUPS, whose outputs fit side by side
+// in bufA.  Units (m, n, column group) are sorted by decreasing cost L_j - max(m, |n|) and
+// dealt to the eight XCD lists in turn; each unit's theta blocks stay on its list.
+bool build_lsum_list(s2w_plan p)
+{
+    p->lgroups.clear();
+    p->lgroup_off.clear();
+    size_t off = 0;
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        const auto &grp = p->groups[gi];
+        if (grp.L < 64 || lsum_vector(p, grp.L)) continue;
+        const int nn = (int)p->S.s[grp.scales[0]].n.size();
+        const size_t sz = grp.scales.size() * (size_t)p->B * nn * grp.L * grp.L * 2;   // floats
+        if (p->lgroups.size() == (size_t)s2w::MAX_LGROUPS || off + sz > 2 * p->szA) break;
+        p->lgroups.push_back((int)gi);
+        p->lgroup_off.push_back(off);
+        off += sz;
+    }
+    // the groups outside the list write their outputs after the listed ones
+    size_t rest = 0;
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        if (std::find(p->lgroups.begin(), p->lgroups.end(), (int)gi) != p->lgroups.end()) continue;
+        const auto &grp = p->groups[gi];
+        const int nn = (int)p->S.s[grp.scales[0]].n.size();
+        rest = std::max(rest, grp.scales.size() * (size_t)p->B * nn * grp.L * grp.L * 2);
+    }
+    if (p->lgroups.size() < 2 || off + rest > 2 * p->szA) {
+        p->lgroups.clear();
+        p->lgroup_off.clear();
+        return false;
+    }
+    p->list_end = off;
+    struct U { int cost, gi, m, ni, g, ntb; };
+    std::vector<U> units;
+    for (size_t k = 0; k < p->lgroups.size(); ++k) {
+        const auto &grp = p->groups[p->lgroups[k]];
+        const auto &si = p->S.s[grp.scales[0]];
+        const int NS = (int)grp.scales.size(), nn = (int)si.n.size();
+        const int ngrp = (2 * p->B * NS + 63) / 64, ntb = ((grp.L + 63) / 64 + 3) / 4;
+        for (int g = 0; g < ngrp; ++g)
+            for (int ni = 0; ni < nn; ++ni)
+                for (int m = 0; m < grp.L; ++m) {
+                    const int l0 = std::max(m, std::abs(si.n[ni]));
+                    if (l0 < grp.L) units.push_back({grp.L - l0, (int)k, m, ni, g, ntb});
+                }
+    }
+    std::stable_sort(units.begin(), units.end(), [](const U &a, const U &b) { return a.cost > b.cost; });
+    std::vector<uint2> lists[8];
+    for (size_t u = 0; u < units.size(); ++u)
+        for (int tb = 0; tb < units[u].ntb; ++tb) {
+            uint2 it;
+            it.x = (unsigned)units[u].gi | ((unsigned)units[u].ni << 4) | ((unsigned)tb << 8) | ((unsigned)units[u].g << 16);
+            it.y = (unsigned)units[u].m;
+            lists[u % 8].push_back(it);
+        }
+    std::vector<uint2> all;
+    for (int x = 0; x < 8; ++x) {
+        p->list_off[x] = (int)all.size();
+        p->list_cnt[x] = (int)lists[x].size();
+        all.insert(all.end(), lists[x].begin(), lists[x].end());
+    }
+    if (!upload(p, p->items, all)) return false;
+    if (!p->counters && !dalloc(p, p->counters, 8)) return false;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || ncu <= 0) ncu = 256;
+    p->list_blocks = 2 * ncu;
+    p->list_B = p->B;
+    return true;
+}
+
+// Launch arguments of the persistent l-contraction of the analysis from flm (bufA outputs at
+// the groups' offsets)
+s2w::LsumList lsum_list_args(s2w_plan p, const double *flm)
+{
+    s2w::LsumList gl{};
+    gl.ngroups = (int)p->lgroups.size();
+    for (int x = 0; x < 8; ++x) {
+        gl.cnt[x] = p->list_cnt[x];
+        gl.off[x] = p->list_off[x];
+    }
+    float *A32 = (float *)p->bufA;
+    for (int k = 0; k < gl.ngroups; ++k) {
+        const auto &grp = p->groups[p->lgroups[k]];
+        const DevGrid &g = p->grids[grp.L];
+        const auto &si = p->S.s[grp.scales[0]];
+        const int NS = (int)grp.scales.size(), nn = (int)si.n.size();
+        const size_t cstride = (size_t)p->B * nn * grp.L * grp.L * 2;
+        LsumArgs la = lsum_args(p, g, grp.L, si.n);
+        la.flm = flm;
+        la.flm_m = p->L;
+        la.flm_l = p->L;
+        la.wstride = grp.L;
+        gl.NS[k] = NS;
+        gl.o[k].B = p->B;
+        for (int s = 0; s < NS; ++s) {
+            la.w[s] = p->wpsi[grp.scales[s]];
+            la.lmin[s] = p->lmin[grp.scales[s]];
+            gl.o[k].out[s] = A32 + p->lgroup_off[k] + s * cstride;
+        }
+        gl.a[k] = la;
+    }
+    return gl;
+}
+
 // S2W_PLAN_TUNE: time the candidate kernels of every scale group on the plan's own shapes and
 // workspace, and keep the fastest.  FP64 plans (band limit >= 128): theta samples per lane of
 // k_lsum (1, 2, 4, 8).  Mixed plans (band limit >= 64): for the l-contraction the matrix-core
@@ -825,6 +941,18 @@ void autotune(s2w_plan p)
             }
         });
         if (bt) p->route_tsum[Lk] = bt < 0 ? 1 : 0;
+    }
+    // the analysis l-contraction of all matrix-core groups: one launch per group (1) or the
+    // persistent launch over the cost-sorted work list (2)
+    if (mixed && !p->lsum_list && build_lsum_list(p)) {
+        const s2w::LsumList gl = lsum_list_args(p, p->flm);
+        const int best = pick({1, 2}, [&](int c) {
+            if (c == 1)
+                for (int k = 0; k < gl.ngroups; ++k) s2w::launch_lsum_mm(gl.a[k], gl.o[k], gl.NS[k], nullptr);
+            else
+                s2w::launch_lsum_list(gl, p->items, p->counters, p->list_blocks, nullptr);
+        });
+        p->lsum_list = best == 2;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -933,7 +1061,7 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
     if (!out) return fail(S2W_EINVAL, "null output pointer");
     *out = nullptr;
     if (batch < 1) return fail(S2W_EINVAL, "batch must be >= 1");
-    if (flags & ~(unsigned)(S2W_PLAN_TUNE | S2W_PLAN_GRAPH | S2W_PLAN_NO_WORKSPACE))
+    if (flags & ~(unsigned)(S2W_PLAN_TUNE | S2W_PLAN_GRAPH | S2W_PLAN_NO_WORKSPACE | S2W_PLAN_PERSISTENT))
         return fail(S2W_EINVAL, "unknown flags");
     if ((flags & S2W_PLAN_NO_WORKSPACE) && (flags & (S2W_PLAN_TUNE | S2W_PLAN_GRAPH)))
         return fail(S2W_EINVAL, "S2W_PLAN_NO_WORKSPACE excludes S2W_PLAN_TUNE and S2W_PLAN_GRAPH");
@@ -1047,6 +1175,10 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
             for (auto &it : p->ws)
                 if (!dalloc(p, *it.first, it.second)) return oom("workspace");
     }
+    if ((flags & S2W_PLAN_PERSISTENT) && precision == S2W_MIXED && !p->no_ws) {
+        if (!build_lsum_list(p)) return oom("work list");
+        p->lsum_list = true;
+    }
     if (flags & S2W_PLAN_TUNE) autotune(p);
     p->graph = (flags & S2W_PLAN_GRAPH) != 0;
     if (hipDeviceSynchronize() != hipSuccess) {
@@ -1142,7 +1274,27 @@ static void analysis_from_flm(s2w_plan p, const double *flm, void *wav_, double 
     if (mixed) {
         float *wav32 = (float *)wav_;
         float *A32 = (float *)p->bufA, *B32 = (float *)p->bufB;
-        for (auto &grp : p->groups) {
+        const bool listed = p->lsum_list && p->B == p->list_B;
+        if (listed) {
+            const s2w::LsumList gl = lsum_list_args(p, flm);
+            Work wk;
+            for (int k = 0; k < gl.ngroups; ++k) {
+                const auto &grp = p->groups[p->lgroups[k]];
+                const Work w1 = rec_work_psi(p, grp.scales, grp.L, grp.L, p->S.s[grp.scales[0]].n, B);
+                wk.flop += w1.flop;
+                wk.flop64 += w1.flop64;
+            }
+            Prof pr_(p, "lsum_mm", wk, st);
+            s2w::launch_lsum_list(gl, p->items, p->counters, p->list_blocks, st);
+        }
+        for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+            const auto &grp = p->groups[gi];
+            // output offset of a group computed by the persistent launch (else 0: computed here)
+            size_t goff = listed ? p->list_end : 0;
+            bool done = false;
+            if (listed)
+                for (size_t k = 0; k < p->lgroups.size(); ++k)
+                    if (p->lgroups[k] == (int)gi) { goff = p->lgroup_off[k]; done = true; }
             const DevGrid &g = p->grids[grp.L];
             const int Lk = grp.L, NS = (int)grp.scales.size();
             const auto &si = p->S.s[grp.scales[0]];
@@ -1159,11 +1311,13 @@ static void analysis_from_flm(s2w_plan p, const double *flm, void *wav_, double 
                 la.w[s] = p->wpsi[grp.scales[s]];
                 la.lmin[s] = p->lmin[grp.scales[s]];
                 la.out[s] = p->bufC + s * cstride;
-                mo.out[s] = A32 + s * cstride;
+                mo.out[s] = A32 + goff + s * cstride;
             }
-            if (lsum_vector(p, Lk)) {
+            if (done) {
+                // computed by the persistent launch
+            } else if (lsum_vector(p, Lk)) {
                 { Prof pr_(p, "lsum", rec_work_psi(p, grp.scales, la.L, la.mcount, si.n, B), st); s2w::launch_lsum(la, NS, B, st); }
-                { Prof pr_(p, "convert", 0.0, st); s2w::launch_convert(p->bufC, A32, NS * cstride, true, st); }
+                { Prof pr_(p, "convert", 0.0, st); s2w::launch_convert(p->bufC, A32 + goff, NS * cstride, true, st); }
             } else {
                 Prof pr_(p, "lsum_mm", rec_work_psi(p, grp.scales, la.L, la.mcount, si.n, B), st);
                 s2w::launch_lsum_mm(la, mo, NS, st);
@@ -1171,7 +1325,7 @@ static void analysis_from_flm(s2w_plan p, const double *flm, void *wav_, double 
             for (int s = 0; s < NS; ++s) {
                 const int k = grp.scales[s];
                 GammaArgs ga = gamma_args(p, Lk, Lk, Lk, Lk, si.n, ng);
-                ga.src = A32 + s * cstride;
+                ga.src = A32 + goff + s * cstride;
                 ga.dst = B32;
                 if (p->F.xi_imag) { ga.phr = 0.0; ga.phi = -1.0; }
                 {

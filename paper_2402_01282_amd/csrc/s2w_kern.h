@@ -116,6 +116,20 @@ struct MixIn {
     double *out[MAX_NS];         // [B][mcount][nn][L] complex FP64, defined for l >= m
 };
 void launch_lsum_mm(const LsumArgs &a, const MixOut &o, int NS, hipStream_t st);
+
+// persistent mixed l-contraction over several degree groups (band limit >= 64, 4 waves per
+// block): per group its arguments, outputs and scale count; work items in eight per-XCD
+// lists (cnt[x] items from off[x]), each item (x: group | n index << 4 | theta block << 8 |
+// column group << 16, y: m)
+constexpr int MAX_LGROUPS = 8;
+struct LsumList {
+    int ngroups;
+    int NS[MAX_LGROUPS];
+    int cnt[8], off[8];
+    LsumArgs a[MAX_LGROUPS];
+    MixOut o[MAX_LGROUPS];
+};
+void launch_lsum_list(const LsumList &gl, const uint2 *items, unsigned *counters, int nblocks, hipStream_t st);
 void launch_tsum_mm(const TsumArgs &a, const MixIn &in, int NS, hipStream_t st);
 
 void launch_lsum(const LsumArgs &a, int NS, int B, hipStream_t st);

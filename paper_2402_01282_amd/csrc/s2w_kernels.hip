@@ -1115,8 +1115,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 
 // Plain prime-factor stages (direct length-n1 and length-n2 sums, twiddles read
 // from global memory, two LDS buffers per row pair); used by the FP32 (mixed)
-// path.  Position p holds input index pin[p] and, after both stages, output
-// frequency pout[p].
+// path for lengths the matrix-core DFT does not cover (a prime factor above 95, e.g.
+// 1999 at L = 1000).  The sums accumulate in FP64 whatever the element type: a direct
+// sum of a prime length takes up to 2L - 1 terms, whose FP32 accumulation alone would
+// approach 1e-6 of the result.  Position p holds input index pin[p] and, after both
+// stages, output frequency pout[p].
 
 template <typename Tr>
 __device__ inline void pfa_stages_direct(typename V2<Tr>::t *Z, typename V2<Tr>::t *Y, const double2 *w1,
@@ -1128,25 +1131,26 @@ __device__ inline void pfa_stages_direct(typename V2<Tr>::t *Z, typename V2<Tr>:
         const int nb1 = (n1 + 3) / 4, nb2 = (n2 + 3) / 4;
         for (int task = tid; task < nb1 * nb2; task += nt) {
             const int a1b = (task / nb2) * 4, m2b = (task % nb2) * 4;
-            C2 acc[4][4];
+            double2 acc[4][4];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = mk2<Tr>(0, 0);
+                for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
             int tw[4], st[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) { st[i] = (a1b + i) % n1; tw[i] = 0; }
             for (int m1 = 0; m1 < n1; ++m1) {
-                C2 z[4], w[4];
+                double2 z[4], w[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int m2 = m2b + j < n2 ? m2b + j : n2 - 1;
-                    z[j] = Z[m1 * n2 + m2];
+                    const C2 zt = Z[m1 * n2 + m2];
+                    z[j] = make_double2((double)zt.x, (double)zt.y);
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const double2 wd = w1[tw[i]];
-                    w[i] = mk2<Tr>((Tr)wd.x, sgn * (Tr)wd.y);
+                    w[i] = make_double2(wd.x, (double)sgn * wd.y);
                     tw[i] += st[i];
                     if (tw[i] >= n1) tw[i] -= n1;
                 }
@@ -1162,7 +1166,7 @@ __device__ inline void pfa_stages_direct(typename V2<Tr>::t *Z, typename V2<Tr>:
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    if (a1b + i < n1 && m2b + j < n2) Y[(a1b + i) * n2 + m2b + j] = acc[i][j];
+                    if (a1b + i < n1 && m2b + j < n2) Y[(a1b + i) * n2 + m2b + j] = mk2<Tr>((Tr)acc[i][j].x, (Tr)acc[i][j].y);
         }
     }
     __syncthreads();
@@ -1170,25 +1174,26 @@ __device__ inline void pfa_stages_direct(typename V2<Tr>::t *Z, typename V2<Tr>:
         const int nb1 = (n1 + 3) / 4, nb2 = (n2 + 3) / 4;
         for (int task = tid; task < nb1 * nb2; task += nt) {
             const int a1b = (task / nb2) * 4, a2b = (task % nb2) * 4;
-            C2 acc[4][4];
+            double2 acc[4][4];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = mk2<Tr>(0, 0);
+                for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
             int tw[4], st[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) { st[j] = (a2b + j) % n2; tw[j] = 0; }
             for (int m2 = 0; m2 < n2; ++m2) {
-                C2 y[4], w[4];
+                double2 y[4], w[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int a1 = a1b + i < n1 ? a1b + i : n1 - 1;
-                    y[i] = Y[a1 * n2 + m2];
+                    const C2 yt = Y[a1 * n2 + m2];
+                    y[i] = make_double2((double)yt.x, (double)yt.y);
                 }
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const double2 wd = w2[tw[j]];
-                    w[j] = mk2<Tr>((Tr)wd.x, sgn * (Tr)wd.y);
+                    w[j] = make_double2(wd.x, (double)sgn * wd.y);
                     tw[j] += st[j];
                     if (tw[j] >= n2) tw[j] -= n2;
                 }
@@ -1204,7 +1209,7 @@ __device__ inline void pfa_stages_direct(typename V2<Tr>::t *Z, typename V2<Tr>:
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    if (a1b + i < n1 && a2b + j < n2) Z[(a1b + i) * n2 + a2b + j] = acc[i][j];
+                    if (a1b + i < n1 && a2b + j < n2) Z[(a1b + i) * n2 + a2b + j] = mk2<Tr>((Tr)acc[i][j].x, (Tr)acc[i][j].y);
         }
     }
     __syncthreads();

@@ -669,21 +669,18 @@ __device__ __forceinline__ f16v mfma32(const bf16x8 &a, const bf16x8 &b, const f
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-template <int NS, int W>
-__global__ __launch_bounds__(64 * W, 2) void k_lsum_bf3(const LsumArgs a, const MixOut o)
+// One unit (m, n index ni, column group g) on the theta block tb: the body of the
+// l-contraction, shared by the per-group launch (k_lsum_bf3) and the persistent launch over
+// a work list (k_lsum_bf3_list).  Dp, Up: the block's d slices and coefficient buffers;
+// lsab: the dynamic LDS of the coefficient row (sized for the largest band limit).
+template <int W>
+__device__ __forceinline__ void lsum_bf3_unit(const LsumArgs &a, const MixOut &o, const int NS, const int m,
+                                              const int ni, const int g, const int tb, __bf16 *Dp,
+                                              __bf16 (*Up)[3 * 64 * LB_RS], double2 *lsab)
 {
     constexpr int R = 4 / W;           // staging slots per thread
     const int L = a.L;
-    const int ntt = (L + 63) >> 6;
-    const int ntb = (ntt + W - 1) / W;
     const int B = o.B, ncols = 2 * B * NS;
-    const int ngrp = (ncols + 63) >> 6;
-    const int nunit = a.mcount * a.nn * ngrp;
-    // XCD-aware order: the ntb theta blocks of one unit get consecutive slots on one XCD
-    const int bid = blockIdx.x, xcd = bid & 7, kx = bid >> 3;
-    const int tb = kx % ntb, unit = (kx / ntb) * 8 + xcd;
-    if (unit >= nunit) return;
-    const int m = unit % a.mcount, ni = (unit / a.mcount) % a.nn, g = unit / (a.mcount * a.nn);
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int n = a.nval[ni], ng = a.nglob[ni];
     const int an = n < 0 ? -n : n;
@@ -697,10 +694,7 @@ __global__ __launch_bounds__(64 * W, 2) void k_lsum_bf3(const LsumArgs a, const 
         for (int s = s0; s <= s1; ++s) glmin = min(glmin, a.lmin[s]);
     }
 
-    __shared__ __align__(16) __bf16 Dp[W * LB_SLICE];       // per wave: [part][theta][l]
-    __shared__ __align__(16) __bf16 Up[2][3 * 64 * LB_RS];  // per buffer: [part][column][l]
-    extern __shared__ double2 lsab[];                        // (A_l, B_l), then S_l
-    double *lss = reinterpret_cast<double *>(lsab + L + LS_CPAD);
+    double *lss = reinterpret_cast<double *>(lsab + L + LS_CPAD);   // (A_l, B_l), then S_l
 
     const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
     for (int l = l0 + tid; l < L + LS_CPAD; l += 64 * W) {
@@ -917,6 +911,57 @@ __global__ __launch_bounds__(64 * W, 2) void k_lsum_bf3(const LsumArgs a, const 
     }
 }
 
+template <int NS, int W>
+__global__ __launch_bounds__(64 * W, 2) void k_lsum_bf3(const LsumArgs a, const MixOut o)
+{
+    __shared__ __align__(16) __bf16 Dp[W * LB_SLICE];       // per wave: [part][theta][l]
+    __shared__ __align__(16) __bf16 Up[2][3 * 64 * LB_RS];  // per buffer: [part][column][l]
+    extern __shared__ double2 lsab[];
+    const int ntt = (a.L + 63) >> 6;
+    const int ntb = (ntt + W - 1) / W;
+    const int ngrp = (2 * o.B * NS + 63) >> 6;
+    const int nunit = a.mcount * a.nn * ngrp;
+    // XCD-aware order: the ntb theta blocks of one unit get consecutive slots on one XCD
+    const int bid = blockIdx.x, xcd = bid & 7, kx = bid >> 3;
+    const int tb = kx % ntb, unit = (kx / ntb) * 8 + xcd;
+    if (unit >= nunit) return;
+    const int m = unit % a.mcount, ni = (unit / a.mcount) % a.nn, g = unit / (a.mcount * a.nn);
+    lsum_bf3_unit<W>(a, o, NS, m, ni, g, tb, Dp, Up, lsab);
+}
+
+// Persistent l-contraction over every degree group of a transform: one launch of
+// about two blocks per CU, each taking work items (group, m, n, column group, theta block)
+// from the list of its XCD (blocks are dispatched to the eight XCDs in turn) through an
+// atomic counter.  Each list is sorted by decreasing cost (degrees L_j - max(m, |n|)), so
+// the cheap items of every group fill the end of the launch, and all theta blocks of a
+// unit are on one list (their coefficient rows are read through one L2).  The counters
+// are zero at launch (k_zero_counters).
+template <int W>
+__global__ __launch_bounds__(64 * W, 2) void k_lsum_bf3_list(const LsumList gl, const uint2 *__restrict__ items,
+                                                             unsigned *counters)
+{
+    __shared__ __align__(16) __bf16 Dp[W * LB_SLICE];
+    __shared__ __align__(16) __bf16 Up[2][3 * 64 * LB_RS];
+    __shared__ int item_sh;
+    extern __shared__ double2 lsab[];
+    const int x = blockIdx.x & 7;
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = (int)atomicAdd(&counters[x], 1u);
+        __syncthreads();               // the previous item is finished by every wave
+        const int i = item_sh;
+        __syncthreads();               // every thread has read the item index
+        if (i >= gl.cnt[x]) break;
+        const uint2 it = items[gl.off[x] + i];
+        const int gi = it.x & 15, ni = (it.x >> 4) & 15, tb = (it.x >> 8) & 255, g = it.x >> 16, m = (int)it.y;
+        lsum_bf3_unit<W>(gl.a[gi], gl.o[gi], gl.NS[gi], m, ni, g, tb, Dp, Up, lsab);
+    }
+}
+
+__global__ void k_zero_counters(unsigned *c, int n)
+{
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0u;
+}
+
 // ------------------------------------------------------------- launchers ---
 
 void launch_lsum_bf3(const LsumArgs &a, const MixOut &o, int NS, hipStream_t st)
@@ -936,6 +981,15 @@ void launch_lsum_bf3(const LsumArgs &a, const MixOut &o, int NS, hipStream_t st)
         if (W == 2) hipLaunchKernelGGL((k_lsum_bf3<2, 2>), grid, blk, smem, st, a, o);
         else hipLaunchKernelGGL((k_lsum_bf3<2, 4>), grid, blk, smem, st, a, o);
     }
+}
+
+void launch_lsum_list(const LsumList &gl, const uint2 *items, unsigned *counters, int nblocks, hipStream_t st)
+{
+    int Lmax = 0;
+    for (int i = 0; i < gl.ngroups; ++i) Lmax = std::max(Lmax, gl.a[i].L);
+    const size_t smem = (sizeof(double2) + sizeof(double)) * (size_t)(Lmax + LS_CPAD);
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, counters, 8);
+    hipLaunchKernelGGL(k_lsum_bf3_list<4>, dim3((unsigned)nblocks), dim3(256), smem, st, gl, items, counters);
 }
 
 void launch_lsum_mm(const LsumArgs &a, const MixOut &o, int NS, hipStream_t st)

@@ -1,5 +1,7 @@
-"""Plan flags: graph replay (S2W_PLAN_GRAPH) and tile-shape autotuning (S2W_PLAN_TUNE)
-give the same coefficients and maps as the plain plan, replay after replay."""
+"""Plan flags: graph replay (S2W_PLAN_GRAPH) and autotuning (S2W_PLAN_TUNE) give the same
+coefficients and maps as the plain plan, replay after replay: bitwise in FP64 (whose
+candidates differ only in the work split), to the mixed form's precision in mixed plans
+(whose candidates include other arithmetic), and bitwise between replays of one input."""
 import numpy as np
 import pytest
 
@@ -39,7 +41,25 @@ def test_graph_and_tune_match_plain_plan(prec):
         w_ref, s_ref = plain.analysis(f)
         g_ref = plain.synthesis(w_ref, s_ref)
         torch.cuda.synchronize()
-        assert torch.equal(wav, w_ref), rep
-        assert torch.equal(scal, s_ref), rep
-        assert torch.equal(f2, g_ref), rep
-        print(f"  replay {rep}: identical", flush=True)
+        if prec == "fp64":
+            # the FP64 candidates differ only in the work split: same sums in the same order
+            assert torch.equal(wav, w_ref), rep
+            assert torch.equal(scal, s_ref), rep
+            assert torch.equal(f2, g_ref), rep
+            print(f"  replay {rep}: identical", flush=True)
+        else:
+            # mixed candidates (FP64 vector or BF16 matrix-core contractions, persistent or
+            # per-group launches) agree to the precision of the mixed form
+            ew = (torch.linalg.norm((wav - w_ref).double()) / torch.linalg.norm(w_ref.double())).item()
+            ef = (torch.linalg.norm(f2 - g_ref) / torch.linalg.norm(g_ref)).item()
+            print(f"  replay {rep}: rel diff wavelets {ew:.1e}, maps {ef:.1e}", flush=True)
+            assert ew < 1e-6 and ef < 1e-6, rep
+            assert (torch.linalg.norm(f2 - f) / torch.linalg.norm(f)).item() < 1e-6
+    if prec == "mixed":
+        # replays of one input are bitwise equal
+        w1 = wav.clone()
+        g1 = f2.clone()
+        fast.analysis(f, wav, scal)
+        fast.synthesis(wav, scal, f2)
+        torch.cuda.synchronize()
+        assert torch.equal(w1, wav) and torch.equal(g1, f2)

@@ -151,3 +151,30 @@ def test_mixed_routes_agree(L, N, B):
 def _plan_flags(L, N, J0, B, flags):
     import paper_2402_01282_amd as s2w
     return s2w.Plan(L, N, 2.0, J0, batch=B, precision=s2w.S2W_MIXED, device=0, flags=flags)
+
+
+@pytest.mark.parametrize("L,N,B", [(256, 4, 16), (1000, 3, 4)])
+def test_mixed_persistent_matches_per_group(L, N, B):
+    """S2W_PLAN_PERSISTENT: the analysis l-contraction of every matrix-core degree group in one
+    launch over the cost-sorted work list gives the same coefficients as one launch per group
+    (the same per-unit arithmetic, so equal to rounding), and the oracle's on one map."""
+    torch = _torch()
+    import paper_2402_01282_amd as s2w
+    print(f"[mixed persistent L={L} N={N} B={B}]", flush=True)
+    flm = np.stack([S.sphere_flm(L, S.stream_key(9, b)) for b in range(B)])
+    p64 = s2w.Plan(L, N, 2.0, 0, batch=B, device=0)
+    f = p64.sht_inverse(torch.from_numpy(flm).cuda())
+    w0, s0 = _plan_flags(L, N, 0, B, 0).analysis(f)
+    plan = _plan_flags(L, N, 0, B, s2w.S2W_PLAN_PERSISTENT)
+    w1, s1 = plan.analysis(f)
+    d = (torch.linalg.norm((w1 - w0).double()) / torch.linalg.norm(w0.double())).item()
+    print(f"  persistent vs per-group rel diff {d:.1e}", flush=True)
+    assert d < 1e-7
+    P = wavelets.Plan(L, N, 2.0, 0)
+    wr, _ = wavelets.analysis_lm(flm[B - 1], P)
+    views = plan.wav_views(w1)
+    es = [_rel(views[k][B - 1].double().cpu().numpy(), w) for k, w in enumerate(wr)]
+    print("  per-scale rel err " + " ".join(f"{x:.1e}" for x in es), flush=True)
+    assert max(es) < TOL
+    f2 = plan.synthesis(w1, s1)
+    assert (torch.linalg.norm(f2 - f) / torch.linalg.norm(f)).item() < TOL
