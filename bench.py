@@ -52,11 +52,16 @@ def parse():
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay each transform as a HIP graph (no per-kernel timing)")
     ap.add_argument("--no-tune", action="store_true", help="skip the plan's tile-shape autotuning")
+    ap.add_argument("--precompute", action="store_true",
+                    help="precompute mode: Wigner d tabulated in device memory for grids of band limit <= 512")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM traffic counters)")
     ap.add_argument("--sweep", action="store_true",
                     help="no headline line: the mixed form at batch 1, 4, 16, 64, each eager and with HIP-graph "
                          "replay, one JSON line with maps/s per setting")
+    ap.add_argument("--ball", action="store_true",
+                    help="no headline line: the ball transform at the setting of the paper's ball benchmark "
+                         "(N=1, P=L=256 by default; --L sets L=P), FP64 and mixed, one JSON line")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="no benchmark: read two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; csv output) "
                          "of 'bench.py --precision mixed --steps 1 --warmup 0 --no-tune --copy-calibration' (one "
@@ -211,9 +216,16 @@ def run_form(args, precision, B):
     L, N, lam, J0 = args.L, args.N, args.lam, args.J0
     mixed = precision == "mixed"
     print(f"[bench] L={L} N={N} lambda={lam} J0={J0} batch={B} precision={precision}", file=sys.stderr, flush=True)
-    flags = (0 if args.no_tune else s2w.S2W_PLAN_TUNE) | (s2w.S2W_PLAN_GRAPH if args.graph else 0)
+    flags = (0 if args.no_tune else s2w.S2W_PLAN_TUNE) | (s2w.S2W_PLAN_GRAPH if args.graph else 0) \
+        | (s2w.S2W_PLAN_PRECOMPUTE if args.precompute else 0)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    t0 = time.perf_counter()
     plan = s2w.Plan(L, N, lam, J0, batch=B, device=0, precision=s2w.S2W_MIXED if mixed else s2w.S2W_FP64,
                     flags=flags)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    plan_bytes = free0 - torch.cuda.mem_get_info()[0]   # the plan's tables and workspace
     # synthetic Gaussian random fields, synthesised on the GPU (FP64 inverse SHT, one map per call)
     synth = s2w.Plan(L, 1, lam, 0, batch=1, device=0)
     f = torch.empty(plan.map_shape, dtype=torch.float64, device="cuda")
@@ -271,6 +283,7 @@ def run_form(args, precision, B):
     out = {"value": maps_per_s, "ms_per_step": 1e3 * dt / args.steps,
            "dtype": "f32+f64" if mixed else "f64", "workload": workload, "batch": B,
            "coefficients_per_s": maps_per_s * (plan.wav_offset[-1] // B), "round_trip_rel_err": err,
+           "plan_create_s": t_plan, "plan_device_gib": plan_bytes / 2 ** 30,
            "gradient": {"maps_per_s": B * args.steps / dtg, "ms_per_step": 1e3 * dtg / args.steps,
                         "what": "analysis + transpose of the analysis (gradient of sum_j sum (W^j)^2)"}}
     if kern:
@@ -322,8 +335,61 @@ def run_form(args, precision, B):
     return out
 
 
+# The paper's ball round trip (S2BALL, one A100, FP64, N=1, P=L; Section 5.4, Table 2), ms
+PAPER_BALL_MS = {8: 0.75, 16: 0.95, 32: 1.3, 64: 3.0, 128: 17.0, 256: 160.0}
+
+
+def run_ball(args):
+    """Ball analysis + synthesis round trips of one map at N=1, P=L (lambda = nu = 2,
+    J0 = J0' = 0), FP64 and mixed, timed as the sphere forms are."""
+    import torch
+
+    import paper_2402_01282_amd as s2w
+    import synthetic
+
+    L = args.L if args.L != 1024 else 256
+    P, N = L, 1
+    flmp = synthetic.ball_flmp(L, P, synthetic.stream_key(13))
+    rows = {}
+    for prec in ("fp64", "mixed"):
+        print(f"[bench] ball L=P={L} N=1 {prec}", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        plan = s2w.BallPlan(L, N, P, batch=1, device=0,
+                            precision=s2w.S2W_MIXED if prec == "mixed" else s2w.S2W_FP64)
+        torch.cuda.synchronize()
+        t_plan = time.perf_counter() - t0
+        f = plan.sl_inverse(torch.from_numpy(flmp[None].copy()))
+        wav = plan.empty_wav()
+        scal = torch.empty(plan.map_shape, dtype=torch.float64, device="cuda")
+        f2 = torch.empty_like(f)
+        for _ in range(args.warmup):
+            plan.analysis(f, wav, scal)
+            plan.synthesis(wav, scal, f2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.analysis(f, wav, scal)
+            plan.synthesis(wav, scal, f2)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        err = (torch.linalg.norm(f2 - f) / torch.linalg.norm(f)).item()
+        rows[prec] = {"ms_per_round_trip": 1e3 * dt, "round_trips_per_s": 1.0 / dt, "round_trip_rel_err": err,
+                      "plan_create_s": t_plan, "wavelet_coefficients": plan.wav_offset[-1]}
+        del plan, wav, scal, f, f2
+        torch.cuda.empty_cache()
+    out = {"ball": f"ball directional wavelets analysis+synthesis, L=P={L}, N=1, lambda=nu=2, J0=J0'=0, one map",
+           "forms": rows,
+           "paper_context": {"S2BALL_one_A100_ms": PAPER_BALL_MS.get(L), "source": "Section 5.4, Table 2 (FP64)"}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.ball:
+        if args.gpus != 1:
+            sys.exit(2)
+        run_ball(args)
+        return
     if args.record_traffic:
         record_traffic(args.record_traffic[0], args.record_traffic[1], args)
         return
@@ -366,7 +432,9 @@ def main():
         "dtype": head["dtype"],
         "data": "synthetic Gaussian random fields, C_l = 1/(l+1)^2, synthesised on the GPU",
         "config": {"workload": head["workload"], "L": args.L, "N": args.N, "lambda": args.lam, "J0": args.J0,
-                   "batch": head["batch"], "form": forms[0], "tuned": not args.no_tune, "graph": args.graph},
+                   "batch": head["batch"], "form": forms[0], "tuned": not args.no_tune, "graph": args.graph,
+                   "precompute": args.precompute},
+        "plan_create_s": head["plan_create_s"],
         "coefficients_per_s": head["coefficients_per_s"],
         "round_trip_rel_err": head["round_trip_rel_err"],
         "gradient": head["gradient"],

@@ -68,13 +68,19 @@ enum {
     S2W_PLAN_NO_WORKSPACE = 4, /* allocate no workspace (tables only): the plan runs only through
                                s2w_analysis_noalloc; other transform entry points return S2W_ESTATE.
                                Excludes S2W_PLAN_TUNE and S2W_PLAN_GRAPH. */
-    S2W_PLAN_PERSISTENT = 8 /* mixed plans: the l-contraction of the analysis runs as one
+    S2W_PLAN_PERSISTENT = 8, /* mixed plans: the l-contraction of the analysis runs as one
                                persistent launch over every degree group of band limit >= 64 on
                                matrix cores, its work items (degree group, m, n, column group,
                                theta block) in per-XCD lists sorted by decreasing cost
                                L_j - max(m, |n|) (Section 3.3: the top scales dominate).  With
                                S2W_PLAN_TUNE alone the autotuner chooses between this and one
                                launch per degree group by timing both. */
+    S2W_PLAN_PRECOMPUTE = 16 /* precompute mode (Section 4.2): for every grid of band limit <= 512,
+                               Wigner d^l_mn(theta_b) is tabulated in device memory at plan
+                               creation (all n of the plan, m < L, l >= max(m, |n|): about
+                               N L^3 / 2 doubles per grid, 4.8 GB at L = 512, N = 8) and the FP64
+                               vector contractions (FP64 plans below 16 maps, the vector route of
+                               mixed plans) read d from it instead of running the recursion. */
 };
 
 /* Size of the static device scratch that s2w_analysis_noalloc works in (one copy per

@@ -24,6 +24,7 @@ S2W_PLAN_TUNE = 1
 S2W_PLAN_GRAPH = 2
 S2W_PLAN_NO_WORKSPACE = 4
 S2W_PLAN_PERSISTENT = 8
+S2W_PLAN_PRECOMPUTE = 16
 S2W_SCRATCH_BYTES = 64 << 20
 
 _STATUS = {0: "S2W_OK", -1: "S2W_EINVAL", -2: "S2W_ENOMEM", -3: "S2W_EHIP",

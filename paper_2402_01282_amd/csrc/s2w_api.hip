@@ -203,6 +203,8 @@ struct s2w_plan_s {
     // mixed plans, per grid band limit: contraction route, 1 = FP64 vector kernels with an
     // FP32 conversion at the boundary (fastest for very small batches), 0 = matrix cores
     std::map<int, int> route_lsum, route_tsum;
+    // precompute mode: per grid band limit (<= PRE_MAX_L), the d table and its row offsets
+    std::map<int, std::pair<double *, int64_t *>> dtabs;
     // persistent l-contraction of the mixed analysis (one launch over the degree groups in
     // lgroups, work items in eight per-XCD lists sorted by cost); used when lsum_list is set
     // and the batch is the one the list was built for
@@ -515,6 +517,11 @@ LsumArgs lsum_args(s2w_plan p, const DevGrid &g, int mcount, const std::vector<i
     a.sh = g.sh;
     a.ceps = g.ceps;
     a.seps = g.seps;
+    auto dt = p->dtabs.find(g.L);
+    if (dt != p->dtabs.end()) {
+        a.dtab = dt->second.first;
+        a.doff = dt->second.second;
+    }
     return a;
 }
 
@@ -545,7 +552,44 @@ TsumArgs tsum_args(s2w_plan p, const DevGrid &g, int mcount, const std::vector<i
     a.seps = g.seps;
     a.npar = npar;
     sig_counts(mcount, npar, a.M0, a.M1);
+    auto dt = p->dtabs.find(g.L);
+    if (dt != p->dtabs.end()) {
+        a.dtab = dt->second.first;
+        a.doff = dt->second.second;
+    }
     return a;
+}
+
+// Precompute mode (S2W_PLAN_PRECOMPUTE): for every grid of band limit <= PRE_MAX_L, the table
+// d^l_mn(theta_b) for all n of the recursion tables, m < L and max(m, |n|) <= l < L, filled
+// on the device by the recursion (one launch per n).  The FP64 vector contractions then read
+// d from it; grids above PRE_MAX_L keep the recursion.
+constexpr int PRE_MAX_L = 512;
+
+bool make_dtables(s2w_plan p)
+{
+    const int NG = (int)p->nglob.size();
+    for (auto &kv : p->grids) {
+        const int L = kv.first;
+        if (L > PRE_MAX_L) continue;
+        std::vector<int64_t> off((size_t)NG * L, 0);
+        int64_t tot = 0;
+        for (int ng = 0; ng < NG; ++ng)
+            for (int m = 0; m < L; ++m) {
+                off[(size_t)ng * L + m] = tot;
+                const int l0 = std::max(m, std::abs(p->nglob[ng]));
+                if (l0 < L) tot += (int64_t)(L - l0) * L;
+            }
+        double *tab = nullptr;
+        int64_t *doff = nullptr;
+        if (!dalloc(p, tab, (size_t)tot) || !upload(p, doff, off)) return false;
+        for (int ng = 0; ng < NG; ++ng) {
+            LsumArgs la = lsum_args(p, kv.second, L, std::vector<int>{p->nglob[ng]});
+            s2w::launch_dtable(la, tab, doff, nullptr);
+        }
+        p->dtabs[L] = {tab, doff};
+    }
+    return hipDeviceSynchronize() == hipSuccess && hipGetLastError() == hipSuccess;
 }
 
 GammaArgs gamma_args(s2w_plan p, int M, int L, int Min, int Mout, const std::vector<int> &ns, int ng)
@@ -1061,7 +1105,8 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
     if (!out) return fail(S2W_EINVAL, "null output pointer");
     *out = nullptr;
     if (batch < 1) return fail(S2W_EINVAL, "batch must be >= 1");
-    if (flags & ~(unsigned)(S2W_PLAN_TUNE | S2W_PLAN_GRAPH | S2W_PLAN_NO_WORKSPACE | S2W_PLAN_PERSISTENT))
+    if (flags & ~(unsigned)(S2W_PLAN_TUNE | S2W_PLAN_GRAPH | S2W_PLAN_NO_WORKSPACE | S2W_PLAN_PERSISTENT |
+                            S2W_PLAN_PRECOMPUTE))
         return fail(S2W_EINVAL, "unknown flags");
     if ((flags & S2W_PLAN_NO_WORKSPACE) && (flags & (S2W_PLAN_TUNE | S2W_PLAN_GRAPH)))
         return fail(S2W_EINVAL, "S2W_PLAN_NO_WORKSPACE excludes S2W_PLAN_TUNE and S2W_PLAN_GRAPH");
@@ -1175,6 +1220,7 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
             for (auto &it : p->ws)
                 if (!dalloc(p, *it.first, it.second)) return oom("workspace");
     }
+    if ((flags & S2W_PLAN_PRECOMPUTE) && !make_dtables(p)) return oom("precomputed d tables");
     if ((flags & S2W_PLAN_PERSISTENT) && precision == S2W_MIXED && !p->no_ws) {
         if (!build_lsum_list(p)) return oom("work list");
         p->lsum_list = true;

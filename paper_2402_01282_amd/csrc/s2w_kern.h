@@ -34,6 +34,8 @@ struct LsumArgs {
     int tileW;                   // waves per block of k_lsum_mm (1, 2, 4; 0: default)
     int lmin[MAX_NS];            // mixed kernels: first degree of each scale's filter support (the
                                  // weights are zero below it; 0 when unknown)
+    const double *dtab;          // precompute mode (FP64 vector kernels): d^l_mn(theta) of this grid,
+    const int64_t *doff;         // row l0 of (n, m) at dtab + doff[nglob L + m]; nullptr: recursion
 };
 
 // sum over theta (reduction across lanes)
@@ -50,6 +52,8 @@ struct TsumArgs {
     int M0, M1;                  // number of m with sigma index 0 / 1
     int lmin[MAX_NS];            // mixed kernels: first degree of each scale's filter support (the
                                  // weights are zero below it; 0 when unknown)
+    const double *dtab;          // precompute mode, as in LsumArgs
+    const int64_t *doff;
     const double *h[MAX_NS];     // rows [sig][b][m'][ni][c][L]
     const double *w[MAX_NS];
     int wstride;
@@ -133,6 +137,8 @@ void launch_lsum_list(const LsumList &gl, const uint2 *items, unsigned *counters
 void launch_tsum_mm(const TsumArgs &a, const MixIn &in, int NS, hipStream_t st);
 
 void launch_lsum(const LsumArgs &a, int NS, int B, hipStream_t st);
+// precompute mode: d table of one grid for the n values of a (nval, nglob), all m < L
+void launch_dtable(const LsumArgs &a, double *tab, const int64_t *doff, hipStream_t st);
 void launch_tsum(const TsumArgs &a, int NS, int B, hipStream_t st);
 void launch_gemm(const double *A, const double *Bm, double *C, int M, int N, int K, hipStream_t st,
                  bool accum = false);

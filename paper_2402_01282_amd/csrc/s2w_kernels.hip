@@ -34,8 +34,10 @@ __device__ inline int polar_theta(int p, int L, int npol) { return p < npol ? p 
 //
 // C_s[b][ni][m][theta] = sum_{l=l0}^{L-1} u_s(l) e^l(theta),
 // u_s(l) = S_l w_s[ni][l] flm[b][m][l]   (so that u e^l = w flm d^l).
+// PRE (precompute mode): d^l(theta) is read from the grid's table instead of being
+// recursed, and u_s(l) = w_s[ni][l] flm[b][m][l].
 
-template <int T, int NS>
+template <int T, int NS, bool PRE>
 __global__ __launch_bounds__(64) void k_lsum(const LsumArgs a)
 {
     const int m = blockIdx.x, ni = blockIdx.y;
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(64) void k_lsum(const LsumArgs a)
         k[t] = 0;
         c[t] = 0.0;
         cl[t] = 0.0;
-        if (th < a.L && l0 < lmax) {
+        if (!PRE && th < a.L && l0 < lmax) {
             c[t] = a.cth[th];
             cl[t] = a.ctl[th];
             start_value(mant, ex, p1, p2, a.ch[th], a.sh[th], a.ceps[th], a.seps[th], e[t], k[t]);
@@ -76,6 +78,8 @@ __global__ __launch_bounds__(64) void k_lsum(const LsumArgs a)
         for (int s = 0; s < NS; ++s) { acc[s][0][t] = 0.0; acc[s][1][t] = 0.0; }
     }
     bool anyAsleep = __any(asleep_any);
+    // precompute mode: this (n, m) row block of the table, and this lane's theta samples
+    const double *drow = PRE ? a.dtab + a.doff[(size_t)ng * a.L + m] : nullptr;
 
     for (int lb = l0; lb < lmax; lb += 64) {
         {
@@ -87,7 +91,7 @@ __global__ __launch_bounds__(64) void k_lsum(const LsumArgs a)
             if (l < lmax) {
                 A = a.A[tabm + l];
                 Bv = a.B[tabm + l];
-                const double S = a.S[tabm + l];
+                const double S = PRE ? 1.0 : a.S[tabm + l];
                 const double *fl = a.flm + (((size_t)b * a.flm_m + m) * a.flm_l + l) * 2;
                 const double fr = fl[0], fi = fl[1];
 #pragma unroll
@@ -113,17 +117,25 @@ __global__ __launch_bounds__(64) void k_lsum(const LsumArgs a)
                 for (int s = 0; s < NS; ++s) u[s] = sU[s][g + i];
 #pragma unroll
                 for (int t = 0; t < T; ++t) {
+                    if (PRE) {
+                        // table row of degree lb + g + i (past the last degree u is zero)
+                        const int th = chk * 64 * T + t * 64 + lane;
+                        const int li = lb + g + i - l0;
+                        e[t] = (th < a.L && lb + g + i < lmax) ? drow[(size_t)li * a.L + th] : 0.0;
+                    }
 #pragma unroll
                     for (int s = 0; s < NS; ++s) {
                         acc[s][0][t] = fma(u[s].x, e[t], acc[s][0][t]);
                         acc[s][1][t] = fma(u[s].y, e[t], acc[s][1][t]);
                     }
-                    const double en = fma(fma(ab.x, cl[t], fma(ab.x, c[t], -ab.y)), e[t], -ep[t]);
-                    ep[t] = e[t];
-                    e[t] = en;
+                    if (!PRE) {
+                        const double en = fma(fma(ab.x, cl[t], fma(ab.x, c[t], -ab.y)), e[t], -ep[t]);
+                        ep[t] = e[t];
+                        e[t] = en;
+                    }
                 }
             }
-            if (anyAsleep) {
+            if (!PRE && anyAsleep) {
                 bool any = false;
 #pragma unroll
                 for (int t = 0; t < T; ++t) {
@@ -163,7 +175,7 @@ __global__ __launch_bounds__(64) void k_lsum(const LsumArgs a)
 // P_s[b][m][ni][l] = S_l w_s[ni][l] sum_theta e^l(theta) h_s(theta)   (l >= l0, else 0)
 // h_s rows (re, im) come from the sigma-grouped layout [sig][b][m'][ni][c][theta].
 
-template <int T, int NS>
+template <int T, int NS, bool PRE>
 __global__ __launch_bounds__(256) void k_tsum(const TsumArgs a)
 {
     constexpr int LB = 16 / NS;          // l-steps per reduction block: 2*NS*LB = 32 entries
@@ -208,9 +220,11 @@ __global__ __launch_bounds__(256) void k_tsum(const TsumArgs a)
 #pragma unroll
         for (int s = 0; s < NS; ++s) { hr[s][t] = 0.0; hi[s][t] = 0.0; }
         if (th < a.L && l0 < lmax) {
-            c[t] = a.cth[th];
-            cl[t] = a.ctl[th];
-            start_value(mant, ex, p1, p2, a.ch[th], a.sh[th], a.ceps[th], a.seps[th], e[t], k[t]);
+            if (!PRE) {
+                c[t] = a.cth[th];
+                cl[t] = a.ctl[th];
+                start_value(mant, ex, p1, p2, a.ch[th], a.sh[th], a.ceps[th], a.seps[th], e[t], k[t]);
+            }
             if (k[t] == 0 && !is_polar(th, a.L, a.npol)) {
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
@@ -222,6 +236,7 @@ __global__ __launch_bounds__(256) void k_tsum(const TsumArgs a)
         asleep_any |= (k[t] < 0);
     }
     bool anyAsleep = __any(asleep_any);
+    const double *drow = PRE ? a.dtab + a.doff[(size_t)ng * a.L + m] : nullptr;
 
     for (int lb = l0; lb < lmax; lb += LB) {
         __syncthreads();
@@ -239,21 +254,27 @@ __global__ __launch_bounds__(256) void k_tsum(const TsumArgs a)
             for (int s = 0; s < NS; ++s) { pr[s] = 0.0; pi[s] = 0.0; }
 #pragma unroll
             for (int t = 0; t < T; ++t) {
+                if (PRE) {
+                    const int th = (w * T + t) * 64 + lane;
+                    e[t] = (th < a.L && lb + i < lmax) ? drow[(size_t)(lb + i - l0) * a.L + th] : 0.0;
+                }
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     pr[s] = fma(e[t], hr[s][t], pr[s]);
                     pi[s] = fma(e[t], hi[s][t], pi[s]);
                 }
-                const double en = fma(fma(ab.x, cl[t], fma(ab.x, c[t], -ab.y)), e[t], -ep[t]);
-                ep[t] = e[t];
-                e[t] = en;
+                if (!PRE) {
+                    const double en = fma(fma(ab.x, cl[t], fma(ab.x, c[t], -ab.y)), e[t], -ep[t]);
+                    ep[t] = e[t];
+                    e[t] = en;
+                }
             }
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 red[w][lane][(s * LB + i) * 2 + 0] = pr[s];
                 red[w][lane][(s * LB + i) * 2 + 1] = pi[s];
             }
-            if (anyAsleep && ((i & 7) == 7)) {
+            if (!PRE && anyAsleep && ((i & 7) == 7)) {
                 bool any = false;
 #pragma unroll
                 for (int t = 0; t < T; ++t) {
@@ -295,7 +316,7 @@ __global__ __launch_bounds__(256) void k_tsum(const TsumArgs a)
             const int cc = j & 1;
             const int l = lb + i;
             if (l < lmax) {
-                const double S = a.S[tabm + l];
+                const double S = PRE ? 1.0 : a.S[tabm + l];
                 const double wgt = a.w[s][(size_t)ni * a.wstride + l];
                 a.out[s][((((size_t)b * a.mcount + m) * a.nn + ni) * a.L + l) * 2 + cc] = v * S * wgt;
             }
@@ -308,6 +329,42 @@ __global__ __launch_bounds__(256) void k_tsum(const TsumArgs a)
             double *o = a.out[s] + ((((size_t)b * a.mcount + m) * a.nn + ni) * a.L + l) * 2;
             o[0] = 0.0;
             o[1] = 0.0;
+        }
+    }
+}
+
+// ------------------------------------------------------------- d tables ----
+// Precompute mode: d^l_mn(theta_b) = S_l e^l(theta_b) of one grid for every (n, m) and
+// l0 <= l < L, rows over theta: tab[doff[nglob L + m] + (l - l0) L + theta], by the same
+// scaled, log-rescaled recursion the contraction kernels run (a sample whose scaled value
+// has not reached the representable range holds 0, as those kernels treat it).  One lane
+// per theta sample, one block per (m, n, 64 samples).
+__global__ __launch_bounds__(64) void k_dtable(const LsumArgs a, double *tab, const int64_t *doff)
+{
+    const int m = blockIdx.x, ni = blockIdx.y;
+    const int th = blockIdx.z * 64 + threadIdx.x;
+    const int n = a.nval[ni], ng = a.nglob[ni];
+    const int an = n < 0 ? -n : n, l0 = m > an ? m : an;
+    if (l0 >= a.L || th >= a.L) return;
+    const size_t tabm = ((size_t)ng * a.Lrec + m) * a.Lrec;
+    const int p1 = (m + n) < 0 ? -(m + n) : (m + n);
+    const int p2 = (m - n) < 0 ? -(m - n) : (m - n);
+    const double c = a.cth[th], cl = a.ctl[th];
+    double e = 0.0, ep = 0.0;
+    int k = 0;
+    start_value(a.smant[(size_t)ng * a.Lrec + m], a.sexp[(size_t)ng * a.Lrec + m], p1, p2, a.ch[th], a.sh[th],
+                a.ceps[th], a.seps[th], e, k);
+    double *row = tab + doff[(size_t)ng * a.L + m] + th;
+    for (int l = l0; l < a.L; ++l) {
+        row[(size_t)(l - l0) * a.L] = k == 0 ? a.S[tabm + l] * e : 0.0;
+        const double A = a.A[tabm + l], Bv = a.B[tabm + l];
+        const double en = fma(fma(A, cl, fma(A, c, -Bv)), e, -ep);
+        ep = e;
+        e = en;
+        if (k < 0 && fabs(e) > 0x1p256) {
+            e *= 0x1p-512;
+            ep *= 0x1p-512;
+            k += 1;
         }
     }
 }
@@ -1570,7 +1627,15 @@ static void launch_lsum_t(const LsumArgs &a, int B, hipStream_t st)
 {
     const int nch = (a.L + 64 * T - 1) / (64 * T);
     dim3 grid(a.mcount, a.nn, B * nch);
-    hipLaunchKernelGGL((k_lsum<T, NS>), grid, dim3(64), 0, st, a);
+    if (a.dtab) hipLaunchKernelGGL((k_lsum<T, NS, true>), grid, dim3(64), 0, st, a);
+    else hipLaunchKernelGGL((k_lsum<T, NS, false>), grid, dim3(64), 0, st, a);
+}
+
+void launch_dtable(const LsumArgs &a, double *tab, const int64_t *doff, hipStream_t st)
+{
+    if (a.L <= 0 || a.nn <= 0) return;
+    dim3 grid(a.L, a.nn, (a.L + 63) / 64);
+    hipLaunchKernelGGL(k_dtable, grid, dim3(64), 0, st, a, tab, doff);
 }
 
 void launch_lsum(const LsumArgs &a, int NS, int B, hipStream_t st)
@@ -1627,7 +1692,8 @@ template <int T, int NS>
 static void launch_tsum_t(const TsumArgs &a, int B, int nw, hipStream_t st)
 {
     dim3 grid(a.mcount, a.nn, B);
-    hipLaunchKernelGGL((k_tsum<T, NS>), grid, dim3(64 * nw), 0, st, a);
+    if (a.dtab) hipLaunchKernelGGL((k_tsum<T, NS, true>), grid, dim3(64 * nw), 0, st, a);
+    else hipLaunchKernelGGL((k_tsum<T, NS, false>), grid, dim3(64 * nw), 0, st, a);
 }
 
 void launch_tsum_vec(const TsumArgs &a, int NS, int B, hipStream_t st);

@@ -125,3 +125,37 @@ def test_spherical_laguerre_transform_against_oracle(prec):
         assert _rel(got[b], flmp[b]) < 1e-12, b
     back = plan.sl_inverse(torch.from_numpy(np.stack(flmp))).cpu().numpy()
     assert _rel(back, f) < 1e-12
+
+
+@pytest.mark.parametrize("prec_tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_ball_paper_setting_L256_P256_N1(prec_tol):
+    """The ball at the setting of the paper's ball benchmark (Section 5.4, Table 2): N = 1,
+    P = L = 256, lambda = nu = 2, J0 = J0' = 0, one map.  Round trip, the scaling
+    coefficients' radial projection, and sampled (radial scale, angular scale, shell) blocks
+    against the oracle (its per-block functions on the seeded coefficients)."""
+    torch = _torch()
+    import paper_2402_01282_amd as s2w
+    prec, tol = prec_tol
+    print(f"[ball paper setting L=P=256 N=1 {prec}]", flush=True)
+    L, N, P = 256, 1, 256
+    BP = ball.BallPlan(L, N, P)
+    plan = s2w.BallPlan(L, N, P, batch=1, device=0,
+                        precision=s2w.S2W_MIXED if prec == "mixed" else s2w.S2W_FP64)
+    assert plan.Pk == BP.Pj and plan.Lk == BP.ang.Lj
+    flmp = S.ball_flmp(L, P, S.stream_key(13))
+    f = plan.sl_inverse(torch.from_numpy(flmp[None].copy()))
+    wav, scal = plan.analysis(f)
+    f2 = plan.synthesis(wav, scal)
+    e = (torch.linalg.norm(f2 - f) / torch.linalg.norm(f)).item()
+    print(f"  round trip rel err {e:.2e}", flush=True)
+    assert e < tol
+    views = plan.wav_views(wav)
+    nr, na = len(BP.rscales), len(BP.ang.scales)
+    for (i, k, s) in [(0, na - 1, 1), (3, na - 1, 5), (nr - 1, na - 1, 0), (nr - 1, na - 2, 200), (nr - 2, 3, 77),
+                      (5, 0, 31)]:
+        g = ball._shell_coeffs(flmp, BP, i)[s:s + 1]
+        ref = ball._angular_scale(g, BP, k, True)[0]
+        got = views[(i, k)][0, s].double().cpu().numpy()
+        e = _rel(got, ref)
+        print(f"  block (i={i}, k={k}) shell {s}: rel err {e:.2e}", flush=True)
+        assert e < tol

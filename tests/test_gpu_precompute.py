@@ -1,0 +1,59 @@
+"""Precompute mode (S2W_PLAN_PRECOMPUTE; Section 4.2, precomputed components): Wigner d
+tabulated in device memory for grids of band limit <= 512 and read by the FP64 vector
+contractions.  Against the oracle and against the recursion form of the same plan."""
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import mw, wavelets
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("prec,L,N,J0,B", [(0, 64, 4, 0, 1), (0, 200, 5, 1, 2), (0, 256, 4, 2, 1), (1, 130, 3, 0, 1),
+                                           (0, 600, 3, 0, 1)])
+def test_precompute_against_oracle(prec, L, N, J0, B):
+    torch = _torch()
+    import paper_2402_01282_amd as s2w
+    print(f"[precompute prec={prec} L={L} N={N} J0={J0} B={B}]", flush=True)
+    tol = 1e-12 if prec == 0 else 1e-6
+    pre = s2w.Plan(L, N, 2.0, J0, batch=B, precision=prec, device=0, flags=s2w.S2W_PLAN_PRECOMPUTE)
+    rec = s2w.Plan(L, N, 2.0, J0, batch=B, precision=prec, device=0)
+    P = wavelets.Plan(L, N, 2.0, J0)
+    flm = np.stack([S.sphere_flm(L, S.stream_key(14, b)) for b in range(B)])
+    f = np.stack([np.real(mw.sht_inverse(flm[b], L)) for b in range(B)])
+    ft = torch.from_numpy(f).cuda()
+    wp, sp = pre.analysis(ft)
+    wp, sp = wp.clone(), sp.clone()
+    wr, sr = rec.analysis(ft)
+    d = (torch.linalg.norm((wp - wr).double()) / torch.linalg.norm(wr.double())).item()
+    print(f"  precompute vs recursion rel diff {d:.1e}", flush=True)
+    assert d < (1e-13 if prec == 0 else 1e-6)
+    views = pre.wav_views(wp)
+    for b in sorted({0, B - 1}):
+        ow, os_ = wavelets.analysis_lm(flm[b], P)
+        es = [_rel(views[k][b].double().cpu().numpy(), w) for k, w in enumerate(ow)]
+        print(f"  map {b} per-scale rel err " + " ".join(f"{e:.1e}" for e in es), flush=True)
+        assert max(es) < tol
+        assert _rel(sp[b].cpu().numpy(), os_) < tol
+    f2 = pre.synthesis(wp, sp).cpu().numpy()
+    assert _rel(f2, f) < tol
+    # the transpose reads the same tables: dot test on random arrays
+    g = torch.from_numpy(np.random.default_rng(L).normal(size=pre.map_shape)).cuda()
+    yw = torch.from_numpy(np.random.default_rng(L + 1).normal(size=pre.wav_offset[-1])).to(pre.wav_dtype).cuda()
+    ys = torch.from_numpy(np.random.default_rng(L + 2).normal(size=pre.scal_shape)).cuda()
+    Aw, As = pre.analysis(g)
+    lhs = (torch.dot(Aw.double(), yw.double()) + torch.sum(As * ys)).item()
+    rhs = torch.sum(g * pre.analysis_adjoint(yw, ys)).item()
+    assert abs(lhs - rhs) < (1e-12 if prec == 0 else 3e-6) * abs(lhs)
