@@ -75,6 +75,9 @@ enum {
                                L_j - max(m, |n|) (Section 3.3: the top scales dominate).  With
                                S2W_PLAN_TUNE alone the autotuner chooses between this and one
                                launch per degree group by timing both. */
+    S2W_PLAN_WIGNER = 32,   /* recursion tables for every |n| < N (N <= 4) and buffers for the
+                               standalone SO(3) transforms (s2w_wigner_*; on ball plans, the
+                               Wigner-Laguerre transforms b3w_wl_*) */
     S2W_PLAN_PRECOMPUTE = 16 /* precompute mode (Section 4.2): for every grid of band limit <= 512,
                                Wigner d^l_mn(theta_b) is tabulated in device memory at plan
                                creation (all n of the plan, m < L, l >= max(m, |n|): about
@@ -148,6 +151,17 @@ s2w_status s2w_analysis_adjoint(s2w_plan plan, const void *gwav, const double *g
 s2w_status s2w_synthesis_adjoint(s2w_plan plan, const double *gf, void *gwav, double *gscal,
                                  void *stream);
 
+/* Wigner (SO(3)) transforms of real functions on the plan's MW grid (Section 2.2,
+ * eq:forward_wigner_transform and eq:inverse_wigner_transform) at band limits (L, N), FP64
+ * for either precision; the plan needs S2W_PLAN_WIGNER (N <= 4, else creation fails with
+ * S2W_EUNSUPPORTED), otherwise S2W_ESTATE.  Samples f [B][2N-1][L][2L-1] (gamma, beta, alpha);
+ * coefficients flmn complex interleaved [B][2N-1][L][2L-1] in the "nlm" layout of Algorithm 1
+ * (index n+N-1, l, m+L-1), zero where |m| > l or |n| > l.  Inputs to s2w_wigner_inverse must
+ * describe real functions (f^l_{-m,-n} = (-1)^(m+n) conj(f^l_mn)); only m >= 0 entries are read.
+ * The forward transform is exact on MW samples of band-limited functions. */
+s2w_status s2w_wigner_forward(s2w_plan plan, const double *f, double *flmn, void *stream);
+s2w_status s2w_wigner_inverse(s2w_plan plan, const double *flmn, double *f, void *stream);
+
 /* Spin-0 spherical-harmonic transforms on the plan's grid (Section 2.1,
  * eq:fswsh / eq:iswsh; the S^2 case of the Wigner transforms).  flm is complex
  * interleaved [B][L][2L-1].  Inputs to s2w_sht_inverse must describe real maps
@@ -204,7 +218,7 @@ s2w_status s2w_plan_profile_read(s2w_plan plan, int max, char *names, double *to
 typedef struct b3w_plan_s *b3w_plan;
 
 /* Create a ball plan: L >= 2, 1 <= N <= L, P >= 1, lambda > 1, nu > 1, 0 <= J0 <= J,
- * 0 <= J0p <= J', tau > 0, batch >= 1, flags 0 or S2W_PLAN_TUNE.  Errors: S2W_EINVAL,
+ * 0 <= J0p <= J', tau > 0, batch >= 1, flags from S2W_PLAN_TUNE, S2W_PLAN_WIGNER.  Errors: S2W_EINVAL,
  * S2W_EUNSUPPORTED (N > 8), S2W_ENOMEM, S2W_EHIP. */
 s2w_status b3w_plan_create(b3w_plan *out, int L, int N, int P, double lambda, double nu, int J0,
                            int J0p, double tau, int batch, s2w_precision precision, int device,
@@ -239,6 +253,15 @@ s2w_status b3w_synthesis_adjoint(b3w_plan plan, const double *gf, void *gwav, do
  * entries are read.  Device buffers, stream-ordered; errors as for s2w plans. */
 s2w_status b3w_sl_forward(b3w_plan plan, const double *f, double *flmp, void *stream);
 s2w_status b3w_sl_inverse(b3w_plan plan, const double *flmp, double *f, void *stream);
+
+/* Wigner-Laguerre transform of real functions on R+ x SO(3), the SO(3) analogue of the ball
+ * (Section 2.5: basis Q^l_mnp = K_p D^l_mn, its decomposition and synthesis eq:wiglag_inverse),
+ * FP64 for either precision; the ball plan needs S2W_PLAN_WIGNER (else S2W_ESTATE).  Samples f
+ * [B][P][2N-1][L][2L-1] on the radial nodes x the MW SO(3) grid; coefficients f^l_mnp complex
+ * interleaved [B][P][2N-1][L][2L-1], per p the layout of s2w_wigner_forward.  Inputs to
+ * b3w_wl_inverse must describe real functions; only m >= 0 entries are read. */
+s2w_status b3w_wl_forward(b3w_plan plan, const double *f, double *flmnp, void *stream);
+s2w_status b3w_wl_inverse(b3w_plan plan, const double *flmnp, double *f, void *stream);
 
 /* Kernel timing for ball transforms: as s2w_plan_profile / s2w_plan_profile_read. */
 s2w_status b3w_plan_profile(b3w_plan plan, int capacity);

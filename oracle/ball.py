@@ -286,3 +286,22 @@ def synthesis_adjoint(gf, BP: BallPlan):
                 out.append(np.real(mw.wigner_forward_adjoint(g_nlm, Lj, Nj)))
             gwav[(i, k)] = np.stack(out)
     return gwav, gscal
+
+
+# ------------------------------------------------------ Wigner-Laguerre -----
+
+def wl_forward(f: np.ndarray, BP: BallPlan, N: int) -> np.ndarray:
+    """Wigner-Laguerre transform (Section 2.5: basis Q^l_mnp = K_p D^l_mn, with the SO(3)
+    conventions of the sphere transforms, reading 17): samples f [P, 2N-1, L, 2L-1] on the
+    radial nodes x the MW SO(3) grid -> coefficients [P, 2N-1, L, 2L-1] ("nlm" per p).  The
+    SO(3) forward transform on every shell, then the radial forward (eq:flag on the rule)."""
+    per = np.stack([mw.wigner_forward(f[k], BP.L, N) for k in range(BP.P)])
+    return BP.rad.forward(per)
+
+
+def wl_inverse(fh: np.ndarray, BP: BallPlan, N: int, real: bool = True) -> np.ndarray:
+    """Inverse Wigner-Laguerre transform (eq:wiglag_inverse): radial synthesis at the nodes,
+    then the SO(3) inverse on every shell."""
+    per = BP.rad.inverse(fh)
+    out = np.stack([mw.wigner_inverse(per[k], BP.L, N) for k in range(BP.P)])
+    return np.real(out) if real else out

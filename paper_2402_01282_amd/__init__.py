@@ -25,6 +25,7 @@ S2W_PLAN_GRAPH = 2
 S2W_PLAN_NO_WORKSPACE = 4
 S2W_PLAN_PERSISTENT = 8
 S2W_PLAN_PRECOMPUTE = 16
+S2W_PLAN_WIGNER = 32
 S2W_SCRATCH_BYTES = 64 << 20
 
 _STATUS = {0: "S2W_OK", -1: "S2W_EINVAL", -2: "S2W_ENOMEM", -3: "S2W_EHIP",
@@ -56,6 +57,8 @@ def _load():
         "s2w_analysis_lm": [vp, vp, vp, vp, vp],
         "s2w_analysis_noalloc": [vp, vp, vp, vp, vp],
         "s2w_sht_forward": [vp, vp, vp, vp],
+        "s2w_wigner_forward": [vp, vp, vp, vp],
+        "s2w_wigner_inverse": [vp, vp, vp, vp],
         "s2w_sht_inverse": [vp, vp, vp, vp],
         "s2w_plan_profile": [vp, ctypes.c_int],
         "s2w_plan_profile_read": [vp, ctypes.c_int, ctypes.c_char_p, dp, i64p, dp, dp, dp, ip, i64p],
@@ -74,6 +77,8 @@ def _load():
         "b3w_analysis_adjoint": [vp, vp, vp, vp, vp],
         "b3w_synthesis_adjoint": [vp, vp, vp, vp, vp],
         "b3w_sl_forward": [vp, vp, vp, vp],
+        "b3w_wl_forward": [vp, vp, vp, vp],
+        "b3w_wl_inverse": [vp, vp, vp, vp],
         "b3w_sl_inverse": [vp, vp, vp, vp],
         "b3w_plan_profile": [vp, ctypes.c_int],
         "b3w_plan_profile_read": [vp, ctypes.c_int, ctypes.c_char_p, dp, i64p, dp, dp, dp, ip, i64p],
@@ -92,11 +97,12 @@ _lib = _load()
 # every symbol the header declares (checked by the tests)
 EXPORTS = ["s2w_plan_create", "s2w_plan_destroy", "s2w_plan_layout", "s2w_analysis", "s2w_synthesis",
            "s2w_analysis_lm", "s2w_analysis_noalloc", "s2w_analysis_adjoint", "s2w_synthesis_adjoint", "s2w_sht_forward", "s2w_sht_inverse",
+           "s2w_wigner_forward", "s2w_wigner_inverse",
            "s2w_plan_profile", "s2w_plan_profile_read",
            "s2w_last_error", "s2w_host_scales", "s2w_host_filters", "s2w_host_theta_matrix",
            "s2w_host_wigner_d", "s2w_host_laguerre_rule",
            "b3w_plan_create", "b3w_plan_destroy", "b3w_plan_layout", "b3w_analysis", "b3w_synthesis",
-           "b3w_analysis_adjoint", "b3w_synthesis_adjoint", "b3w_sl_forward", "b3w_sl_inverse", "b3w_plan_profile", "b3w_plan_profile_read"]
+           "b3w_analysis_adjoint", "b3w_synthesis_adjoint", "b3w_sl_forward", "b3w_sl_inverse", "b3w_wl_forward", "b3w_wl_inverse", "b3w_plan_profile", "b3w_plan_profile_read"]
 
 
 def lib():
@@ -327,6 +333,31 @@ class Plan:
         (algorithmic work as counted by the library, see include/s2w.h)."""
         return _profile_read(_lib.s2w_plan_profile_read, self._h)
 
+    @property
+    def so3_shape(self):
+        """Samples of a function on SO(3) at the plan's band limits: [B, 2N-1, L, 2L-1]."""
+        return (self.batch, 2 * self.N - 1, self.L, 2 * self.L - 1)
+
+    def wigner_forward(self, f):
+        """Wigner coefficients [B, 2N-1, L, 2L-1] (complex128, "nlm") of real SO(3) samples
+        (plan made with S2W_PLAN_WIGNER)."""
+        torch = self._torch
+        _require(f, "f", torch.float64, self.so3_shape, self.device)
+        out = torch.empty(self.so3_shape + (2,), dtype=torch.float64, device=self._dev())
+        _check(_lib.s2w_wigner_forward(self._h, self._p(f), self._p(out), _stream_ptr(torch, self.device)))
+        return torch.view_as_complex(out)
+
+    def wigner_inverse(self, flmn):
+        """Real SO(3) samples [B, 2N-1, L, 2L-1] from Wigner coefficients of a real function."""
+        torch = self._torch
+        if tuple(flmn.shape) != self.so3_shape or not flmn.is_complex():
+            raise ValueError(f"flmn: expected complex coefficients of shape {self.so3_shape}")
+        x = _require(torch.view_as_real(flmn.to(device=self._dev(), dtype=torch.complex128)).contiguous(),
+                     "flmn", torch.float64, self.so3_shape + (2,), self.device)
+        f = torch.empty(self.so3_shape, dtype=torch.float64, device=self._dev())
+        _check(_lib.s2w_wigner_inverse(self._h, self._p(x), self._p(f), _stream_ptr(torch, self.device)))
+        return f
+
     def sht_forward(self, f):
         torch = self._torch
         self._check_map(f)
@@ -491,6 +522,33 @@ class BallPlan:
         _require(x, "flmp", torch.float64, self.map_shape + (2,), self.device)
         f = torch.empty(self.map_shape, dtype=torch.float64, device=self._dev())
         _check(_lib.b3w_sl_inverse(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                                   _stream_ptr(torch, self.device)))
+        return f
+
+    @property
+    def wl_shape(self):
+        """Samples on the radial nodes x SO(3): [B, P, 2N-1, L, 2L-1]."""
+        return (self.batch, self.P, 2 * self.N - 1, self.L, 2 * self.L - 1)
+
+    def wl_forward(self, f):
+        """Wigner-Laguerre coefficients [B, P, 2N-1, L, 2L-1] (complex128) of real samples
+        (ball plan made with S2W_PLAN_WIGNER)."""
+        torch = self._torch
+        _require(f, "f", torch.float64, self.wl_shape, self.device)
+        out = torch.empty(self.wl_shape + (2,), dtype=torch.float64, device=self._dev())
+        _check(_lib.b3w_wl_forward(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                   _stream_ptr(torch, self.device)))
+        return torch.view_as_complex(out)
+
+    def wl_inverse(self, flmnp):
+        """Real samples on the radial nodes x SO(3) from Wigner-Laguerre coefficients."""
+        torch = self._torch
+        if tuple(flmnp.shape) != self.wl_shape or not flmnp.is_complex():
+            raise ValueError(f"flmnp: expected complex coefficients of shape {self.wl_shape}")
+        x = _require(torch.view_as_real(flmnp.to(device=self._dev(), dtype=torch.complex128)).contiguous(),
+                     "flmnp", torch.float64, self.wl_shape + (2,), self.device)
+        f = torch.empty(self.wl_shape, dtype=torch.float64, device=self._dev())
+        _check(_lib.b3w_wl_inverse(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(f.data_ptr()),
                                    _stream_ptr(torch, self.device)))
         return f
 

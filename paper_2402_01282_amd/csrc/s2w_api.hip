@@ -203,6 +203,10 @@ struct s2w_plan_s {
     // mixed plans, per grid band limit: contraction route, 1 = FP64 vector kernels with an
     // FP32 conversion at the boundary (fastest for very small batches), 0 = matrix cores
     std::map<int, int> route_lsum, route_tsum;
+    // standalone SO(3) (Wigner) transforms, S2W_PLAN_WIGNER: internal coefficients
+    // [B][2N-1][L][L], degree weights (2l+1)/(8 pi^2) and ones
+    bool wigner = false;
+    double *wint = nullptr, *w8pi = nullptr, *wone = nullptr;
     // precompute mode: per grid band limit (<= PRE_MAX_L), the d table and its row offsets
     std::map<int, std::pair<double *, int64_t *>> dtabs;
     // persistent l-contraction of the mixed analysis (one launch over the degree groups in
@@ -242,6 +246,7 @@ struct b3w_plan_s {
     std::vector<double *> G, H;              // per radial scale: [P_j'][P], [P][P_j']
     std::vector<double *> Gt, Ht;            // their transposes: [P][P_j'], [P_j'][P]
     double *flmp = nullptr, *shell = nullptr, *shell2 = nullptr;
+    double *wltmp = nullptr;                 // Wigner-Laguerre transforms: [B][P][2N-1][L][2L-1] complex
     std::vector<void *> allocs;
 };
 
@@ -1106,8 +1111,10 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
     *out = nullptr;
     if (batch < 1) return fail(S2W_EINVAL, "batch must be >= 1");
     if (flags & ~(unsigned)(S2W_PLAN_TUNE | S2W_PLAN_GRAPH | S2W_PLAN_NO_WORKSPACE | S2W_PLAN_PERSISTENT |
-                            S2W_PLAN_PRECOMPUTE))
+                            S2W_PLAN_PRECOMPUTE | S2W_PLAN_WIGNER))
         return fail(S2W_EINVAL, "unknown flags");
+    if ((flags & S2W_PLAN_WIGNER) && 2 * N - 1 > s2w::MAX_NN)
+        return fail(S2W_EUNSUPPORTED, "S2W_PLAN_WIGNER needs 2N - 1 <= 8 azimuthal orders (N <= 4)");
     if ((flags & S2W_PLAN_NO_WORKSPACE) && (flags & (S2W_PLAN_TUNE | S2W_PLAN_GRAPH)))
         return fail(S2W_EINVAL, "S2W_PLAN_NO_WORKSPACE excludes S2W_PLAN_TUNE and S2W_PLAN_GRAPH");
     if (precision != S2W_FP64 && precision != S2W_MIXED) return fail(S2W_EINVAL, "unknown precision");
@@ -1142,9 +1149,14 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
     for (int k = 0; k < K; ++k)
         p->wav_off[k + 1] = p->wav_off[k] + (int64_t)batch * (2 * S.s[k].N - 1) * S.s[k].L * (2 * S.s[k].L - 1);
 
-    // global n list: top scale's n values plus n = 0
+    // global n list: top scale's n values plus n = 0 (and, for the standalone SO(3)
+    // transforms, every |n| < N)
     p->nglob = S.s.back().n;
     if (std::find(p->nglob.begin(), p->nglob.end(), 0) == p->nglob.end()) p->nglob.push_back(0);
+    p->wigner = (flags & S2W_PLAN_WIGNER) != 0;
+    if (p->wigner)
+        for (int n = -(N - 1); n <= N - 1; ++n)
+            if (std::find(p->nglob.begin(), p->nglob.end(), n) == p->nglob.end()) p->nglob.push_back(n);
 
     // grids
     if (!make_grid(p, L) || !make_grid(p, p->Lphi)) return oom("grid tables");
@@ -1166,6 +1178,11 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
         for (int l = 0; l < L; ++l) ws[l] = sqrt((2.0 * l + 1.0) / (4.0 * M_PI));
         for (int l = 0; l < p->Lphi; ++l) wp[l] = p->F.phi[l];
         if (!upload(p, p->wsht, ws) || !upload(p, p->wphi, wp)) return oom("weights");
+        if (p->wigner) {
+            std::vector<double> w8(L), w1(L, 1.0);
+            for (int l = 0; l < L; ++l) w8[l] = (2.0 * l + 1.0) / (8.0 * M_PI * M_PI);
+            if (!upload(p, p->w8pi, w8) || !upload(p, p->wone, w1)) return oom("weights");
+        }
         p->wpsi.assign(K, nullptr);
         p->lmin.assign(K, 0);
         for (int k = 0; k < K; ++k) {
@@ -1215,6 +1232,7 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
         }
         p->ws.push_back({&p->Pphi, (size_t)batch * p->Lphi * p->Lphi * 2});
         for (auto &it : p->ws) p->ws_bytes += (it.second * sizeof(double) + 255) / 256 * 256;
+        if (p->wigner) p->ws.push_back({&p->wint, (size_t)batch * (2 * N - 1) * L * L * 2});
         p->no_ws = (flags & S2W_PLAN_NO_WORKSPACE) != 0;
         if (!p->no_ws)
             for (auto &it : p->ws)
@@ -1907,6 +1925,100 @@ s2w_status s2w_analysis_lm(s2w_plan p, const double *flm, void *wav_, double *sc
     return post_launch("s2w_analysis_lm");
 }
 
+// ---- standalone SO(3) transforms of real functions (S2W_PLAN_WIGNER) --------------------
+// Section 2.2, eq:inverse_wigner_transform and eq:forward_wigner_transform, at the plan's
+// band limits (L, N), FP64: the same stages as a wavelet scale with every |n| < N and the
+// degree weights (2l+1)/(8 pi^2) (inverse) or 1 (forward) in place of the filters.
+
+// internal coefficients wint [B][2N-1][m][l] -> samples f [B][2N-1][L][2L-1]
+static void wigner_inverse_internal(s2w_plan p, const double *cin, double *f, hipStream_t st)
+{
+    const DevGrid &g = p->grids[p->L];
+    const int L = p->L, N = p->N, B = p->B, ng = 2 * N - 1;
+    std::vector<int> nall;
+    for (int n = -(N - 1); n <= N - 1; ++n) nall.push_back(n);
+    LsumArgs la = lsum_args(p, g, L, nall);
+    la.flm = cin;
+    la.flm_m = ng * L;
+    la.flm_l = L;
+    la.flm_nstride = (long)L * L;
+    la.w[0] = p->w8pi;
+    la.wstride = 0;
+    la.out[0] = p->bufA;
+    { Prof pr_(p, "lsum", rec_work(L, L, nall, 1, B, [](int, int, int) { return 1.0; }), st); s2w::launch_lsum(la, 1, B, st); }
+    GammaArgs ga = gamma_args(p, L, L, L, L, nall, ng);
+    ga.src = p->bufA;
+    ga.dst = p->bufB;
+    { Prof pr_(p, "gamma_c2r", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_c2r(ga, st); }
+    const DftArgs da_ = dft_args(g, p->bufB, L, f, 2 * L - 1, B * ng * L, 1.0);
+    Prof pr_(p, "dft_c2r", dft_flop(da_.n, da_.nrows), st);
+    s2w::launch_dft_c2r(da_, st);
+}
+
+// samples f [B][2N-1][L][2L-1] -> coefficients, external "nlm" layout [B][2N-1][L][2L-1]
+// complex; the two parities of n run separately (the quadrature matrix depends on (-1)^(m+n))
+static void wigner_forward_internal(s2w_plan p, const double *f, double *ext, hipStream_t st)
+{
+    const DevGrid &g = p->grids[p->L];
+    const int L = p->L, N = p->N, B = p->B, ng = 2 * N - 1;
+    {
+        const DftArgs da_ = dft_args(g, f, 2 * L - 1, p->bufB, L, B * ng * L, 1.0);
+        Prof pr_(p, "dft_r2c", dft_flop(da_.n, da_.nrows), st);
+        s2w::launch_dft_r2c(da_, st);
+    }
+    double *Pout = p->P[p->S.s.size() - 1];
+    for (int q = 0; q < 2; ++q) {
+        std::vector<int> nq;
+        for (int n = -(N - 1); n <= N - 1; ++n)
+            if (((n % 2) + 2) % 2 == q) nq.push_back(n);
+        if (nq.empty()) continue;
+        GammaArgs ga = gamma_args(p, L, L, L, L, nq, ng);
+        ga.src = p->bufB;
+        ga.dst = p->bufA;
+        ga.sgn = -1.0;
+        ga.wscale = (2.0 * M_PI / (2 * L - 1)) * (2.0 * M_PI / ng);
+        ga.npar = q;
+        sig_counts(L, q, ga.M0, ga.M1);
+        { Prof pr_(p, "gamma_r2c", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_r2c(ga, st); }
+        theta_quadrature(p, g, p->bufA, p->bufC, L, (int)nq.size(), q, st);
+        TsumArgs ta = tsum_args(p, g, L, nq, q);
+        ta.h[0] = p->bufC;
+        ta.w[0] = p->wone;
+        ta.wstride = 0;
+        ta.out[0] = Pout;
+        { Prof pr_(p, "tsum", rec_work(L, L, nq, 1, B, [](int, int, int) { return 1.0; }), st); s2w::launch_tsum(ta, 1, B, st); }
+        { Prof pr_(p, "wig_layout", 0.0, st); s2w::launch_wig_sum_to_ext(Pout, ext, L, N, B, (int)nq.size(), nq.data(), st); }
+    }
+}
+
+static s2w_status check_wigner(s2w_plan p)
+{
+    if (!p->wigner) return fail(S2W_ESTATE, "plan created without S2W_PLAN_WIGNER");
+    return S2W_OK;
+}
+
+s2w_status s2w_wigner_forward(s2w_plan p, const double *f, double *flmn, void *stream)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (s2w_status st = check_ws(p)) return st;
+    if (s2w_status st = check_wigner(p)) return st;
+    if (!f || !flmn) return fail(S2W_EINVAL, "null buffer");
+    wigner_forward_internal(p, f, flmn, (hipStream_t)stream);
+    return post_launch("s2w_wigner_forward");
+}
+
+s2w_status s2w_wigner_inverse(s2w_plan p, const double *flmn, double *f, void *stream)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (s2w_status st = check_ws(p)) return st;
+    if (s2w_status st = check_wigner(p)) return st;
+    if (!f || !flmn) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    s2w::launch_wig_ext_to_int(flmn, p->wint, p->L, p->N, p->B, st);
+    wigner_inverse_internal(p, p->wint, f, st);
+    return post_launch("s2w_wigner_inverse");
+}
+
 s2w_status s2w_plan_profile(s2w_plan p, int capacity)
 {
     if (s2w_status st = check_plan(p)) return st;
@@ -2032,7 +2144,8 @@ s2w_status b3w_plan_create(b3w_plan *out, int L, int N, int P, double lambda, do
     if (!(nu > 1.0)) return fail(S2W_EINVAL, "nu must be > 1");
     if (!(tau > 0.0)) return fail(S2W_EINVAL, "tau must be > 0");
     if (batch < 1) return fail(S2W_EINVAL, "batch must be >= 1");
-    if (flags & ~(unsigned)S2W_PLAN_TUNE) return fail(S2W_EINVAL, "ball plans accept S2W_PLAN_TUNE only");
+    if (flags & ~(unsigned)(S2W_PLAN_TUNE | S2W_PLAN_WIGNER))
+        return fail(S2W_EINVAL, "ball plans accept S2W_PLAN_TUNE and S2W_PLAN_WIGNER only");
     int Jp = 0;
     while (std::pow(nu, (double)Jp) < (double)P) ++Jp;
     if (J0p < 0 || J0p > Jp) return fail(S2W_EINVAL, "J0p must satisfy 0 <= J0p <= J'");
@@ -2120,6 +2233,9 @@ s2w_status b3w_plan_create(b3w_plan *out, int L, int N, int P, double lambda, do
     const size_t per = (size_t)batch * P * L * L * 2;
     if (!ball_alloc(p, p->flmp, per) || !ball_alloc(p, p->shell, per) || !ball_alloc(p, p->shell2, per))
         return oom("workspace");
+    if ((flags & S2W_PLAN_WIGNER) &&
+        !ball_alloc(p, p->wltmp, (size_t)batch * P * (2 * N - 1) * L * (2 * L - 1) * 2))
+        return oom("workspace");
     if (hipDeviceSynchronize() != hipSuccess) {
         free_ball(p);
         delete p;
@@ -2158,11 +2274,11 @@ s2w_status b3w_plan_layout(b3w_plan p, int *nang, int *nrad, int *Lk, int *Nk, i
 }
 
 // Radial matrix A ([rows][kin]) applied to every map: out[b] = A in[b] (+ out[b] when acc),
-// rows of 2 L^2 doubles (internal harmonic layout).
+// rows of `row` doubles (default: 2 L^2, the internal harmonic layout).
 static void ball_radial(b3w_plan p, const double *A, const double *in, int kin, double *out, int rows, bool acc,
-                        hipStream_t st)
+                        hipStream_t st, size_t row = 0)
 {
-    const size_t row = (size_t)2 * p->L * p->L;
+    if (row == 0) row = (size_t)2 * p->L * p->L;
     for (int b = 0; b < p->B; ++b) {
         Prof pr_(p->sp, "gemm_radial", 2.0 * rows * kin * (double)row, st);
         s2w::launch_gemm(A, in + (size_t)b * kin * row, out + (size_t)b * rows * row, rows, (int)row, kin, st, acc);
@@ -2284,6 +2400,43 @@ s2w_status b3w_synthesis_adjoint(b3w_plan p, const double *gf, void *gwav, doubl
         sht_forward_T(sp, L, sp->wsht, p->shell, L, L, gscal, st);
     }
     return post_launch("b3w_synthesis_adjoint");
+}
+
+// Wigner-Laguerre transform of real functions on R+ x SO(3) (Section 2.5: Q^l_mnp = K_p D^l_mn,
+// the decomposition and its synthesis eq:wiglag_inverse): the SO(3) transform on every radial
+// node (B P at a time), then the radial forward f_p = sum_k W_k K_p(r_k) f(r_k) on the
+// coefficient rows (and the inverse in reverse order).  FP64.
+s2w_status b3w_wl_forward(b3w_plan p, const double *f, double *flmnp, void *stream)
+{
+    if (s2w_status st = check_ball(p)) return st;
+    if (!p->wltmp) return fail(S2W_ESTATE, "ball plan created without S2W_PLAN_WIGNER");
+    if (!f || !flmnp) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    s2w_plan sp = p->sp;
+    const int B = p->B, P = p->P, L = p->L, ng = 2 * p->N - 1;
+    {
+        BatchScope bs(sp, B * P);
+        wigner_forward_internal(sp, f, p->wltmp, st);
+        ball_radial(p, p->Zf, p->wltmp, P, flmnp, P, false, st, (size_t)ng * L * (2 * L - 1) * 2);
+    }
+    return post_launch("b3w_wl_forward");
+}
+
+s2w_status b3w_wl_inverse(b3w_plan p, const double *flmnp, double *f, void *stream)
+{
+    if (s2w_status st = check_ball(p)) return st;
+    if (!p->wltmp) return fail(S2W_ESTATE, "ball plan created without S2W_PLAN_WIGNER");
+    if (!f || !flmnp) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    s2w_plan sp = p->sp;
+    const int B = p->B, P = p->P, L = p->L, N = p->N, ng = 2 * N - 1;
+    {
+        BatchScope bs(sp, B * P);
+        ball_radial(p, p->Zi, flmnp, P, p->wltmp, P, false, st, (size_t)ng * L * (2 * L - 1) * 2);
+        s2w::launch_wig_ext_to_int(p->wltmp, sp->wint, L, N, B * P, st);
+        wigner_inverse_internal(sp, sp->wint, f, st);
+    }
+    return post_launch("b3w_wl_inverse");
 }
 
 // Z and Z^{-1}: per-shell spherical-harmonic transforms (B P shells at a time) and the

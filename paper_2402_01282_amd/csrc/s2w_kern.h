@@ -27,6 +27,8 @@ struct LsumArgs {
     int npol;
     const double *flm;           // [B][flm_m][flm_l] complex
     int flm_m, flm_l;
+    long flm_nstride;            // complex elements between the coefficient rows of consecutive n
+                                 // indices (0: one row per m shared by every n)
     const double *w[MAX_NS];     // weights [nn][wstride] (wstride 0: shared by all n)
     int wstride;
     double *out[MAX_NS];         // [B][nn][mcount][L] complex
@@ -166,5 +168,11 @@ void launch_pack_sigma_f32(const float *in, float *out, int B, int nn, int M, in
                            int M1, int dir, hipStream_t st);
 void launch_flm_to_ext(const double *in, double *out, int L, int B, hipStream_t st);
 void launch_flm_from_ext(const double *in, double *out, int L, int B, hipStream_t st);
+// SO(3) coefficient layouts: external "nlm" [B][2N-1][L][2L-1] complex (index n+N-1, l, m+L-1)
+// <-> internal [B][2N-1][m < L][l < L]; outputs of the theta sum [B][m][nq][l] for the n
+// values nval[0..nq) -> external, with the m < 0 entries from the real-function symmetry
+void launch_wig_ext_to_int(const double *ext, double *in, int L, int N, int B, hipStream_t st);
+void launch_wig_sum_to_ext(const double *P, double *ext, int L, int N, int B, int nq, const int *nval,
+                           hipStream_t st);
 
 }  // namespace s2w

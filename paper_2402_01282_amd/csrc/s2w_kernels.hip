@@ -92,7 +92,7 @@ __global__ __launch_bounds__(64) void k_lsum(const LsumArgs a)
                 A = a.A[tabm + l];
                 Bv = a.B[tabm + l];
                 const double S = PRE ? 1.0 : a.S[tabm + l];
-                const double *fl = a.flm + (((size_t)b * a.flm_m + m) * a.flm_l + l) * 2;
+                const double *fl = a.flm + (((size_t)b * a.flm_m + m) * a.flm_l + l + ni * a.flm_nstride) * 2;
                 const double fr = fl[0], fi = fl[1];
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(64) void k_lsum_polar(const LsumArgs a)
         for (int s = 0; s < NS; ++s) { acc[p][s][0] = 0.0; acc[p][s][1] = 0.0; }
     const double *tab = a.pol + ((size_t)ng * a.L + m) * P * a.L;
     for (int l = l0 + lane; l < a.L; l += 64) {
-        const double *fl = a.flm + (((size_t)b * a.flm_m + m) * a.flm_l + l) * 2;
+        const double *fl = a.flm + (((size_t)b * a.flm_m + m) * a.flm_l + l + ni * a.flm_nstride) * 2;
         const double fr = fl[0], fi = fl[1];
         double ur[NS], ui[NS];
 #pragma unroll
@@ -690,7 +690,7 @@ __global__ __launch_bounds__(64 * W) void k_lsum_mm64(const LsumArgs a, const do
             cb = (cg - cs * 2 * B) >> 1;
         }
         wv[r] = a.w[cs < NS ? cs : 0] + (size_t)ni * a.wstride;
-        fl[r] = reinterpret_cast<const double2 *>(a.flm) + ((size_t)cb * a.flm_m + m) * a.flm_l;
+        fl[r] = reinterpret_cast<const double2 *>(a.flm) + ((size_t)cb * a.flm_m + m) * a.flm_l + ni * a.flm_nstride;
     }
 
     typedef double d4 __attribute__((ext_vector_type(4)));
@@ -1618,6 +1618,63 @@ __global__ void k_flm_from_ext(const double *in, double *out, int L, int B)
         o[0] = re;
         o[1] = im;
     }
+}
+
+// ----------------------------------------------------------- SO(3) layouts ----
+// external "nlm" -> internal [b][n index][m >= 0][l] (the inverse transform reads m >= 0)
+__global__ void k_wig_ext_to_int(const double *ext, double *in, int L, int N)
+{
+    const int m = blockIdx.x, ni = blockIdx.y, b = blockIdx.z;
+    const int ng = 2 * N - 1;
+    for (int l = threadIdx.x; l < L; l += blockDim.x) {
+        const double *src = ext + ((((size_t)b * ng + ni) * L + l) * (2 * L - 1) + (m + L - 1)) * 2;
+        double *dst = in + ((((size_t)b * ng + ni) * L + m) * L + l) * 2;
+        dst[0] = src[0];
+        dst[1] = src[1];
+    }
+}
+
+// theta-sum outputs P[b][m][qi][l] (defined at l >= m; zero at m <= l < max(m, |n|)) of the
+// n values nval[qi] -> external "nlm": entry (n, l, m >= 0), and for m >= 1 the entry
+// (-n, l, -m) = (-1)^(m+n) conj(n, l, m) of a real function on SO(3); zero at l < max(|m|, |n|)
+struct WigNvals {
+    int v[8];
+};
+__global__ void k_wig_sum_to_ext(const double *P, double *ext, int L, int N, int nq, const WigNvals nv)
+{
+    const int m = blockIdx.x, qi = blockIdx.y, b = blockIdx.z;
+    const int n = nv.v[qi], an = n < 0 ? -n : n;
+    const int ng = 2 * N - 1, na = 2 * L - 1;
+    const double sg = ((m + n) & 1) ? -1.0 : 1.0;
+    for (int l = threadIdx.x; l < L; l += blockDim.x) {
+        double re = 0.0, im = 0.0;
+        if (l >= m && l >= an) {
+            const double *src = P + ((((size_t)b * L + m) * nq + qi) * L + l) * 2;
+            re = src[0];
+            im = src[1];
+        }
+        double *d = ext + ((((size_t)b * ng + (n + N - 1)) * L + l) * na + (m + L - 1)) * 2;
+        d[0] = re;
+        d[1] = im;
+        if (m >= 1) {
+            double *e = ext + ((((size_t)b * ng + (-n + N - 1)) * L + l) * na + (-m + L - 1)) * 2;
+            e[0] = sg * re;
+            e[1] = -sg * im;
+        }
+    }
+}
+
+void launch_wig_ext_to_int(const double *ext, double *in, int L, int N, int B, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_wig_ext_to_int, dim3(L, 2 * N - 1, B), dim3(256), 0, st, ext, in, L, N);
+}
+
+void launch_wig_sum_to_ext(const double *P, double *ext, int L, int N, int B, int nq, const int *nval,
+                           hipStream_t st)
+{
+    WigNvals nv{};
+    for (int i = 0; i < nq && i < 8; ++i) nv.v[i] = nval[i];
+    hipLaunchKernelGGL(k_wig_sum_to_ext, dim3(L, nq, B), dim3(256), 0, st, P, ext, L, N, nq, nv);
 }
 
 // ------------------------------------------------------------- launchers ---

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(64 * W, 2) void k_lsum_mm(const LsumArgs a, const M
             cb = (cg - cs * 2 * B) >> 1;
         }
         wv[r] = a.w[cs < NS ? cs : 0] + (size_t)ni * a.wstride;
-        fl[r] = reinterpret_cast<const double2 *>(a.flm) + ((size_t)cb * a.flm_m + m) * a.flm_l;
+        fl[r] = reinterpret_cast<const double2 *>(a.flm) + ((size_t)cb * a.flm_m + m) * a.flm_l + ni * a.flm_nstride;
     }
     double2 f0[R], f1[R];
     double w0[R], w1[R];
@@ -738,7 +738,7 @@ __device__ __forceinline__ void lsum_bf3_unit(const LsumArgs &a, const MixOut &o
             cb = (cg - cs * 2 * B) >> 1;
         }
         wv[r] = a.w[cs < NS ? cs : 0] + (size_t)ni * a.wstride;
-        fl[r] = reinterpret_cast<const double2 *>(a.flm) + ((size_t)cb * a.flm_m + m) * a.flm_l;
+        fl[r] = reinterpret_cast<const double2 *>(a.flm) + ((size_t)cb * a.flm_m + m) * a.flm_l + ni * a.flm_nstride;
     }
     double2 f0[R], f1[R];
     double w0[R], w1[R];

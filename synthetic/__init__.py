@@ -88,3 +88,35 @@ def ball_flmp(L: int, P: int, key: int) -> np.ndarray:
         out[p] = sphere_flm(L, (key * 1000003 + p + 1) & 0xFFFFFFFFFFFFFFFF,
                             spectrum=lambda l, p=p: 1.0 / ((l + 1.0) ** 2 * (p + 1.0) ** 2))
     return out
+
+
+def so3_flmn(L: int, N: int, key: int) -> np.ndarray:
+    """Wigner coefficients [2N-1, L, 2L-1] ("nlm": index n+N-1, l, m+L-1) of a real
+    band-limited Gaussian function on SO(3): complex Gaussian with variance 1/(l+1)^2 for
+    |m|, |n| <= l, with f^l_{-m,-n} = (-1)^(m+n) conj(f^l_mn) (so the function is real;
+    the (0, 0) coefficient real)."""
+    out = np.zeros((2 * N - 1, L, 2 * L - 1), dtype=np.complex128)
+    z = normals(key, 2 * (2 * N - 1) * L * (2 * L - 1))
+    k = 0
+    for l in range(L):
+        s = 1.0 / (l + 1.0)
+        for n in range(-min(N - 1, l), min(N - 1, l) + 1):
+            for m in range(-l, l + 1):
+                # one representative of each (m, n), (-m, -n) pair: n > 0, or n == 0 and m >= 0
+                if n < 0 or (n == 0 and m < 0):
+                    continue
+                if n == 0 and m == 0:
+                    v = s * z[k]
+                else:
+                    v = s * np.sqrt(0.5) * (z[k] + 1j * z[k + 1])
+                k += 2
+                out[n + N - 1, l, m + L - 1] = v
+                out[-n + N - 1, l, -m + L - 1] = (-1) ** ((m + n) % 2) * np.conj(v)
+    return out
+
+
+def wl_flmnp(L: int, N: int, P: int, key: int) -> np.ndarray:
+    """Wigner-Laguerre coefficients [P, 2N-1, L, 2L-1] of a real function on R+ x SO(3):
+    per p the SO(3) coefficients of so3_flmn, scaled by 1/(p+1)."""
+    return np.stack([so3_flmn(L, N, (key * 1000003 + p + 1) & 0xFFFFFFFFFFFFFFFF) / (p + 1.0)
+                     for p in range(P)])

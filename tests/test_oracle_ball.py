@@ -7,7 +7,7 @@ from scipy.integrate import quad
 from scipy.special import eval_genlaguerre, roots_genlaguerre
 
 import synthetic as S
-from oracle import ball, wavelets
+from oracle import ball, mw, wavelets
 
 
 def test_laguerre_functions_closed_forms():
@@ -125,3 +125,36 @@ def test_ball_adjoints_dot(L, N, P, J0, J0p, tau):
     lhs2 = np.sum(Sy * x)
     rhs2 = sum(np.sum(yw[k] * gw[k]) for k in yw) + np.sum(ys * gs)
     assert abs(lhs2 - rhs2) < 1e-11 * abs(lhs2)
+
+
+@pytest.mark.parametrize("L,N,P,tau", [(6, 3, 5, 1.0), (8, 1, 7, 0.8), (5, 4, 4, 1.2)])
+def test_wigner_laguerre_round_trip_and_separability(L, N, P, tau):
+    """Wigner-Laguerre transform: forward(inverse(c)) = c for band-limited real coefficients
+    (the SO(3) MW sampling and the Laguerre rule are exact), the synthesised samples are real,
+    and a separable function h(r) g(rho) has coefficients (radial coefficients of h) x (SO(3)
+    coefficients of g)."""
+    BP = ball.BallPlan(L, N, P, 2.0, 2.0, 0, 0, tau)
+    c = S.wl_flmnp(L, N, P, S.stream_key(15))
+    f = ball.wl_inverse(c, BP, N, real=False)
+    assert np.abs(f.imag).max() < 1e-13 * np.abs(f.real).max()
+    np.testing.assert_allclose(ball.wl_forward(f.real, BP, N), c, atol=1e-12 * np.abs(c).max())
+    # separable input
+    hp = S.normals(S.stream_key(16), P)                       # radial coefficients
+    h = BP.rad.inverse(hp)                                    # h(r_k)
+    g = S.so3_flmn(L, N, S.stream_key(17))
+    gs = np.real(mw.wigner_inverse(g, L, N))
+    sep = h[:, None, None, None] * gs[None]
+    ref = hp[:, None, None, None] * g[None]
+    np.testing.assert_allclose(ball.wl_forward(sep, BP, N), ref, atol=1e-12 * np.abs(ref).max())
+
+
+def test_so3_generator_is_real_and_band_limited():
+    L, N = 6, 3
+    c = S.so3_flmn(L, N, S.stream_key(18))
+    f = mw.wigner_inverse(c, L, N)
+    assert np.abs(f.imag).max() < 1e-14 * np.abs(f.real).max()
+    for i, n in enumerate(range(-(N - 1), N)):
+        for l in range(L):
+            for j, m in enumerate(range(-(L - 1), L)):
+                if abs(m) > l or abs(n) > l:
+                    assert c[i, l, j] == 0
