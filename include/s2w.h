@@ -28,8 +28,17 @@
  * work on `stream` (a hipStream_t, or NULL for the default stream).  Argument
  * errors are reported synchronously; device faults surface as S2W_EHIP at a later
  * call.  Calls never abort: failures return a negative status and set a
- * thread-local message readable with s2w_last_error().  A plan may be used by one
- * stream at a time (its workspace is shared by all calls on the plan).
+ * thread-local message readable with s2w_last_error().
+ *
+ * Streams: the calls on one plan share its workspace, so the library orders them: a call
+ * on a stream other than the previous call's waits (on the device) for that call to end.
+ * Calls on one stream run in order anyway.  A stream under graph capture is left alone;
+ * the capturing program orders the captured work.  A plan is used from one host thread
+ * at a time.
+ *
+ * Allocation failure can be injected for tests of the error paths: with the environment
+ * variable S2W_FAIL_ALLOC_AT=k, the k-th device allocation (counting from 1) of each plan
+ * creation fails, and the creation returns S2W_ENOMEM having freed what it allocated.
  */
 #ifndef S2W_H
 #define S2W_H

@@ -27,6 +27,7 @@ S2W_PLAN_PERSISTENT = 8
 S2W_PLAN_PRECOMPUTE = 16
 S2W_PLAN_WIGNER = 32
 S2W_SCRATCH_BYTES = 64 << 20
+S2W_OK, S2W_EINVAL, S2W_ENOMEM, S2W_EHIP, S2W_EUNSUPPORTED, S2W_ESTATE = 0, -1, -2, -3, -4, -5
 
 _STATUS = {0: "S2W_OK", -1: "S2W_EINVAL", -2: "S2W_ENOMEM", -3: "S2W_EHIP",
            -4: "S2W_EUNSUPPORTED", -5: "S2W_ESTATE"}

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -58,6 +59,33 @@ bool reg_remove(const void *h)
 {
     std::lock_guard<std::mutex> lk(g_reg_mu);
     return g_live.erase(h) != 0;
+}
+
+// Injected allocation failure, for tests of the error paths: with S2W_FAIL_ALLOC_AT=k in
+// the environment, the k-th device allocation (counting from 1) of a plan creation fails
+// as if the device were out of memory.  Counted per creating thread; the sphere plan a
+// ball plan creates counts in the ball plan's sequence.
+thread_local int g_alloc_depth = 0, g_alloc_seq = 0, g_alloc_fail_at = 0;
+
+struct AllocSeq {
+    AllocSeq()
+    {
+        if (g_alloc_depth++ == 0) {
+            g_alloc_seq = 0;
+            const char *e = std::getenv("S2W_FAIL_ALLOC_AT");
+            g_alloc_fail_at = e ? std::atoi(e) : 0;
+        }
+    }
+    ~AllocSeq() { --g_alloc_depth; }
+};
+
+hipError_t dev_malloc(void **v, size_t bytes)
+{
+    ++g_alloc_seq;
+    if (g_alloc_fail_at > 0 && g_alloc_seq == g_alloc_fail_at) return hipErrorOutOfMemory;
+    const hipError_t e = hipMalloc(v, bytes);
+    if (e != hipSuccess) (void)hipGetLastError();   // reported as S2W_ENOMEM, not left for a later call
+    return e;
 }
 
 // device address of the static scratch per device (resolved at plan creation)
@@ -223,6 +251,10 @@ struct s2w_plan_s {
     // graph replay (S2W_PLAN_GRAPH)
     bool graph = false, capturing = false;
     hipStream_t cap_stream = nullptr;
+    // ordering of calls across streams: recorded at the end of every call
+    hipEvent_t order_ev = nullptr;
+    hipStream_t order_stream = nullptr;
+    bool order_used = false;
     struct GraphEntry {
         int kind;
         const void *a, *b, *c;
@@ -264,6 +296,35 @@ using s2w::TsumArgs;
 // for a cheaper algorithm (dense: the theta-quadrature matrix product; 0 elsewhere).
 struct Work {
     double flop = 0.0, flop64 = 0.0, dense = 0.0;
+};
+
+// Orders the calls on one plan across streams.  The calls of a plan share its workspace,
+// so a call on a stream other than the previous call's first waits for the end of that
+// call (an event recorded at the end of every call).  Skipped on a stream under graph
+// capture, where the capturing program orders the work.
+struct StreamOrder {
+    s2w_plan p;
+    hipStream_t st;
+    bool on = false;
+    StreamOrder(s2w_plan p_, hipStream_t st_) : p(p_), st(st_)
+    {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+            (void)hipGetLastError();
+            return;
+        }
+        if (cs != hipStreamCaptureStatusNone) return;
+        on = true;
+        if (p->order_used && p->order_stream != st) (void)hipStreamWaitEvent(st, p->order_ev, 0);
+    }
+    ~StreamOrder()
+    {
+        if (!on) return;
+        if (hipEventRecord(p->order_ev, st) == hipSuccess) {
+            p->order_stream = st;
+            p->order_used = true;
+        }
+    }
 };
 
 // One HIP event pair around a kernel launch when profiling is on.
@@ -355,7 +416,7 @@ bool dalloc(s2w_plan p, Tp *&ptr, size_t count)
 {
     void *v = nullptr;
     if (count == 0) count = 1;
-    if (hipMalloc(&v, count * sizeof(Tp)) != hipSuccess) return false;
+    if (dev_malloc(&v, count * sizeof(Tp)) != hipSuccess) return false;
     p->allocs.push_back(v);
     ptr = (Tp *)v;
     return true;
@@ -909,7 +970,11 @@ void autotune(s2w_plan p)
     (void)hipMemset(p->bufA, 0, sizeof(double) * p->szA);
     (void)hipMemset(p->bufC, 0, sizeof(double) * p->szC);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipGetLastError();
+        if (e0) (void)hipEventDestroy(e0);
+        return;
+    }
     // best of the candidates (each launched once untimed, then twice timed); 0 if none ran
     auto pick = [&](const std::vector<int> &cands, const std::function<void(int)> &launch) {
         int best = 0;
@@ -1107,6 +1172,7 @@ s2w_status s2w_host_wigner_d(int L, int m, int n, double *out)
 s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, int batch,
                            s2w_precision precision, int device, unsigned flags)
 {
+    AllocSeq alloc_seq;
     if (!out) return fail(S2W_EINVAL, "null output pointer");
     *out = nullptr;
     if (batch < 1) return fail(S2W_EINVAL, "batch must be >= 1");
@@ -1231,8 +1297,8 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
             p->ws.push_back({&p->P[k], (size_t)batch * Lk * nn * Lk * 2});
         }
         p->ws.push_back({&p->Pphi, (size_t)batch * p->Lphi * p->Lphi * 2});
-        for (auto &it : p->ws) p->ws_bytes += (it.second * sizeof(double) + 255) / 256 * 256;
         if (p->wigner) p->ws.push_back({&p->wint, (size_t)batch * (2 * N - 1) * L * L * 2});
+        for (auto &it : p->ws) p->ws_bytes += (it.second * sizeof(double) + 255) / 256 * 256;
         p->no_ws = (flags & S2W_PLAN_NO_WORKSPACE) != 0;
         if (!p->no_ws)
             for (auto &it : p->ws)
@@ -1245,7 +1311,14 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
     }
     if (flags & S2W_PLAN_TUNE) autotune(p);
     p->graph = (flags & S2W_PLAN_GRAPH) != 0;
+    if (hipEventCreateWithFlags(&p->order_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        free_plan(p);
+        delete p;
+        return fail(S2W_EHIP, "event creation failed during plan creation");
+    }
     if (hipDeviceSynchronize() != hipSuccess) {
+        (void)hipEventDestroy(p->order_ev);
         free_plan(p);
         delete p;
         return fail(S2W_EHIP, "device synchronisation failed during plan creation");
@@ -1265,6 +1338,7 @@ s2w_status s2w_plan_destroy(s2w_plan p)
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     for (auto e : p->ev0) (void)hipEventDestroy(e);
     for (auto e : p->ev1) (void)hipEventDestroy(e);
+    if (p->order_ev) (void)hipEventDestroy(p->order_ev);
     free_plan(p);
     delete p;
     return S2W_OK;
@@ -1292,6 +1366,7 @@ s2w_status s2w_sht_forward(s2w_plan p, const double *f, double *flm, void *strea
     if (s2w_status st = check_ws(p)) return st;
     if (!f || !flm) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p, st);
     sht_forward_internal(p, f, p->flm, st);
     s2w::launch_flm_to_ext(p->flm, flm, p->L, p->B, st);
     return post_launch("s2w_sht_forward");
@@ -1303,6 +1378,7 @@ s2w_status s2w_sht_inverse(s2w_plan p, const double *flm, double *f, void *strea
     if (s2w_status st = check_ws(p)) return st;
     if (!f || !flm) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p, st);
     s2w::launch_flm_from_ext(flm, p->flm, p->L, p->B, st);
     sht_inverse_internal(p, p->flm, f, st);
     return post_launch("s2w_sht_inverse");
@@ -1437,6 +1513,7 @@ s2w_status s2w_analysis(s2w_plan p, const double *f, void *wav_, double *scal, v
     if (s2w_status st = check_ws(p)) return st;
     if (!f || !wav_ || !scal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p, st);
     // the forward SHT of the input map runs in FP64 in both forms: it is shared by every
     // scale, and FP32 rounding here would spread as white noise across all degrees
     if (p->graph && !p->capturing)
@@ -1481,6 +1558,7 @@ s2w_status s2w_analysis_noalloc(s2w_plan p, const double *f, void *wav_, double 
     unsigned char *base = scratch_ptr(p->device);
     if (!base) return fail(S2W_ESTATE, "the device scratch address was not resolved at plan creation");
     hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p, st);
     ScratchScope sc(p, base);
     sht_forward_internal(p, f, p->flm, st);
     analysis_from_flm(p, p->flm, wav_, scal, st);
@@ -1620,6 +1698,7 @@ s2w_status s2w_synthesis(s2w_plan p, const void *wav_, const double *scal, doubl
     if (s2w_status st = check_ws(p)) return st;
     if (!f || !wav_ || !scal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p, st);
     if (p->graph && !p->capturing)
         return run_graph(p, 1, wav_, scal, f, st, [&](hipStream_t cs) {
             synthesis_to_fhat(p, wav_, scal, p->fhat, cs);
@@ -1893,6 +1972,7 @@ s2w_status s2w_analysis_adjoint(s2w_plan p, const void *gwav_, const double *gsc
     if (s2w_status st = check_ws(p)) return st;
     if (!gf || !gwav_ || !gscal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p, st);
     analysis_from_flm_T(p, gwav_, gscal, p->fhat, st);
     sht_forward_T(p, p->L, p->wsht, p->fhat, p->L, p->L, gf, st);
     return post_launch("s2w_analysis_adjoint");
@@ -1904,6 +1984,7 @@ s2w_status s2w_synthesis_adjoint(s2w_plan p, const double *gf, void *gwav_, doub
     if (s2w_status st = check_ws(p)) return st;
     if (!gf || !gwav_ || !gscal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p, st);
     sht_inverse_T(p, p->L, p->wsht, gf, p->fhat, st);
     synthesis_to_fhat_T(p, p->fhat, gwav_, gscal, st);
     return post_launch("s2w_synthesis_adjoint");
@@ -1915,6 +1996,7 @@ s2w_status s2w_analysis_lm(s2w_plan p, const double *flm, void *wav_, double *sc
     if (s2w_status st = check_ws(p)) return st;
     if (!flm || !wav_ || !scal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p, st);
     if (p->graph && !p->capturing)
         return run_graph(p, 2, flm, wav_, scal, st, [&](hipStream_t cs) {
             s2w::launch_flm_from_ext(flm, p->flm, p->L, p->B, cs);
@@ -2003,7 +2085,9 @@ s2w_status s2w_wigner_forward(s2w_plan p, const double *f, double *flmn, void *s
     if (s2w_status st = check_ws(p)) return st;
     if (s2w_status st = check_wigner(p)) return st;
     if (!f || !flmn) return fail(S2W_EINVAL, "null buffer");
-    wigner_forward_internal(p, f, flmn, (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p, st);
+    wigner_forward_internal(p, f, flmn, st);
     return post_launch("s2w_wigner_forward");
 }
 
@@ -2014,6 +2098,7 @@ s2w_status s2w_wigner_inverse(s2w_plan p, const double *flmn, double *f, void *s
     if (s2w_status st = check_wigner(p)) return st;
     if (!f || !flmn) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p, st);
     s2w::launch_wig_ext_to_int(flmn, p->wint, p->L, p->N, p->B, st);
     wigner_inverse_internal(p, p->wint, f, st);
     return post_launch("s2w_wigner_inverse");
@@ -2111,7 +2196,7 @@ static void free_ball(b3w_plan p)
 static bool ball_upload(b3w_plan p, double *&ptr, const std::vector<double> &h)
 {
     void *v = nullptr;
-    if (hipMalloc(&v, std::max<size_t>(h.size(), 1) * sizeof(double)) != hipSuccess) return false;
+    if (dev_malloc(&v, std::max<size_t>(h.size(), 1) * sizeof(double)) != hipSuccess) return false;
     p->allocs.push_back(v);
     ptr = (double *)v;
     return hipMemcpy(ptr, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
@@ -2129,7 +2214,7 @@ static std::vector<double> transpose(const std::vector<double> &a, int r, int c)
 static bool ball_alloc(b3w_plan p, double *&ptr, size_t count)
 {
     void *v = nullptr;
-    if (hipMalloc(&v, std::max<size_t>(count, 1) * sizeof(double)) != hipSuccess) return false;
+    if (dev_malloc(&v, std::max<size_t>(count, 1) * sizeof(double)) != hipSuccess) return false;
     p->allocs.push_back(v);
     ptr = (double *)v;
     return true;
@@ -2138,6 +2223,7 @@ static bool ball_alloc(b3w_plan p, double *&ptr, size_t count)
 s2w_status b3w_plan_create(b3w_plan *out, int L, int N, int P, double lambda, double nu, int J0, int J0p,
                            double tau, int batch, s2w_precision precision, int device, unsigned flags)
 {
+    AllocSeq alloc_seq;
     if (!out) return fail(S2W_EINVAL, "null output pointer");
     *out = nullptr;
     if (P < 1) return fail(S2W_EINVAL, "P must be >= 1");
@@ -2290,6 +2376,7 @@ s2w_status b3w_analysis(b3w_plan p, const double *f, void *wav, double *scal, vo
     if (s2w_status st = check_ball(p)) return st;
     if (!f || !wav || !scal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p->sp, st);
     s2w_plan sp = p->sp;
     const int B = p->B, P = p->P, L = p->L;
     const size_t esz = p->prec == S2W_MIXED ? sizeof(float) : sizeof(double);
@@ -2315,6 +2402,7 @@ s2w_status b3w_synthesis(b3w_plan p, const void *wav, const double *scal, double
     if (s2w_status st = check_ball(p)) return st;
     if (!f || !wav || !scal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p->sp, st);
     s2w_plan sp = p->sp;
     const int B = p->B, P = p->P, L = p->L;
     const size_t esz = p->prec == S2W_MIXED ? sizeof(float) : sizeof(double);
@@ -2347,6 +2435,7 @@ s2w_status b3w_analysis_adjoint(b3w_plan p, const void *gwav, const double *gsca
     if (s2w_status st = check_ball(p)) return st;
     if (!gf || !gwav || !gscal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p->sp, st);
     s2w_plan sp = p->sp;
     const int B = p->B, P = p->P, L = p->L;
     const size_t esz = p->prec == S2W_MIXED ? sizeof(float) : sizeof(double);
@@ -2379,6 +2468,7 @@ s2w_status b3w_synthesis_adjoint(b3w_plan p, const double *gf, void *gwav, doubl
     if (s2w_status st = check_ball(p)) return st;
     if (!gf || !gwav || !gscal) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p->sp, st);
     s2w_plan sp = p->sp;
     const int B = p->B, P = p->P, L = p->L;
     const size_t esz = p->prec == S2W_MIXED ? sizeof(float) : sizeof(double);
@@ -2412,6 +2502,7 @@ s2w_status b3w_wl_forward(b3w_plan p, const double *f, double *flmnp, void *stre
     if (!p->wltmp) return fail(S2W_ESTATE, "ball plan created without S2W_PLAN_WIGNER");
     if (!f || !flmnp) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p->sp, st);
     s2w_plan sp = p->sp;
     const int B = p->B, P = p->P, L = p->L, ng = 2 * p->N - 1;
     {
@@ -2428,6 +2519,7 @@ s2w_status b3w_wl_inverse(b3w_plan p, const double *flmnp, double *f, void *stre
     if (!p->wltmp) return fail(S2W_ESTATE, "ball plan created without S2W_PLAN_WIGNER");
     if (!f || !flmnp) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p->sp, st);
     s2w_plan sp = p->sp;
     const int B = p->B, P = p->P, L = p->L, N = p->N, ng = 2 * N - 1;
     {
@@ -2446,6 +2538,7 @@ s2w_status b3w_sl_forward(b3w_plan p, const double *f, double *flmp, void *strea
     if (s2w_status st = check_ball(p)) return st;
     if (!f || !flmp) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p->sp, st);
     s2w_plan sp = p->sp;
     const int B = p->B, P = p->P, L = p->L;
     {
@@ -2462,6 +2555,7 @@ s2w_status b3w_sl_inverse(b3w_plan p, const double *flmp, double *f, void *strea
     if (s2w_status st = check_ball(p)) return st;
     if (!f || !flmp) return fail(S2W_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p->sp, st);
     s2w_plan sp = p->sp;
     const int B = p->B, P = p->P, L = p->L;
     {
