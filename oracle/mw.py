@@ -262,6 +262,40 @@ def sht_inverse(flm: np.ndarray, L: int) -> np.ndarray:
     return _ifft(X, 1) * na
 
 
+# ------------------------------------------------------------ spin-s ------
+# Spin-weighted harmonics (Section 2.1, eq:u1sym to eq:iswsh) in the convention
+#   sY_lm(t, p) = (-1)^s sqrt((2l+1)/(4 pi)) D^{l*}_{m,-s}(p, t, 0)
+#               = (-1)^s sqrt((2l+1)/(4 pi)) d^l_{m,-s}(t) e^{i m p},
+# which is Y_lm at s = 0 and gives 1Y_10 = sqrt(3/(8 pi)) sin t.  The spin-s
+# transforms are the spin-0 ones with the d column n = -s in place of n = 0; the
+# theta extension of the n = -s integrand has the parity (-1)^{m+s}.
+
+def spin_sht_forward(f: np.ndarray, L: int, s: int) -> np.ndarray:
+    """Forward spin-s SHT (Section 2.1, eq:fswsh) on MW samples of a complex spin-s
+    map f [L, 2L-1] -> sflm [L, 2L-1] (index m+L-1; zero for l < |s|)."""
+    ms = mrange(L)
+    na = 2 * L - 1
+    X = _fft(np.asarray(f, dtype=np.complex128), 1) * (2 * np.pi / na)   # [b, k]
+    F = X[:, ms % na].T                                                   # [m, b]
+    G = mw_quadrature_G(F, L, (-1.0) ** (ms + s))
+    raw = _project(L, ms, np.array([-s]), G[:, None, :])[:, :, 0]         # [l, m]
+    ls = np.arange(L)
+    return (-1.0) ** s * np.sqrt((2 * ls + 1) / (4 * np.pi))[:, None] * _ipow(-s - ms)[None, :] * raw
+
+
+def spin_sht_inverse(flm: np.ndarray, L: int, s: int) -> np.ndarray:
+    """Inverse spin-s SHT (Section 2.1, eq:iswsh): sflm [L, 2L-1] -> complex map [L, 2L-1]."""
+    ms = mrange(L)
+    ls = np.arange(L)
+    a = ((-1.0) ** s * np.sqrt((2 * ls + 1) / (4 * np.pi))[:, None] * flm)[:, :, None]   # [l, m, 1]
+    G = _fourier(L, ms, np.array([-s]), a)[:, 0, :] * _ipow(-s - ms)[:, None]
+    C = eval_fourier(G, L)                                                # [m, b]
+    na = 2 * L - 1
+    X = np.zeros((L, na), dtype=np.complex128)
+    X[:, ms % na] = C.T
+    return _ifft(X, 1) * na
+
+
 # ------------------------------------------------------------- adjoints ----
 # Literal (Hermitian) transposes of the discrete maps above, for real inner
 # products <x, y> = Re sum conj(x) y.

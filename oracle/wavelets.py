@@ -141,3 +141,21 @@ def synthesis_adjoint(gf, P: Plan):
         g_nlm = np.conj(psi).T[:, :, None] * gk[None, :, :]        # transpose of the sum over n
         gwav.append(np.real(mw.wigner_forward_adjoint(g_nlm, Lj, Nj)))
     return gwav, gscal
+
+
+# ------------------------------------------------------------ spin-s ------
+# Spin-s maps (Section 4.1 with the spin subscripts kept, Section 2.1 eq:u1sym):
+# the wavelet and scaling coefficients depend on the map only through its spin-s
+# harmonic coefficients sf_lm (eq:wigner_wav_coeffs, eq:harmonic_scal_coeffs), with the
+# same filters as for spin 0 (Appendix A: the dictionary's harmonic coefficients carry no
+# spin-dependent factor).  The wavelet coefficients live on SO(3) and the scaling
+# coefficients are a spin-0 map; both are complex.
+
+def analysis_spin(f: np.ndarray, P: Plan, s: int):
+    """Complex spin-s map f [L, 2L-1] -> (complex W^j, complex W^Phi)."""
+    return analysis_lm(mw.spin_sht_forward(f, P.L, s), P, real=False)
+
+
+def synthesis_spin(wav, scal, P: Plan, s: int) -> np.ndarray:
+    """(complex W^j, complex W^Phi) -> complex spin-s map f [L, 2L-1]."""
+    return mw.spin_sht_inverse(synthesis_lm(wav, scal, P), P.L, s)

@@ -80,6 +80,24 @@ def sphere_flm(L: int, key: int, spectrum=None) -> np.ndarray:
     return flm
 
 
+def spin_flm(L: int, s: int, key: int, spectrum=None) -> np.ndarray:
+    """Harmonic coefficients of a complex band-limited spin-s Gaussian field on S^2:
+    [L, 2L-1] ("lm" layout, index m + L - 1), every (l, m) with l >= max(|s|, |m|)
+    independent complex normal with variance spectrum(l) (default 1/(l+1)^2), zero
+    elsewhere."""
+    if spectrum is None:
+        spectrum = lambda l: 1.0 / (l + 1.0) ** 2  # noqa: E731
+    flm = np.zeros((L, 2 * L - 1), dtype=np.complex128)
+    z = normals(key, 2 * L * (2 * L - 1))
+    k = 0
+    for l in range(abs(s), L):
+        c = np.sqrt(spectrum(l) / 2.0)
+        for m in range(-l, l + 1):
+            flm[l, L - 1 + m] = c * (z[k] + 1j * z[k + 1])
+            k += 2
+    return flm
+
+
 def ball_flmp(L: int, P: int, key: int) -> np.ndarray:
     """Spherical-Laguerre coefficients [P, L, 2L-1] of a real Gaussian field
     on the ball with E|f_lmp|^2 = 1/((l+1)^2 (p+1)^2)."""
