@@ -178,6 +178,34 @@ s2w_status s2w_wigner_inverse(s2w_plan plan, const double *flmn, double *f, void
 s2w_status s2w_sht_forward(s2w_plan plan, const double *f, double *flm, void *stream);
 s2w_status s2w_sht_inverse(s2w_plan plan, const double *flm, double *f, void *stream);
 
+/* Complex spin-s maps (Section 2.1, eq:u1sym to eq:iswsh; Section 4.1 with the spin kept:
+ * eq:wigner_wav_coeffs, eq:harmonic_scal_coeffs, eq:s2_cont_synthesis).  Spin-weighted
+ * harmonics in the convention sY_lm = (-1)^s sqrt((2l+1)/(4 pi)) e^{i m phi} d^l_{m,-s}(theta)
+ * (Y_lm at s = 0; 1Y_10 = sqrt(3/(8 pi)) sin theta).  The filters are those of spin 0 (the
+ * dictionary's harmonic coefficients carry no spin factor, Appendix A).
+ *
+ * s2w_plan_create_spin makes a plan for `batch` complex spin-`spin` maps (|spin| < L; spin 0
+ * gives complex scalar maps); other arguments as for s2w_plan_create, flags limited to
+ * S2W_PLAN_TUNE, S2W_PLAN_PERSISTENT and S2W_PLAN_PRECOMPUTE.  Such a plan runs only the
+ * s2w_spin_* calls (the real-map calls return S2W_ESTATE on it, and the s2w_spin_* calls on
+ * a real-map plan).  Layouts, B = batch:
+ *   f    planar complex [B][2][L][2L-1]: real part, then imaginary part of each map;
+ *   flm  complex interleaved [B][L][2L-1] (index m+L-1), zero for l < max(|m|, |spin|);
+ *   wav  the packed layout that s2w_plan_layout reports for the plan (2B real maps per
+ *        scale): map 2b holds Re W^j, map 2b+1 holds Im W^j of input b;
+ *   scal [B][2][L_phi][2L_phi-1]: Re and Im of the (spin-0) scaling map.
+ * The wavelet coefficients are linear in the spin-s coefficients g_lm, so with g = A + i B
+ * for real maps A and B they are W(A) + i W(B): the plan computes the real transforms of A
+ * and B (the same precision split as a real plan) and the spin-s harmonic transforms in
+ * FP64.  s2w_spin_synthesis reconstructs f exactly (to rounding) from the coefficients of
+ * s2w_spin_analysis for maps band-limited at L.  Device buffers, stream-ordered. */
+s2w_status s2w_plan_create_spin(s2w_plan *out, int L, int N, double lambda, int J0, int spin, int batch,
+                                s2w_precision precision, int device, unsigned flags);
+s2w_status s2w_spin_sht_forward(s2w_plan plan, const double *f, double *flm, void *stream);
+s2w_status s2w_spin_sht_inverse(s2w_plan plan, const double *flm, double *f, void *stream);
+s2w_status s2w_spin_analysis(s2w_plan plan, const double *f, void *wav, double *scal, void *stream);
+s2w_status s2w_spin_synthesis(s2w_plan plan, const void *wav, const double *scal, double *f, void *stream);
+
 /* Kernel timing (for measurement).  s2w_plan_profile(plan, capacity) with capacity > 0
  * creates `capacity` pairs of HIP events and from then on records one pair around
  * every kernel launch of the transform entry points, on the stream of the call, together

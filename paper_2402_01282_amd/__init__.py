@@ -49,6 +49,12 @@ def _load():
     sigs = {
         "s2w_plan_create": [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint],
+        "s2w_plan_create_spin": [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint],
+        "s2w_spin_sht_forward": [vp, vp, vp, vp],
+        "s2w_spin_sht_inverse": [vp, vp, vp, vp],
+        "s2w_spin_analysis": [vp, vp, vp, vp, vp],
+        "s2w_spin_synthesis": [vp, vp, vp, vp, vp],
         "s2w_plan_destroy": [vp],
         "s2w_plan_layout": [vp, ip, ip, ip, ip, i64p, ip],
         "s2w_analysis": [vp, vp, vp, vp, vp],
@@ -99,6 +105,8 @@ _lib = _load()
 EXPORTS = ["s2w_plan_create", "s2w_plan_destroy", "s2w_plan_layout", "s2w_analysis", "s2w_synthesis",
            "s2w_analysis_lm", "s2w_analysis_noalloc", "s2w_analysis_adjoint", "s2w_synthesis_adjoint", "s2w_sht_forward", "s2w_sht_inverse",
            "s2w_wigner_forward", "s2w_wigner_inverse",
+           "s2w_plan_create_spin", "s2w_spin_sht_forward", "s2w_spin_sht_inverse", "s2w_spin_analysis",
+           "s2w_spin_synthesis",
            "s2w_plan_profile", "s2w_plan_profile_read",
            "s2w_last_error", "s2w_host_scales", "s2w_host_filters", "s2w_host_theta_matrix",
            "s2w_host_wigner_d", "s2w_host_laguerre_rule",
@@ -374,6 +382,92 @@ class Plan:
         f = torch.empty(self.map_shape, dtype=torch.float64, device=self._dev())
         _check(_lib.s2w_sht_inverse(self._h, self._p(x), self._p(f), _stream_ptr(torch, self.device)))
         return f
+
+
+class SpinPlan(Plan):
+    """Plan for complex spin-s maps (s2w_plan_create_spin).
+
+    Maps are planar float64 tensors [B, 2, L, 2L-1] (real part, imaginary part); spin-s
+    harmonic coefficients complex [B, L, 2L-1]; wavelet coefficients one packed tensor
+    whose per-scale views are [B, 2, 2N_k-1, L_k, 2L_k-1] (Re, Im); scaling coefficients
+    [B, 2, L_phi, 2L_phi-1].
+    """
+
+    def __init__(self, L, N, spin, lam=2.0, J0=0, batch=1, precision=S2W_FP64, device=0, flags=0):
+        import torch
+        self._torch = torch
+        self.L, self.N, self.spin, self.lam, self.J0, self.batch = L, N, int(spin), float(lam), J0, batch
+        self.precision = precision
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(_lib.s2w_plan_create_spin(ctypes.byref(h), L, N, float(lam), J0, int(spin), batch, precision,
+                                         device, int(flags)))
+        self._h = h
+        ns, j0 = ctypes.c_int(), ctypes.c_int()
+        Lk = (ctypes.c_int * 70)()
+        Nk = (ctypes.c_int * 70)()
+        off = (ctypes.c_int64 * 71)()
+        Lp = ctypes.c_int()
+        _check(_lib.s2w_plan_layout(h, ctypes.byref(ns), ctypes.byref(j0), Lk, Nk, off, ctypes.byref(Lp)))
+        self.nscales = ns.value
+        self.Lk = list(Lk[:ns.value])
+        self.Nk = list(Nk[:ns.value])
+        self.wav_offset = list(off[:ns.value + 1])
+        self.Lphi = Lp.value
+        self.wav_dtype = torch.float64 if precision == S2W_FP64 else torch.float32
+
+    @property
+    def map_shape(self):
+        return (self.batch, 2, self.L, 2 * self.L - 1)
+
+    @property
+    def scal_shape(self):
+        return (self.batch, 2, self.Lphi, 2 * self.Lphi - 1)
+
+    def scale_shape(self, k):
+        return (self.batch, 2, 2 * self.Nk[k] - 1, self.Lk[k], 2 * self.Lk[k] - 1)
+
+    def analysis(self, f, wav=None, scal=None):
+        torch = self._torch
+        self._check_map(f)
+        wav = self._out(wav, (self.wav_offset[-1],), self.wav_dtype, "wav")
+        scal = self._out(scal, self.scal_shape, torch.float64, "scal")
+        _check(_lib.s2w_spin_analysis(self._h, self._p(f), self._p(wav), self._p(scal),
+                                      _stream_ptr(torch, self.device)))
+        return wav, scal
+
+    def synthesis(self, wav, scal, f=None):
+        torch = self._torch
+        self._check_wav(wav)
+        self._check_scal(scal)
+        f = self._out(f, self.map_shape, torch.float64, "f")
+        _check(_lib.s2w_spin_synthesis(self._h, self._p(wav), self._p(scal), self._p(f),
+                                       _stream_ptr(torch, self.device)))
+        return f
+
+    def sht_forward(self, f):
+        torch = self._torch
+        self._check_map(f)
+        flm = torch.empty((self.batch, self.L, 2 * self.L - 1, 2), dtype=torch.float64, device=self._dev())
+        _check(_lib.s2w_spin_sht_forward(self._h, self._p(f), self._p(flm), _stream_ptr(torch, self.device)))
+        return torch.view_as_complex(flm)
+
+    def sht_inverse(self, flm):
+        torch = self._torch
+        shape = (self.batch, self.L, 2 * self.L - 1)
+        if tuple(flm.shape) != shape or not flm.is_complex():
+            raise ValueError(f"flm: expected complex coefficients of shape {shape}")
+        x = _require(torch.view_as_real(flm.to(torch.complex128)).contiguous(), "flm", torch.float64,
+                     shape + (2,), self.device)
+        f = torch.empty(self.map_shape, dtype=torch.float64, device=self._dev())
+        _check(_lib.s2w_spin_sht_inverse(self._h, self._p(x), self._p(f), _stream_ptr(torch, self.device)))
+        return f
+
+    def _unsupported(self, *a, **k):
+        raise S2WError(S2W_ESTATE, "spin plans run analysis, synthesis, sht_forward and sht_inverse only")
+
+    analysis_lm = analysis_noalloc = analysis_adjoint = synthesis_adjoint = _unsupported
+    wigner_forward = wigner_inverse = _unsupported
 
 
 def _profile_read(fn, h):

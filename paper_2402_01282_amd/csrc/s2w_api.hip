@@ -215,6 +215,9 @@ struct s2w_plan_s {
     std::vector<std::pair<double **, size_t>> ws;
     size_t ws_bytes = 0;
     bool no_ws = false;                      // created with S2W_PLAN_NO_WORKSPACE
+    // complex spin-s maps (s2w_plan_create_spin): B counts real maps, two per complex map
+    bool cplx = false;
+    int spin = 0;
     std::vector<double *> P;                 // per scale [B][L_k][nn][L_k] complex
     double *Pphi = nullptr;
     std::vector<Group> groups;
@@ -747,6 +750,66 @@ void sht_inverse_internal(s2w_plan p, const double *flm_in, double *f, hipStream
     { const DftArgs da_ = dft_args(g, p->bufB, L, f, na, p->B * L, 1.0); Prof pr_(p, "dft_c2r", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_c2r(da_, st); }
 }
 
+// Spin-s maps (plans from s2w_plan_create_spin; B counts real maps, u = Re f at 2b and
+// v = Im f at 2b + 1).  Forward spin-s SHT (eq:fswsh with sY_lm = (-1)^s sqrt((2l+1)/(4 pi))
+// e^{i m phi} d^l_{m,-s}): the real DFTs of u and v, the theta quadrature with the parity
+// (-1)^{m+s} of the n = -s integrand, the theta sums with d^l_{m,-s} and d^l_{m,s} (the
+// negative orders), then the combination into the real-map pairs (A, B) with g = A + i B
+// and / or g itself in the external layout.
+void spin_sht_forward_internal(s2w_plan p, const double *f, double *pairs, double *ext, hipStream_t st)
+{
+    const DevGrid &g = p->grids[p->L];
+    const int L = p->L, na = 2 * L - 1, s = p->spin, npar = s & 1;
+    { const DftArgs da_ = dft_args(g, f, na, p->bufA, L, p->B * L, 2.0 * M_PI / na); Prof pr_(p, "dft_r2c", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_r2c(da_, st); }
+    const std::vector<int> ns{-s, s};
+    GammaArgs ga = gamma_args(p, L, L, L, L, ns, 1);
+    ga.src = p->bufA;
+    ga.dst = p->bufB;
+    ga.sgn = -1.0;
+    ga.npar = npar;
+    sig_counts(L, npar, ga.M0, ga.M1);
+    { Prof pr_(p, "gamma_r2c", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_r2c(ga, st); }
+    theta_quadrature(p, g, p->bufB, p->bufC, L, 2, npar, st);
+    TsumArgs ta = tsum_args(p, g, L, ns, npar);
+    ta.h[0] = p->bufC;
+    ta.w[0] = p->wsht;
+    ta.wstride = 0;
+    ta.out[0] = p->bufA;
+    {
+        Prof pr_(p, "tsum", rec_work(L, L, ns, 1, p->B, [](int, int, int) { return 1.0; }), st);
+        s2w::launch_tsum(ta, 1, p->B, st);
+    }
+    s2w::launch_spin_combine(p->bufA, pairs, ext, L, s, p->B / 2, st);
+}
+
+// Inverse spin-s SHT (eq:iswsh) from the real-map pairs or from g in the external layout:
+// the split into the coefficient rows of u and v (n = -s and n = +s slots), the l-sums, the
+// sum over the two slots, and the real inverse DFTs.
+void spin_sht_inverse_internal(s2w_plan p, const double *pairs, const double *ext, double *f, hipStream_t st)
+{
+    const DevGrid &g = p->grids[p->L];
+    const int L = p->L, na = 2 * L - 1, s = p->spin;
+    s2w::launch_spin_split(pairs, ext, p->bufC, L, s, p->B / 2, st);
+    const std::vector<int> ns{-s, s};
+    LsumArgs la = lsum_args(p, g, L, ns);
+    la.flm = p->bufC;
+    la.flm_m = 2 * L;
+    la.flm_l = L;
+    la.flm_nstride = (long)L * L;
+    la.w[0] = p->wsht;
+    la.wstride = 0;
+    la.out[0] = p->bufA;
+    {
+        Prof pr_(p, "lsum", rec_work(L, L, ns, 1, p->B, [](int, int, int) { return 1.0; }), st);
+        s2w::launch_lsum(la, 1, p->B, st);
+    }
+    GammaArgs ga = gamma_args(p, L, L, L, L, ns, 1);
+    ga.src = p->bufA;
+    ga.dst = p->bufB;
+    { Prof pr_(p, "gamma_c2r", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_c2r(ga, st); }
+    { const DftArgs da_ = dft_args(g, p->bufB, L, f, na, p->B * L, 1.0); Prof pr_(p, "dft_c2r", dft_flop(da_.n, da_.nrows), st); s2w::launch_dft_c2r(da_, st); }
+}
+
 // ---- mixed-precision stages (FP32 arrays, FP64 recursion and scale sums) ----
 
 void theta_quadrature32(s2w_plan p, const DevGrid &g, const float *F, float *H, int M, int nn, int npar,
@@ -1080,11 +1143,18 @@ s2w_status check_plan(s2w_plan p)
     return S2W_OK;
 }
 
-// transform entry points that use the plan's own workspace
+// real-map transform entry points that use the plan's own workspace
 s2w_status check_ws(s2w_plan p)
 {
+    if (p->cplx) return fail(S2W_ESTATE, "plan made for complex spin maps: use the s2w_spin_* calls");
     if (p->no_ws)
         return fail(S2W_ESTATE, "plan created with S2W_PLAN_NO_WORKSPACE: only s2w_analysis_noalloc runs on it");
+    return S2W_OK;
+}
+
+s2w_status check_spin(s2w_plan p)
+{
+    if (!p->cplx) return fail(S2W_ESTATE, "plan made for real maps: the s2w_spin_* calls need s2w_plan_create_spin");
     return S2W_OK;
 }
 
@@ -1169,13 +1239,22 @@ s2w_status s2w_host_wigner_d(int L, int m, int n, double *out)
     return S2W_OK;
 }
 
-s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, int batch,
-                           s2w_precision precision, int device, unsigned flags)
+// Plan creation for real maps (cplx false) or for complex spin-`spin` maps (cplx true:
+// every map is held as its real and imaginary parts, so the internal batch is 2 batch).
+static s2w_status plan_create(s2w_plan *out, int L, int N, double lambda, int J0, int batch,
+                              s2w_precision precision, int device, unsigned flags, bool cplx, int spin)
 {
     AllocSeq alloc_seq;
     if (!out) return fail(S2W_EINVAL, "null output pointer");
     *out = nullptr;
     if (batch < 1) return fail(S2W_EINVAL, "batch must be >= 1");
+    if (cplx) {
+        if (batch > (1 << 29)) return fail(S2W_EINVAL, "batch too large");
+        if (L < 1 || spin <= -L || spin >= L) return fail(S2W_EINVAL, "spin must satisfy |spin| < L");
+        if (flags & (S2W_PLAN_GRAPH | S2W_PLAN_NO_WORKSPACE | S2W_PLAN_WIGNER))
+            return fail(S2W_EINVAL, "spin plans accept S2W_PLAN_TUNE, S2W_PLAN_PERSISTENT and S2W_PLAN_PRECOMPUTE only");
+        batch *= 2;
+    }
     if (flags & ~(unsigned)(S2W_PLAN_TUNE | S2W_PLAN_GRAPH | S2W_PLAN_NO_WORKSPACE | S2W_PLAN_PERSISTENT |
                             S2W_PLAN_PRECOMPUTE | S2W_PLAN_WIGNER))
         return fail(S2W_EINVAL, "unknown flags");
@@ -1199,6 +1278,7 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
     if (!p) return fail(S2W_ENOMEM, "host allocation failed");
     p->L = L; p->N = N; p->J0 = J0; p->J = S.J; p->B = batch; p->device = device;
     p->lambda = lambda; p->prec = precision;
+    p->cplx = cplx; p->spin = cplx ? spin : 0;
     p->S = S;
     p->Lphi = S.Lphi;
     s2w::make_filters(p->S, p->F);
@@ -1219,6 +1299,9 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
     // transforms, every |n| < N)
     p->nglob = S.s.back().n;
     if (std::find(p->nglob.begin(), p->nglob.end(), 0) == p->nglob.end()) p->nglob.push_back(0);
+    if (cplx)
+        for (int n : {-spin, spin})
+            if (std::find(p->nglob.begin(), p->nglob.end(), n) == p->nglob.end()) p->nglob.push_back(n);
     p->wigner = (flags & S2W_PLAN_WIGNER) != 0;
     if (p->wigner)
         for (int n = -(N - 1); n <= N - 1; ++n)
@@ -1326,6 +1409,18 @@ s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, i
     reg_add(p);
     *out = p;
     return S2W_OK;
+}
+
+s2w_status s2w_plan_create(s2w_plan *out, int L, int N, double lambda, int J0, int batch,
+                           s2w_precision precision, int device, unsigned flags)
+{
+    return plan_create(out, L, N, lambda, J0, batch, precision, device, flags, false, 0);
+}
+
+s2w_status s2w_plan_create_spin(s2w_plan *out, int L, int N, double lambda, int J0, int spin, int batch,
+                                s2w_precision precision, int device, unsigned flags)
+{
+    return plan_create(out, L, N, lambda, J0, batch, precision, device, flags, true, spin);
 }
 
 s2w_status s2w_plan_destroy(s2w_plan p)
@@ -1550,6 +1645,7 @@ struct ScratchScope {
 s2w_status s2w_analysis_noalloc(s2w_plan p, const double *f, void *wav_, double *scal, void *stream)
 {
     if (s2w_status st = check_plan(p)) return st;
+    if (p->cplx) return fail(S2W_ESTATE, "plan made for complex spin maps: use the s2w_spin_* calls");
     if (!f || !wav_ || !scal) return fail(S2W_EINVAL, "null buffer");
     if (p->ws_bytes > S2W_SCRATCH_BYTES)
         return fail(S2W_EUNSUPPORTED, "this plan needs " + std::to_string(p->ws_bytes) +
@@ -2102,6 +2198,58 @@ s2w_status s2w_wigner_inverse(s2w_plan p, const double *flmn, double *f, void *s
     s2w::launch_wig_ext_to_int(flmn, p->wint, p->L, p->N, p->B, st);
     wigner_inverse_internal(p, p->wint, f, st);
     return post_launch("s2w_wigner_inverse");
+}
+
+// ---- complex spin-s maps ----
+
+s2w_status s2w_spin_sht_forward(s2w_plan p, const double *f, double *flm, void *stream)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (s2w_status st = check_spin(p)) return st;
+    if (!f || !flm) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p, st);
+    spin_sht_forward_internal(p, f, nullptr, flm, st);
+    return post_launch("s2w_spin_sht_forward");
+}
+
+s2w_status s2w_spin_sht_inverse(s2w_plan p, const double *flm, double *f, void *stream)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (s2w_status st = check_spin(p)) return st;
+    if (!f || !flm) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p, st);
+    spin_sht_inverse_internal(p, nullptr, flm, f, st);
+    return post_launch("s2w_spin_sht_inverse");
+}
+
+// The wavelet coefficients of a spin-s map depend on it only through its spin-s harmonic
+// coefficients g_lm (eq:wigner_wav_coeffs, eq:harmonic_scal_coeffs, filters as for spin
+// 0), and are linear in them: with g = A + i B for the real maps A, B, W(g) = W(A) + i W(B),
+// where W(A) and W(B) are the real transforms of the plan's real machinery.
+s2w_status s2w_spin_analysis(s2w_plan p, const double *f, void *wav, double *scal, void *stream)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (s2w_status st = check_spin(p)) return st;
+    if (!f || !wav || !scal) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p, st);
+    spin_sht_forward_internal(p, f, p->flm, nullptr, st);
+    analysis_from_flm(p, p->flm, wav, scal, st);
+    return post_launch("s2w_spin_analysis");
+}
+
+s2w_status s2w_spin_synthesis(s2w_plan p, const void *wav, const double *scal, double *f, void *stream)
+{
+    if (s2w_status st = check_plan(p)) return st;
+    if (s2w_status st = check_spin(p)) return st;
+    if (!f || !wav || !scal) return fail(S2W_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    StreamOrder order(p, st);
+    synthesis_to_fhat(p, wav, scal, p->fhat, st);
+    spin_sht_inverse_internal(p, p->fhat, nullptr, f, st);
+    return post_launch("s2w_spin_synthesis");
 }
 
 s2w_status s2w_plan_profile(s2w_plan p, int capacity)

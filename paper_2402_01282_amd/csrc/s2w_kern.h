@@ -168,6 +168,9 @@ void launch_pack_sigma_f32(const float *in, float *out, int B, int nn, int M, in
                            int M1, int dir, hipStream_t st);
 void launch_flm_to_ext(const double *in, double *out, int L, int B, hipStream_t st);
 void launch_flm_from_ext(const double *in, double *out, int L, int B, hipStream_t st);
+// spin-s maps held as real pairs (B = user maps; pairs and cin hold 2B real maps)
+void launch_spin_combine(const double *X, double *pairs, double *ext, int L, int s, int B, hipStream_t st);
+void launch_spin_split(const double *pairs, const double *ext, double *cin, int L, int s, int B, hipStream_t st);
 // SO(3) coefficient layouts: external "nlm" [B][2N-1][L][2L-1] complex (index n+N-1, l, m+L-1)
 // <-> internal [B][2N-1][m < L][l < L]; outputs of the theta sum [B][m][nq][l] for the n
 // values nval[0..nq) -> external, with the m < 0 entries from the real-function symmetry

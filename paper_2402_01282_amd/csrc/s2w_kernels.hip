@@ -1620,6 +1620,83 @@ __global__ void k_flm_from_ext(const double *in, double *out, int L, int B)
     }
 }
 
+// ------------------------------------------------------------ spin-s maps ----
+// A complex spin-s map f = u + i v is held as the two real maps u, v (batch entries 2b and
+// 2b + 1).  Its spin-s harmonic coefficients g_lm (all m) use d^l_{m,-s} for m >= 0 and,
+// through d^l_{-m,-s} = (-1)^{m+s} d^l_{m,s}, d^l_{m,s} for the negative orders.  On the
+// real side every sum runs over m >= 0 with two n slots: slot 0 for n = -s, slot 1 for
+// n = +s.
+
+// X [2B][m][2][l] complex: the forward sums of u and v (weights sqrt((2l+1)/(4 pi)) applied),
+// so that g_lm = (-1)^s (XU0 + i XV0) and h_lm = (-1)^m conj(g_{l,-m}) = XU1 - i XV1 (m >= 0).
+// pairs [2B][m][l]: the coefficients of the real maps A, B with g = A + i B,
+//   a = (g + h) / 2, b = (g - h) / (2i); ext [B][l][2L-1] complex: g itself.
+__global__ void k_spin_combine(const double *X, double *pairs, double *ext, int L, int s)
+{
+    const int m = blockIdx.x, b = blockIdx.y;
+    const int as = s < 0 ? -s : s, l0 = m > as ? m : as;
+    const double ss = (as & 1) ? -1.0 : 1.0;
+    const double2 *X2 = reinterpret_cast<const double2 *>(X);
+    const double2 *xu = X2 + (((size_t)(2 * b) * L + m) * 2) * L;
+    const double2 *xv = X2 + (((size_t)(2 * b + 1) * L + m) * 2) * L;
+    for (int l = threadIdx.x; l < L; l += blockDim.x) {
+        double2 g = make_double2(0.0, 0.0), h = make_double2(0.0, 0.0);
+        if (l >= l0) {
+            const double2 u0 = xu[l], v0 = xv[l], u1 = xu[L + l], v1 = xv[L + l];
+            g = make_double2(ss * (u0.x - v0.y), ss * (u0.y + v0.x));
+            h = make_double2(u1.x + v1.y, u1.y - v1.x);
+        }
+        if (pairs) {
+            double2 *pa = reinterpret_cast<double2 *>(pairs);
+            pa[((size_t)(2 * b) * L + m) * L + l] = make_double2(0.5 * (g.x + h.x), 0.5 * (g.y + h.y));
+            pa[((size_t)(2 * b + 1) * L + m) * L + l] = make_double2(0.5 * (g.y - h.y), -0.5 * (g.x - h.x));
+        }
+        if (ext) {
+            double2 *e = reinterpret_cast<double2 *>(ext) + ((size_t)b * L + l) * (2 * L - 1) + (L - 1);
+            e[m] = g;
+            if (m > 0) {   // g_{l,-m} = (-1)^m conj(h)
+                const double sm = (m & 1) ? -1.0 : 1.0;
+                e[-m] = make_double2(sm * h.x, -sm * h.y);
+            }
+        }
+    }
+}
+
+// The inverse: from g (ext [B][l][2L-1], or pairs [2B][m][l] with g = a + i b, h = a - i b)
+// to the coefficient rows cin [2B][2][m][l] of the two real maps u = Re f, v = Im f:
+//   u: slot 0 = (-1)^s g / 2, slot 1 = h / 2;  v: slot 0 = -i (-1)^s g / 2, slot 1 = i h / 2,
+// so that summing the two slots after the l-sums gives the m >= 0 Fourier rows of u and v.
+__global__ void k_spin_split(const double *pairs, const double *ext, double *cin, int L, int s)
+{
+    const int m = blockIdx.x, b = blockIdx.y;
+    const int as = s < 0 ? -s : s, l0 = m > as ? m : as;
+    const double hs = (as & 1) ? -0.5 : 0.5;
+    const double sm = (m & 1) ? -1.0 : 1.0;
+    double2 *c2 = reinterpret_cast<double2 *>(cin);
+    double2 *cu = c2 + (((size_t)(2 * b) * 2) * L + m) * L;
+    double2 *cv = c2 + (((size_t)(2 * b + 1) * 2) * L + m) * L;
+    for (int l = threadIdx.x; l < L; l += blockDim.x) {
+        double2 g = make_double2(0.0, 0.0), h = make_double2(0.0, 0.0);
+        if (l >= l0) {
+            if (pairs) {
+                const double2 *pa = reinterpret_cast<const double2 *>(pairs);
+                const double2 a = pa[((size_t)(2 * b) * L + m) * L + l], c = pa[((size_t)(2 * b + 1) * L + m) * L + l];
+                g = make_double2(a.x - c.y, a.y + c.x);
+                h = make_double2(a.x + c.y, a.y - c.x);
+            } else {
+                const double2 *e = reinterpret_cast<const double2 *>(ext) + ((size_t)b * L + l) * (2 * L - 1) + (L - 1);
+                g = e[m];
+                const double2 n = e[-m];
+                h = make_double2(sm * n.x, -sm * n.y);
+            }
+        }
+        cu[l] = make_double2(hs * g.x, hs * g.y);
+        cu[(size_t)L * L + l] = make_double2(0.5 * h.x, 0.5 * h.y);
+        cv[l] = make_double2(hs * g.y, -hs * g.x);
+        cv[(size_t)L * L + l] = make_double2(-0.5 * h.y, 0.5 * h.x);
+    }
+}
+
 // ----------------------------------------------------------- SO(3) layouts ----
 // external "nlm" -> internal [b][n index][m >= 0][l] (the inverse transform reads m >= 0)
 __global__ void k_wig_ext_to_int(const double *ext, double *in, int L, int N)
@@ -1955,6 +2032,16 @@ void launch_flm_to_ext(const double *in, double *out, int L, int B, hipStream_t 
 void launch_flm_from_ext(const double *in, double *out, int L, int B, hipStream_t st)
 {
     hipLaunchKernelGGL(k_flm_from_ext, dim3(L, B), dim3(256), 0, st, in, out, L, B);
+}
+
+void launch_spin_combine(const double *X, double *pairs, double *ext, int L, int s, int B, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_spin_combine, dim3(L, B), dim3(256), 0, st, X, pairs, ext, L, s);
+}
+
+void launch_spin_split(const double *pairs, const double *ext, double *cin, int L, int s, int B, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_spin_split, dim3(L, B), dim3(256), 0, st, pairs, ext, cin, L, s);
 }
 
 }  // namespace s2w
