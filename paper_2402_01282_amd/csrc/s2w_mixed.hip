@@ -1151,9 +1151,80 @@ __global__ __launch_bounds__(256, 3) void k_dft_mm(const DftArgs a)
     const int k1t = tid % n1, k2t = tid % n2;
     const long npairs = (a.nrows + 1) / 2, ngroups = (npairs + R - 1) / R;
     constexpr int U = 4;
+    // With the sizes fixed at compile time (256 threads), the next row group's input is
+    // fetched into registers while the current group runs its two stages, so the global
+    // loads overlap the matrix-core work (block barriers wait on LDS only).
+    constexpr bool PF = N1C > 0 && RC > 0;
+    constexpr int NTC = 256, NC = N1C * N2C;
+    constexpr int NP = PF ? ((DIR > 0 ? (NC + 1) / 2 : NC) + U * NTC - 1) / (U * NTC) : 1;
+    constexpr int RP = PF ? RC : 1;
+    typedef typename std::conditional<(DIR > 0), float2, Tin>::type PT;
+    PT pf1[NP][RP][U], pf2[NP][RP][U];
+    auto fetch = [&](long grp) {
+        const long pair0 = grp * RP;
+#pragma unroll
+        for (int ps = 0; ps < NP; ++ps)
+#pragma unroll
+            for (int s = 0; s < RP; ++s) {
+                const long r1 = 2 * (pair0 + s);
+                const PT *in1 = reinterpret_cast<const PT *>(a.in) + r1 * a.istride;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int e = ps * U * NTC + tid + NTC * u;
+                    PT z1{}, z2{};
+                    if (e < (DIR > 0 ? (NC + 1) / 2 : NC) && r1 < a.nrows) {
+                        z1 = in1[e];
+                        if (r1 + 1 < a.nrows) z2 = in1[a.istride + e];
+                    }
+                    pf1[ps][s][u] = z1;
+                    pf2[ps][s][u] = z2;
+                }
+            }
+    };
+    if constexpr (PF) {
+        if ((long)blockIdx.x < ngroups) fetch(blockIdx.x);
+    }
     for (long grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
         const long pair0 = grp * R;
-        if (DIR > 0) {
+        if constexpr (PF) {
+            // scatter the fetched group into prime-factor order, then fetch the next one
+            int m1 = m1t, m2 = m2t;
+#pragma unroll
+            for (int ps = 0; ps < NP; ++ps) {
+                int pos[U], posc[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    pos[u] = m1 * n2 + m2;
+                    posc[u] = (m1 == 0 ? 0 : n1 - m1) * n2 + (m2 == 0 ? 0 : n2 - m2);
+                    m1 += d1;
+                    if (m1 >= n1) m1 -= n1;
+                    m2 += d2;
+                    if (m2 >= n2) m2 -= n2;
+                }
+#pragma unroll
+                for (int s = 0; s < RP; ++s) {
+                    float2 *Zs = Z + (size_t)s * n;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int e = ps * U * NTC + tid + NTC * u;
+                        if constexpr (DIR > 0) {
+                            if (e >= Lh) continue;
+                            const float sc = (float)a.scale;
+                            const float2 z1 = pf1[ps][s][u], z2 = pf2[ps][s][u];
+                            if (e == 0) {
+                                Zs[0] = make_float2(sc * z1.x, sc * z2.x);
+                            } else {
+                                Zs[pos[u]] = make_float2(sc * (z1.x - z2.y), sc * (z1.y + z2.x));
+                                Zs[posc[u]] = make_float2(sc * (z1.x + z2.y), sc * (z2.x - z1.y));
+                            }
+                        } else {
+                            if (e < n) Zs[pos[u]] = make_float2((float)pf1[ps][s][u], (float)pf2[ps][s][u]);
+                        }
+                    }
+                }
+            }
+            if (grp + gridDim.x < ngroups) fetch(grp + gridDim.x);
+        } else if (DIR > 0) {
             const float sc = (float)a.scale;
             int m1 = m1t, m2 = m2t;
             for (int mb = 0; mb < Lh; mb += U * NT) {
@@ -1322,14 +1393,14 @@ static void launch_dft_mm_t(DftArgs a, hipStream_t st)
     const int blocks = (int)std::min<long>(ngroups, 2048);
     // 2047 = 23 x 89 (L = 1024, the two top scales) with all sizes as constants
     constexpr bool top = MT1 == 1 && KS1 == 3 && MT2 == 3 && KS2 == 12;
-    if (top && a.n1 == 23 && a.n2 == 89 && R == 2) {
+    if constexpr (top) if (a.n1 == 23 && a.n2 == 89 && R == 2) {
         if (DIR > 0) hipLaunchKernelGGL((k_dft_mm<1, float, MT1, KS1, MT2, KS2, 23, 89, 2>), dim3(blocks), dim3(256), lds, st, a);
         else hipLaunchKernelGGL((k_dft_mm<-1, float, MT1, KS1, MT2, KS2, 23, 89, 2>), dim3(blocks), dim3(256), lds, st, a);
         return;
     }
     // 1023 = 31 x 33 (L = 512)
     constexpr bool l512 = MT1 == 1 && KS1 == 4 && MT2 == 2 && KS2 == 5;
-    if (l512 && a.n1 == 31 && a.n2 == 33 && R == 4) {
+    if constexpr (l512) if (a.n1 == 31 && a.n2 == 33 && R == 4) {
         if (DIR > 0) hipLaunchKernelGGL((k_dft_mm<1, float, MT1, KS1, MT2, KS2, 31, 33, 4>), dim3(blocks), dim3(256), lds, st, a);
         else hipLaunchKernelGGL((k_dft_mm<-1, float, MT1, KS1, MT2, KS2, 31, 33, 4>), dim3(blocks), dim3(256), lds, st, a);
         return;
