@@ -70,7 +70,9 @@ def parse():
 
 
 # name a launch carries in the per-kernel timing -> the library kernel symbols it runs
-KERNEL_NAMES = [("tsum_mm", ["k_tsum_mm<", "k_tsum_mm16<"]), ("lsum_mm", ["k_lsum_mm<"]), ("gemm_theta_f32", ["k_gemm<float>"]),
+KERNEL_NAMES = [("tsum_mm", ["k_tsum_mm<", "k_tsum_mm16<"]), ("tsum_tab", ["k_tsum_tab("]),
+                ("lsum_mm", ["k_lsum_mm<", "k_lsum_bf3<", "k_lsum_bf3_list<"]),
+                ("gemm_theta_bf3", ["k_gemm_bf3("]), ("gemm_theta_f32", ["k_gemm<float>"]),
                 ("gemm_theta", ["k_gemm<double>"]), ("dft_c2r_f32", ["k_dft_mm<1,"]),
                 ("dft_r2c_f32", ["k_dft_mm<-1,"]), ("gamma_c2r_f32", ["k_gamma_c2r<float"]),
                 ("gamma_r2c_f32", ["k_gamma_r2c<float"]), ("tsum", ["k_tsum_mm64<", "k_tsum<"]),
@@ -78,8 +80,9 @@ KERNEL_NAMES = [("tsum_mm", ["k_tsum_mm<", "k_tsum_mm16<"]), ("lsum_mm", ["k_lsu
 
 
 def is_mixed_kernel(name):
-    """Kernels of the mixed form whose contractions run on FP32 matrix cores."""
-    return name.endswith("_mm") or name.endswith("_f32")
+    """Kernels of the mixed form whose contractions run on matrix cores in FP32 accuracy
+    (FP32 products, or BF16 products of three-part splits)."""
+    return name.endswith("_mm") or name.endswith("_f32") or name.endswith("_tab")
 
 
 def end_to_end(kern, steps, ms_step, L, B, nwav, scal_shape, esz):

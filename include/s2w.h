@@ -92,7 +92,14 @@ enum {
                                creation (all n of the plan, m < L, l >= max(m, |n|): about
                                N L^3 / 2 doubles per grid, 4.8 GB at L = 512, N = 8) and the FP64
                                vector contractions (FP64 plans below 16 maps, the vector route of
-                               mixed plans) read d from it instead of running the recursion. */
+                               mixed plans) read d from it instead of running the recursion.
+                               Mixed plans also fold the theta quadrature of the synthesis into a
+                               table: for every scale group on a grid with L >= 64 and L % 8 == 0,
+                               sum_theta' d^l_mn(theta') T_sigma[theta][theta'] in three BF16
+                               parts (3 N L^3 / 2 bytes per grid: 26 GB at L = 1024, N = 8), and
+                               the synthesis contracts its rows with it on matrix cores (no
+                               quadrature product, no recursion).  The product's tile lists are
+                               built for the plan's batch. */
 };
 
 /* Size of the static device scratch that s2w_analysis_noalloc works in (one copy per

@@ -240,6 +240,16 @@ struct s2w_plan_s {
     double *wint = nullptr, *w8pi = nullptr, *wone = nullptr;
     // precompute mode: per grid band limit (<= PRE_MAX_L), the d table and its row offsets
     std::map<int, std::pair<double *, int64_t *>> dtabs;
+    // precompute mode of mixed plans: per scale group (index into groups), the BF16 parts of
+    // the folded theta quadrature and contraction table, and the tile lists of the product
+    struct TTab {
+        uint16_t *tab = nullptr;
+        int64_t *toff = nullptr;
+        int4 *tiles = nullptr;
+        int cnt[8] = {0}, off[8] = {0};
+        size_t bytes = 0;
+    };
+    std::map<int, TTab> ttabs;
     // persistent l-contraction of the mixed analysis (one launch over the degree groups in
     // lgroups, work items in eight per-XCD lists sorted by cost); used when lsum_list is set
     // and the batch is the one the list was built for
@@ -659,6 +669,101 @@ bool make_dtables(s2w_plan p)
         p->dtabs[L] = {tab, doff};
     }
     return hipDeviceSynchronize() == hipSuccess && hipGetLastError() == hipSuccess;
+}
+
+// Precompute mode of mixed plans: for every scale group on a grid of band limit L >= 64
+// with L % 8 == 0, the table Dt^l_mn(theta) = sum_theta' d^l_mn(theta') T_sigma[theta][theta']
+// (sigma = parity of m + n) for the group's n values, m < L and max(m, |n|) <= l < L, in
+// three BF16 parts: 3 N L^3 / 2 bytes per grid (26 GB at L = 1024, N = 8).  Built from the
+// FP64 recursion and the FP64 quadrature matrices one n at a time (temporary FP64 d rows of
+// that n: L^3 / 2 doubles), then the tile lists of the synthesis product for the plan's batch.
+bool make_ttables(s2w_plan p)
+{
+    const int npar = (p->N - 1) & 1;
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        const auto &grp = p->groups[gi];
+        const int L = grp.L;
+        if (L < 64 || L % 8 != 0) continue;
+        const DevGrid &g = p->grids[L];
+        const auto &si = p->S.s[grp.scales[0]];
+        const int nn = (int)si.n.size(), NS = (int)grp.scales.size();
+        s2w_plan_s::TTab tt;
+        std::vector<int64_t> toff((size_t)nn * L, 0);
+        int64_t tot = 0;
+        size_t dmax = 0;
+        for (int ni = 0; ni < nn; ++ni) {
+            size_t dn = 0;
+            for (int m = 0; m < L; ++m) {
+                toff[(size_t)ni * L + m] = tot;
+                const int rows = L - std::max(m, std::abs(si.n[ni]));
+                if (rows > 0) {
+                    tot += 3 * (int64_t)rows * L;
+                    dn += (size_t)rows * L;
+                }
+            }
+            dmax = std::max(dmax, dn);
+        }
+        if (!dalloc(p, tt.tab, (size_t)tot) || !upload(p, tt.toff, toff)) return false;
+        tt.bytes = (size_t)tot * sizeof(uint16_t);
+        // temporaries: FP64 d rows of one n, the folded rows of one m, and the row offsets
+        double *dtmp = nullptr, *ftmp = nullptr;
+        int64_t *doffd = nullptr;
+        const int NG = (int)p->nglob.size();
+        bool ok = dev_malloc((void **)&dtmp, std::max<size_t>(dmax, 1) * sizeof(double)) == hipSuccess;
+        ok = ok && dev_malloc((void **)&ftmp, (size_t)L * L * sizeof(double)) == hipSuccess;
+        ok = ok && dev_malloc((void **)&doffd, (size_t)NG * L * sizeof(int64_t)) == hipSuccess;
+        for (int ni = 0; ok && ni < nn; ++ni) {
+            const int n = si.n[ni], ng = nglob_index(p, n);
+            std::vector<int64_t> doff((size_t)NG * L, 0), moff(L, 0);
+            int64_t t = 0;
+            for (int m = 0; m < L; ++m) {
+                doff[(size_t)ng * L + m] = moff[m] = t;
+                const int rows = L - std::max(m, std::abs(n));
+                if (rows > 0) t += (int64_t)rows * L;
+            }
+            ok = hipMemcpy(doffd, doff.data(), doff.size() * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess;
+            if (!ok) break;
+            LsumArgs la = lsum_args(p, g, L, std::vector<int>{n});
+            s2w::launch_dtable(la, dtmp, doffd, nullptr);
+            for (int m = 0; m < L; ++m) {
+                const int rows = L - std::max(m, std::abs(n));
+                if (rows <= 0) continue;
+                s2w::launch_gemm(dtmp + moff[m], g.T[(m + npar) & 1], ftmp, rows, L, L, nullptr);
+                s2w::launch_split3_f64(ftmp, tt.tab + toff[(size_t)ni * L + m], (size_t)rows * L, nullptr);
+            }
+        }
+        ok = ok && hipDeviceSynchronize() == hipSuccess && hipGetLastError() == hipSuccess;
+        if (dtmp) (void)hipFree(dtmp);
+        if (ftmp) (void)hipFree(ftmp);
+        if (doffd) (void)hipFree(doffd);
+        if (!ok) return false;
+        // tile lists: problems by decreasing row count dealt to the eight XCD lists, the tiles of
+        // a problem consecutive (degree tile outer, column tile inner)
+        const int ncols = 2 * p->B * NS, nct = (ncols + 127) / 128;
+        std::vector<std::pair<int, int>> probs;   // (m, ni)
+        for (int ni = 0; ni < nn; ++ni)
+            for (int m = 0; m < L; ++m)
+                if (L - std::max(m, std::abs(si.n[ni])) > 0) probs.push_back({m, ni});
+        std::stable_sort(probs.begin(), probs.end(), [&](const std::pair<int, int> &u, const std::pair<int, int> &v) {
+            return L - std::max(u.first, std::abs(si.n[u.second])) > L - std::max(v.first, std::abs(si.n[v.second]));
+        });
+        std::vector<int4> lists[8];
+        for (size_t q = 0; q < probs.size(); ++q) {
+            const int m = probs[q].first, ni = probs[q].second;
+            const int rows = L - std::max(m, std::abs(si.n[ni])), nlt = (rows + 127) / 128;
+            for (int lt = 0; lt < nlt; ++lt)
+                for (int ct = 0; ct < nct; ++ct) lists[q % 8].push_back(make_int4(m, ni, ct, lt));
+        }
+        std::vector<int4> all;
+        for (int x = 0; x < 8; ++x) {
+            tt.off[x] = (int)all.size();
+            tt.cnt[x] = (int)lists[x].size();
+            all.insert(all.end(), lists[x].begin(), lists[x].end());
+        }
+        if (!upload(p, tt.tiles, all)) return false;
+        p->ttabs[(int)gi] = tt;
+    }
+    return true;
 }
 
 GammaArgs gamma_args(s2w_plan p, int M, int L, int Min, int Mout, const std::vector<int> &ns, int ng)
@@ -1388,6 +1493,8 @@ static s2w_status plan_create(s2w_plan *out, int L, int N, double lambda, int J0
                 if (!dalloc(p, *it.first, it.second)) return oom("workspace");
     }
     if ((flags & S2W_PLAN_PRECOMPUTE) && !make_dtables(p)) return oom("precomputed d tables");
+    if ((flags & S2W_PLAN_PRECOMPUTE) && precision == S2W_MIXED && !make_ttables(p))
+        return oom("precomputed contraction tables");
     if ((flags & S2W_PLAN_PERSISTENT) && precision == S2W_MIXED && !p->no_ws) {
         if (!build_lsum_list(p)) return oom("work list");
         p->lsum_list = true;
@@ -1669,8 +1776,11 @@ static void synthesis_to_fhat(s2w_plan p, const void *wav_, const double *scal, 
     const int B = p->B;
     const int npar = (p->N - 1) & 1;
     const bool mixed = p->prec == S2W_MIXED;
-    for (auto &grp : p->groups) {
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
         if (!mixed) continue;
+        const auto &grp = p->groups[gi];
+        const auto tti = p->ttabs.find((int)gi);
+        const bool tab = tti != p->ttabs.end();
         const float *wav32 = (const float *)wav_;
         float *A32 = (float *)p->bufA, *B32 = (float *)p->bufB, *C32 = (float *)p->bufC;
         const DevGrid &g = p->grids[grp.L];
@@ -1700,7 +1810,7 @@ static void synthesis_to_fhat(s2w_plan p, const void *wav_, const double *scal, 
                 Prof pr_(p, "gamma_r2c_f32", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st);
                 s2w::launch_gamma_r2c(ga, st, true);
             }
-            theta_quadrature32(p, g, A32 + s * cstride, C32 + s * cstride, Lk, nn, npar, st);
+            if (!tab) theta_quadrature32(p, g, A32 + s * cstride, C32 + s * cstride, Lk, nn, npar, st);
             ta.w[s] = p->wpsi[k];
             ta.lmin[s] = p->lmin[k];
             mi.h[s] = C32 + s * cstride;
@@ -1708,7 +1818,37 @@ static void synthesis_to_fhat(s2w_plan p, const void *wav_, const double *scal, 
             ta.h[s] = p->bufA + s * cstride;
             ta.out[s] = p->P[k];
         }
-        if (tsum_vector(p, Lk)) {
+        if (tab) {
+            // precompute mode: quadrature and contraction through the folded table
+            const auto &tt = tti->second;
+            s2w::TsumTab tb{};
+            tb.L = Lk;
+            tb.mcount = Lk;
+            tb.nn = nn;
+            tb.B = B;
+            tb.NS = NS;
+            tb.npar = npar;
+            sig_counts(Lk, npar, tb.M0, tb.M1);
+            for (int i = 0; i < nn; ++i) tb.nval[i] = si.n[i];
+            for (int s = 0; s < NS; ++s) {
+                tb.h[s] = A32 + s * cstride;
+                tb.out[s] = p->P[grp.scales[s]];
+                tb.w[s] = p->wpsi[grp.scales[s]];
+            }
+            tb.wstride = Lk;
+            tb.tab = tt.tab;
+            tb.toff = tt.toff;
+            tb.tiles = tt.tiles;
+            for (int x = 0; x < 8; ++x) {
+                tb.cnt[x] = tt.cnt[x];
+                tb.off[x] = tt.off[x];
+            }
+            Work wk = rec_work_psi(p, grp.scales, ta.L, ta.mcount, si.n, B);
+            wk.flop -= wk.flop64;   // no recursion: d comes from the table
+            wk.flop64 = 0.0;
+            Prof pr_(p, "tsum_tab", wk, st);
+            s2w::launch_tsum_tab(tb, st);
+        } else if (tsum_vector(p, Lk)) {
             // the quadrature rows of every scale are no longer needed in A32: widen them there
             { Prof pr_(p, "convert", 0.0, st); s2w::launch_convert(C32, p->bufA, NS * cstride, false, st); }
             Prof pr_(p, "tsum", rec_work_psi(p, grp.scales, ta.L, ta.mcount, si.n, B), st);

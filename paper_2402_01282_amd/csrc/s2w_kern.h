@@ -137,6 +137,24 @@ struct LsumList {
 };
 void launch_lsum_list(const LsumList &gl, const uint2 *items, unsigned *counters, int nblocks, hipStream_t st);
 void launch_tsum_mm(const TsumArgs &a, const MixIn &in, int NS, hipStream_t st);
+// precompute mode, mixed plans: the theta contraction of the synthesis through a table of
+// (d T_sigma)^l_mn(theta) in three BF16 parts, as a batched product over (m, n) problems
+struct TsumTab {
+    int L, mcount, nn, B, NS, npar, M0, M1;
+    int nval[MAX_NN];
+    const float *h[MAX_NS];      // sigma-grouped rows before the theta quadrature, FP32
+    double *out[MAX_NS];         // [B][mcount][nn][L] complex FP64
+    const double *w[MAX_NS];     // filter weights [nn][wstride]
+    int wstride;
+    const uint16_t *tab;         // per (n index, m): three BF16 parts, each [L - l0][L]
+    const int64_t *toff;         // [nn][mcount]: offset of the first part
+    const int4 *tiles;           // (m, n index, column tile, degree tile) in eight per-XCD lists
+    int cnt[8], off[8];
+};
+void launch_tsum_tab(const TsumTab &a, hipStream_t st);
+// three BF16 parts of FP64 values (x0 + x1 + x2 = x to 2^-27 |x|): part p of element i at
+// out[p * count + i]
+void launch_split3_f64(const double *in, uint16_t *out, size_t count, hipStream_t st);
 
 void launch_lsum(const LsumArgs &a, int NS, int B, hipStream_t st);
 // precompute mode: d table of one grid for the n values of a (nval, nglob), all m < L

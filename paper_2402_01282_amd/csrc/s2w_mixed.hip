@@ -1578,6 +1578,176 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf3(const float *__restrict__ A
             }
 }
 
+// ------------------------------------------------------- k_tsum_tab -------
+// Precompute mode of the mixed synthesis: the theta quadrature T_sigma and the theta
+// contraction with d^l_mn fold into one table, Dt^l_mn(theta) = sum_theta' d^l_mn(theta')
+// T_sigma[theta][theta'] (T_sigma is symmetric), so that
+//   out[col][l] = w_l sum_theta F[col][theta] Dt^l_mn(theta)
+// with F the rows before the quadrature.  One (m, n) problem is a product of its columns
+// (2 x maps x scales) by its L - max(m, |n|) table rows over the L theta samples, run
+// with the tiling, operand split and product order of k_gemm_bf3 (F split as it is
+// staged, the table stored as three BF16 parts).  Tiles (128 columns x 128 degrees) come
+// from eight per-XCD lists in which the tiles of one problem are consecutive, so that the
+// column tiles sharing the table rows of a degree tile run back to back on one XCD.
+// Result register r of a lane holds column 4 (lane / 16) + r: registers (0, 1) and (2, 3)
+// are the real and imaginary parts of one map, written as one 16-byte (re, im) pair.
+__global__ __launch_bounds__(256, 2) void k_tsum_tab(const TsumTab a)
+{
+    __shared__ __align__(16) __bf16 As[3][G3_BM * G3_RS];
+    __shared__ __align__(16) __bf16 Bs[3][G3_BN * G3_RS];
+    const int xc = blockIdx.x & 7, kx = blockIdx.x >> 3;
+    if (kx >= a.cnt[xc]) return;
+    const int4 tl = a.tiles[a.off[xc] + kx];
+    const int m = tl.x, ni = tl.y;
+    const int L = a.L, B = a.B, ncols = 2 * B * a.NS;
+    const int n = a.nval[ni], an = n < 0 ? -n : n, l0 = m > an ? m : an;
+    const int rows = L - l0;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int row0 = tl.z * G3_BM, col0 = tl.w * G3_BN;   // column rows of F, degree rows of the table
+    const int sig = (m + a.npar) & 1, mp = m >> 1;
+    const size_t sigoff = sig == 0 ? 0 : (size_t)B * a.M0 * a.nn * 2;
+    const int Msig = sig == 0 ? a.M0 : a.M1;
+    const int aq = tid & 7, ar = tid >> 3;
+    const int bq = tid & 3, br = tid >> 2;
+    const float *arow[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int cg = row0 + ar + 32 * r;
+        arow[r] = nullptr;
+        if (cg < ncols) {
+            const int s = cg / (2 * B), rem = cg - s * 2 * B;
+            arow[r] = a.h[s] + (sigoff + (((size_t)(rem >> 1) * Msig + mp) * a.nn + ni) * 2 + (rem & 1)) * L;
+        }
+    }
+    const __bf16 *tb = reinterpret_cast<const __bf16 *>(a.tab) + a.toff[(size_t)ni * a.mcount + m];
+    const size_t pstride = (size_t)rows * L;
+    float4 ra[4];
+    bf16x8 rb[3][2];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int gk = k0 + aq * 4;
+            ra[r] = (arow[r] && gk < L) ? *reinterpret_cast<const float4 *>(arow[r] + gk) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int gn = col0 + br + 64 * r, gk = k0 + bq * 8;
+                if (gn < rows && gk < L) rb[p][r] = *reinterpret_cast<const bf16x8 *>(tb + p * pstride + (size_t)gn * L + gk);
+                else
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) rb[p][r][e] = (__bf16)0.f;
+            }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            bf16x4 p0, p1, p2;
+            split3(ra[r], p0, p1, p2);
+            const int o = (ar + 32 * r) * G3_RS + aq * 4;
+            *reinterpret_cast<bf16x4 *>(&As[0][o]) = p0;
+            *reinterpret_cast<bf16x4 *>(&As[1][o]) = p1;
+            *reinterpret_cast<bf16x4 *>(&As[2][o]) = p2;
+        }
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+                *reinterpret_cast<bf16x8 *>(&Bs[p][(br + 64 * r) * G3_RS + bq * 8]) = rb[p][r];
+    };
+    f4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4{0, 0, 0, 0};
+    const int nk = (L + G3_BK - 1) / G3_BK;
+    const int fo = (lane & 15) * G3_RS + (lane >> 4) * 8;
+    gload(0);
+    for (int t = 0; t < nk; ++t) {
+        __syncthreads();
+        sstore();
+        __syncthreads();
+        if (t + 1 < nk) gload((t + 1) * G3_BK);
+        bf16x8 bf[3][4];
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                bf[p][j] = *reinterpret_cast<const bf16x8 *>(&Bs[p][(wc * 64 + j * 16) * G3_RS + fo]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bf16x8 af[3];
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+                af[p] = *reinterpret_cast<const bf16x8 *>(&As[p][(wr * 64 + i * 16) * G3_RS + fo]);
+            constexpr int PA[6] = {1, 0, 2, 0, 1, 0}, PB[6] = {1, 2, 0, 1, 0, 0};
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[PA[q]], bf[PB[q]][j], acc[i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int lr = col0 + wc * 64 + j * 16 + (lane & 15);
+            if (lr >= rows) continue;
+            const int l = l0 + lr;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int cg = row0 + wr * 64 + i * 16 + 4 * (lane >> 4) + 2 * h;   // even: the real part
+                if (cg >= ncols) continue;
+                const int s = cg / (2 * B), b = (cg - s * 2 * B) >> 1;
+                const double wt = a.w[s][(size_t)ni * a.wstride + l];
+                double2 *o = reinterpret_cast<double2 *>(a.out[s]) + (((size_t)b * a.mcount + m) * a.nn + ni) * L + l;
+                *o = make_double2((double)acc[i][j][2 * h] * wt, (double)acc[i][j][2 * h + 1] * wt);
+            }
+        }
+    // m <= l < l0: zero (d^l_mn vanishes below max(|m|, |n|)); the first degree tile's blocks
+    if (tl.w == 0 && l0 > m) {
+        for (int e = tid; e < 64 * (l0 - m); e += 256) {
+            const int pr = e / (l0 - m), l = m + e - pr * (l0 - m);
+            const int cg = row0 + 2 * pr;
+            if (cg >= ncols) continue;
+            const int s = cg / (2 * B), b = (cg - s * 2 * B) >> 1;
+            reinterpret_cast<double2 *>(a.out[s])[(((size_t)b * a.mcount + m) * a.nn + ni) * L + l] = make_double2(0.0, 0.0);
+        }
+    }
+}
+
+void launch_tsum_tab(const TsumTab &a, hipStream_t st)
+{
+    int mx = 0;
+    for (int x = 0; x < 8; ++x) mx = std::max(mx, a.cnt[x]);
+    if (mx == 0) return;
+    hipLaunchKernelGGL(k_tsum_tab, dim3(8u * (unsigned)mx), dim3(256), 0, st, a);
+}
+
+__global__ void k_split3_f64(const double *__restrict__ in, __bf16 *__restrict__ out, size_t count)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+        const double x = in[i];
+        const __bf16 p0 = (__bf16)(float)x;
+        const double r1 = x - (double)(float)p0;
+        const __bf16 p1 = (__bf16)(float)r1;
+        const double r2 = r1 - (double)(float)p1;
+        out[i] = p0;
+        out[count + i] = p1;
+        out[2 * count + i] = (__bf16)(float)r2;
+    }
+}
+
+void launch_split3_f64(const double *in, uint16_t *out, size_t count, hipStream_t st)
+{
+    if (count == 0) return;
+    const unsigned blocks = (unsigned)std::min<size_t>((count + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_split3_f64, dim3(blocks), dim3(256), 0, st, in, reinterpret_cast<__bf16 *>(out), count);
+}
+
 bool gemm_bf3_ok(int K) { return K % 8 == 0; }
 
 void launch_gemm_bf3(const float *A, const void *B0, const void *B1, const void *B2, float *C, int M, int N, int K,

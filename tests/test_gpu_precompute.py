@@ -57,3 +57,39 @@ def test_precompute_against_oracle(prec, L, N, J0, B):
     lhs = (torch.dot(Aw.double(), yw.double()) + torch.sum(As * ys)).item()
     rhs = torch.sum(g * pre.analysis_adjoint(yw, ys)).item()
     assert abs(lhs - rhs) < (1e-12 if prec == 0 else 3e-6) * abs(lhs)
+
+
+@pytest.mark.parametrize("L,N,J0,B", [(64, 4, 0, 4), (128, 3, 1, 8), (256, 4, 0, 16), (1000, 3, 0, 2)])
+def test_mixed_precompute_synthesis(L, N, J0, B):
+    """Mixed plans in precompute mode: the synthesis contracts through the folded table
+    (d T_sigma in three BF16 parts).  Random coefficients (every entry nonzero) against the
+    recursion form of the same plan and against the oracle's synthesis, element by element."""
+    torch = _torch()
+    import paper_2402_01282_amd as s2w
+    from _gpuutil import elementwise, fmt
+    print(f"[mixed precompute synthesis L={L} N={N} J0={J0} B={B}]", flush=True)
+    pre = s2w.Plan(L, N, 2.0, J0, batch=B, precision=s2w.S2W_MIXED, device=0, flags=s2w.S2W_PLAN_PRECOMPUTE)
+    rec = s2w.Plan(L, N, 2.0, J0, batch=B, precision=s2w.S2W_MIXED, device=0)
+    P = wavelets.Plan(L, N, 2.0, J0)
+    rng = np.random.default_rng(L + B)
+    wav = torch.from_numpy(rng.normal(size=pre.wav_offset[-1]).astype(np.float32)).cuda()
+    scal = torch.from_numpy(rng.normal(size=pre.scal_shape)).cuda()
+    fp = pre.synthesis(wav, scal).clone()
+    fr = rec.synthesis(wav, scal)
+    d = (torch.linalg.norm(fp - fr) / torch.linalg.norm(fr)).item()
+    print(f"  precompute vs recursion rel diff {d:.1e}", flush=True)
+    assert d < 1e-6
+    views = pre.wav_views(wav)
+    fpn = fp.cpu().numpy()
+    for b in sorted({0, B - 1}):
+        ref = wavelets.synthesis([v[b].double().cpu().numpy() for v in views], scal[b].cpu().numpy(), P)
+        r = _rel(fpn[b], ref)
+        e = elementwise(fpn[b], ref, 0)
+        print(f"  map {b}: rel {r:.1e} {fmt(e)}", flush=True)
+        assert r < 1e-6 and e["all"] < 2e-5
+    # analysis with the same plan is unchanged by the table (recursion form)
+    f = torch.from_numpy(rng.normal(size=pre.map_shape)).cuda()
+    wa, sa = pre.analysis(f)
+    wa = wa.clone()
+    wb, sb = rec.analysis(f)
+    assert torch.equal(wa, wb)
