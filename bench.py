@@ -53,7 +53,11 @@ def parse():
     ap.add_argument("--graph", action="store_true", help="replay each transform as a HIP graph (no per-kernel timing)")
     ap.add_argument("--no-tune", action="store_true", help="skip the plan's tile-shape autotuning")
     ap.add_argument("--precompute", action="store_true",
-                    help="precompute mode: Wigner d tabulated in device memory for grids of band limit <= 512")
+                    help="precompute mode for every form (FP64: Wigner d tabulated for grids of band limit "
+                         "<= 512; mixed: also the folded quadrature-contraction tables of the synthesis)")
+    ap.add_argument("--no-precompute", action="store_true",
+                    help="run the mixed form with the recursion only (by default the headline mixed form "
+                         "uses precompute mode and the recursion form is reported beside it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM traffic counters)")
     ap.add_argument("--sweep", action="store_true",
@@ -82,7 +86,7 @@ KERNEL_NAMES = [("tsum_mm", ["k_tsum_mm<", "k_tsum_mm16<"]), ("tsum_tab", ["k_ts
 def is_mixed_kernel(name):
     """Kernels of the mixed form whose contractions run on matrix cores in FP32 accuracy
     (FP32 products, or BF16 products of three-part splits)."""
-    return name.endswith("_mm") or name.endswith("_f32") or name.endswith("_tab")
+    return name.endswith(("_mm", "_f32", "_tab", "_bf3"))
 
 
 def end_to_end(kern, steps, ms_step, L, B, nwav, scal_shape, esz):
@@ -134,16 +138,19 @@ def record_traffic(fetch_dir, write_dir, args):
             continue
         fb = 1024.0 * ff * sum(fv[k] for k in ks) / len(ks)
         wb = 1024.0 * fw * sum(wv[k] for k in kw) / len(kw)
+        pre = args.precompute or not args.no_precompute
         kern[bname] = {"workload": (f"sphere directional wavelets analysis+synthesis, mixed FP32/FP64 batched, "
-                                    f"L={args.L}, N={args.N}, lambda={args.lam:g}, J0={args.J0}, batch=64"),
+                                    f"L={args.L}, N={args.N}, lambda={args.lam:g}, J0={args.J0}, batch=64"
+                                    + (", precompute mode" if pre else "")),
                        "launches": len(ks), "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
                        "bytes_per_launch": fb + wb}
     rec = {"source_sha256": source_hash(),
            "copy_calibration": {"fetch_kib_for_1gib": cf, "write_kib_for_1gib": cw,
                                 "fetch_scale": ff, "write_scale": fw},
            "command": ("cd /tmp && rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <dir> -o run --output-format csv "
-                       "-- python3 bench.py --precision mixed --steps 1 --warmup 0 --no-tune --no-cpu-baseline "
-                       "--no-kernel-timing --copy-calibration"),
+                       "-- python3 bench.py --precision mixed --precompute --steps 1 --warmup 0 --no-cpu-baseline "
+                       "--no-kernel-timing --copy-calibration; per kernel the average over every dispatch of the "
+                       "run (plan tuning, the round trip and the gradient step: same shapes)"),
            "kernels": kern}
     with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
         json.dump(rec, fh, indent=1)
@@ -210,7 +217,7 @@ def recorded_traffic(kernel, workload):
     return ent.get("bytes_per_launch") if ent else None
 
 
-def run_form(args, precision, B):
+def run_form(args, precision, B, precompute=None):
     import torch
 
     import paper_2402_01282_amd as s2w
@@ -219,8 +226,11 @@ def run_form(args, precision, B):
     L, N, lam, J0 = args.L, args.N, args.lam, args.J0
     mixed = precision == "mixed"
     print(f"[bench] L={L} N={N} lambda={lam} J0={J0} batch={B} precision={precision}", file=sys.stderr, flush=True)
+    if precompute is None:
+        precompute = args.precompute
+    print(f"[bench] precompute={precompute}", file=sys.stderr, flush=True)
     flags = (0 if args.no_tune else s2w.S2W_PLAN_TUNE) | (s2w.S2W_PLAN_GRAPH if args.graph else 0) \
-        | (s2w.S2W_PLAN_PRECOMPUTE if args.precompute else 0)
+        | (s2w.S2W_PLAN_PRECOMPUTE if precompute else 0)
     torch.cuda.synchronize()
     free0 = torch.cuda.mem_get_info()[0]
     t0 = time.perf_counter()
@@ -282,11 +292,12 @@ def run_form(args, precision, B):
     torch.cuda.synchronize()
     dtg = time.perf_counter() - t0
     workload = (f"sphere directional wavelets analysis+synthesis, "
-                f"{'mixed FP32/FP64 batched' if mixed else 'FP64'}, L={L}, N={N}, lambda={lam:g}, J0={J0}, batch={B}")
+                f"{'mixed FP32/FP64 batched' if mixed else 'FP64'}, L={L}, N={N}, lambda={lam:g}, J0={J0}, batch={B}"
+                + (", precompute mode" if precompute else ""))
     out = {"value": maps_per_s, "ms_per_step": 1e3 * dt / args.steps,
            "dtype": "f32+f64" if mixed else "f64", "workload": workload, "batch": B,
            "coefficients_per_s": maps_per_s * (plan.wav_offset[-1] // B), "round_trip_rel_err": err,
-           "plan_create_s": t_plan, "plan_device_gib": plan_bytes / 2 ** 30,
+           "plan_create_s": t_plan, "plan_device_gib": plan_bytes / 2 ** 30, "precompute": bool(precompute),
            "gradient": {"maps_per_s": B * args.steps / dtg, "ms_per_step": 1e3 * dtg / args.steps,
                         "what": "analysis + transpose of the analysis (gradient of sum_j sum (W^j)^2)"}}
     if kern:
@@ -403,8 +414,9 @@ def main():
         for B in (1, 4, 16, 64):
             for graph in (False, True):
                 args.graph = graph
-                r = run_form(args, "mixed", B)
-                rows.append({"batch": B, "graph": graph, "maps_per_s": r["value"], "ms_per_call": r["ms_per_step"],
+                r = run_form(args, "mixed", B, precompute=args.precompute or not args.no_precompute)
+                rows.append({"batch": B, "graph": graph, "precompute": r["precompute"], "maps_per_s": r["value"],
+                             "ms_per_call": r["ms_per_step"],
                              "round_trip_rel_err": r["round_trip_rel_err"]})
         print(json.dumps({"sweep": "mixed form, L=%d, N=%d, lambda=%g, J0=%d" % (args.L, args.N, args.lam, args.J0),
                           "rows": rows}), flush=True)
@@ -417,9 +429,17 @@ def main():
 
     forms = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
     res = {}
+    # the mixed form runs in precompute mode unless told otherwise (its tables fit the HBM of
+    # one GPU at L = 1024); its recursion form is measured beside it
+    mixed_pre = args.precompute or not args.no_precompute
     for form in forms:
         B = args.batch if args.batch is not None else (64 if form == "mixed" else 1)
-        res[form] = run_form(args, form, B)
+        if form == "mixed":
+            res[form] = run_form(args, form, B, precompute=mixed_pre)
+            if mixed_pre and not args.precompute:
+                res["mixed_recursion"] = run_form(args, form, B, precompute=False)
+        else:
+            res[form] = run_form(args, form, B)
     head = res[forms[0]]
     out = {
         "metric": "analysis+synthesis maps/s at L=1024,N=8: FP64 vs mixed-batched @ <=1e-6 rel err",
@@ -436,7 +456,8 @@ def main():
         "data": "synthetic Gaussian random fields, C_l = 1/(l+1)^2, synthesised on the GPU",
         "config": {"workload": head["workload"], "L": args.L, "N": args.N, "lambda": args.lam, "J0": args.J0,
                    "batch": head["batch"], "form": forms[0], "tuned": not args.no_tune, "graph": args.graph,
-                   "precompute": args.precompute},
+                   "precompute": head["precompute"]},
+        "plan_device_gib": head["plan_device_gib"],
         "plan_create_s": head["plan_create_s"],
         "coefficients_per_s": head["coefficients_per_s"],
         "round_trip_rel_err": head["round_trip_rel_err"],
@@ -446,6 +467,11 @@ def main():
               "kernel_time_fraction_of_step", "kernel_timing_dropped_launches"):
         if k in head:
             out[k] = head[k]
+    if "mixed_recursion" in res:
+        r = res["mixed_recursion"]
+        out["mixed_recursion_form"] = {k: r[k] for k in ("value", "ms_per_step", "workload", "round_trip_rel_err",
+                                                         "plan_create_s", "plan_device_gib", "roofline",
+                                                         "kernel_breakdown_ms_per_step", "end_to_end") if k in r}
     if "fp64" in res and forms[0] != "fp64":
         out["fp64_form"] = res["fp64"]
         out["speedup_vs_fp64_form"] = head["value"] / res["fp64"]["value"]
