@@ -86,7 +86,7 @@ KERNEL_NAMES = [("tsum_mm", ["k_tsum_mm<", "k_tsum_mm16<"]), ("tsum_tab", ["k_ts
 def is_mixed_kernel(name):
     """Kernels of the mixed form whose contractions run on matrix cores in FP32 accuracy
     (FP32 products, or BF16 products of three-part splits)."""
-    return name.endswith(("_mm", "_f32", "_tab", "_bf3"))
+    return name.endswith(("_mm", "_f32", "_bf3")) or name == "tsum_tab"
 
 
 def end_to_end(kern, steps, ms_step, L, B, nwav, scal_shape, esz):

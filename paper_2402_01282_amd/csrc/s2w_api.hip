@@ -250,6 +250,11 @@ struct s2w_plan_s {
         size_t bytes = 0;
     };
     std::map<int, TTab> ttabs;
+    // precompute mode, batched plans: the folded forward-SHT table of the full grid (FP64)
+    double *shttab = nullptr;
+    int64_t *shtoff = nullptr;
+    int4 *shttiles = nullptr;
+    int shtcnt[8] = {0}, shtoffx[8] = {0};
     // persistent l-contraction of the mixed analysis (one launch over the degree groups in
     // lgroups, work items in eight per-XCD lists sorted by cost); used when lsum_list is set
     // and the batch is the one the list was built for
@@ -766,6 +771,59 @@ bool make_ttables(s2w_plan p)
     return true;
 }
 
+// Precompute mode of batched plans (8 maps or more): the forward SHT of the full grid through
+// the FP64 table Dt^l_m(theta) = sum_theta' d^l_m0(theta') T_sigma[theta][theta'] (per m,
+// rows l = m..L-1): L^2 (L+1) / 2 doubles (4.3 GB at L = 1024), built from the FP64
+// recursion rows of n = 0 and one quadrature product per m; then the tile lists for the
+// plan's batch.  Needs an even L (16-byte loads).
+bool make_shttab(s2w_plan p)
+{
+    const int L = p->L;
+    if (L < 64 || L % 2 != 0 || p->B < 8 || p->cplx) return true;
+    const DevGrid &g = p->grids[L];
+    std::vector<int64_t> toff(L, 0);
+    int64_t tot = 0;
+    for (int m = 0; m < L; ++m) {
+        toff[m] = tot;
+        tot += (int64_t)(L - m) * L;
+    }
+    if (!dalloc(p, p->shttab, (size_t)tot) || !upload(p, p->shtoff, toff)) return false;
+    const int NG = (int)p->nglob.size(), ng = nglob_index(p, 0);
+    double *dtmp = nullptr;
+    int64_t *doffd = nullptr;
+    bool ok = dev_malloc((void **)&dtmp, (size_t)tot * sizeof(double)) == hipSuccess;
+    ok = ok && dev_malloc((void **)&doffd, (size_t)NG * L * sizeof(int64_t)) == hipSuccess;
+    if (ok) {
+        std::vector<int64_t> doff((size_t)NG * L, 0);
+        for (int m = 0; m < L; ++m) doff[(size_t)ng * L + m] = toff[m];
+        ok = hipMemcpy(doffd, doff.data(), doff.size() * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess;
+    }
+    if (ok) {
+        LsumArgs la = lsum_args(p, g, L, std::vector<int>{0});
+        s2w::launch_dtable(la, dtmp, doffd, nullptr);
+        for (int m = 0; m < L; ++m)
+            s2w::launch_gemm(dtmp + toff[m], g.T[m & 1], p->shttab + toff[m], L - m, L, L, nullptr);
+        ok = hipDeviceSynchronize() == hipSuccess && hipGetLastError() == hipSuccess;
+    }
+    if (dtmp) (void)hipFree(dtmp);
+    if (doffd) (void)hipFree(doffd);
+    if (!ok) return false;
+    const int mt = (2 * p->B + 127) / 128;
+    std::vector<int4> lists[8];
+    for (int m = 0; m < L; ++m) {   // rows decrease with m: dealt in order
+        const int nt = (L - m + 63) / 64;
+        for (int j = 0; j < nt; ++j)
+            for (int i = 0; i < mt; ++i) lists[m % 8].push_back(make_int4(m, i, j, 0));
+    }
+    std::vector<int4> all;
+    for (int x = 0; x < 8; ++x) {
+        p->shtoffx[x] = (int)all.size();
+        p->shtcnt[x] = (int)lists[x].size();
+        all.insert(all.end(), lists[x].begin(), lists[x].end());
+    }
+    return upload(p, p->shttiles, all);
+}
+
 GammaArgs gamma_args(s2w_plan p, int M, int L, int Min, int Mout, const std::vector<int> &ns, int ng)
 {
     GammaArgs a{};
@@ -819,6 +877,30 @@ void sht_forward_internal(s2w_plan p, const double *f, double *flm_out, hipStrea
     ga.sgn = -1.0;
     sig_counts(L, 0, ga.M0, ga.M1);
     { Prof pr_(p, "gamma_r2c", 8.0 * ga.B * ga.M * ga.L * ga.ng * ga.nn, st); s2w::launch_gamma_r2c(ga, st); }
+    if (p->shttab) {
+        // precompute mode: quadrature and theta sums through the folded table
+        s2w::ShtTab sa{};
+        sa.L = L;
+        sa.B = p->B;
+        sa.M0 = ga.M0;
+        sa.M1 = ga.M1;
+        sa.F = p->bufB;
+        sa.out = flm_out;
+        sa.w = p->wsht;
+        sa.tab = p->shttab;
+        sa.toff = p->shtoff;
+        sa.tiles = p->shttiles;
+        for (int x = 0; x < 8; ++x) {
+            sa.cnt[x] = p->shtcnt[x];
+            sa.off[x] = p->shtoffx[x];
+        }
+        Work wk = rec_work_n0(p, p->wsht, L, L, p->B);
+        wk.flop -= wk.flop64;   // no recursion: d comes from the table
+        wk.flop64 = 0.0;
+        Prof pr_(p, "sht_tab", wk, st);
+        s2w::launch_sht_tab(sa, st);
+        return;
+    }
     theta_quadrature(p, g, p->bufB, p->bufC, L, 1, 0, st);
     TsumArgs ta = tsum_args(p, g, L, n0, 0);
     ta.h[0] = p->bufC;
@@ -1495,6 +1577,7 @@ static s2w_status plan_create(s2w_plan *out, int L, int N, double lambda, int J0
     if ((flags & S2W_PLAN_PRECOMPUTE) && !make_dtables(p)) return oom("precomputed d tables");
     if ((flags & S2W_PLAN_PRECOMPUTE) && precision == S2W_MIXED && !make_ttables(p))
         return oom("precomputed contraction tables");
+    if ((flags & S2W_PLAN_PRECOMPUTE) && !p->no_ws && !make_shttab(p)) return oom("precomputed SHT table");
     if ((flags & S2W_PLAN_PERSISTENT) && precision == S2W_MIXED && !p->no_ws) {
         if (!build_lsum_list(p)) return oom("work list");
         p->lsum_list = true;

@@ -152,6 +152,19 @@ struct TsumTab {
     int cnt[8], off[8];
 };
 void launch_tsum_tab(const TsumTab &a, hipStream_t st);
+// precompute mode, forward SHT in FP64: f_lm = w_l sum_theta F_m(theta) Dt^l_m(theta) with the
+// folded table Dt^l_m = d^l_m0 T_sigma (per m: rows l = m..L-1, theta contiguous), batched over m
+struct ShtTab {
+    int L, B, M0, M1;
+    const double *F;             // sigma-grouped rows before the quadrature (n = 0)
+    double *out;                 // internal flm [B][L][L] complex
+    const double *w;             // sqrt((2l+1)/(4 pi))
+    const double *tab;           // per m: [L - m][L]
+    const int64_t *toff;         // [L]
+    const int4 *tiles;           // (m, column tile, degree tile, 0) in eight per-XCD lists
+    int cnt[8], off[8];
+};
+void launch_sht_tab(const ShtTab &a, hipStream_t st);
 // three BF16 parts of FP64 values (x0 + x1 + x2 = x to 2^-27 |x|): part p of element i at
 // out[p * count + i]
 void launch_split3_f64(const double *in, uint16_t *out, size_t count, hipStream_t st);

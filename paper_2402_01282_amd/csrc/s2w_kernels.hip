@@ -1876,6 +1876,121 @@ void launch_scale_pl(const double *in, double *out, const double *phi, int P, in
     hipLaunchKernelGGL(k_scale_pl, dim3((unsigned)blocks), dim3(256), 0, st, in, out, phi, P, L, total);
 }
 
+// Precompute mode, forward SHT (FP64): the theta quadrature and the theta sums fold into
+// one table per m, Dt^l_m(theta) = sum_theta' d^l_m0(theta') T_sigma[theta][theta'] (rows
+// l = m..L-1, theta contiguous), so that f_lm = w_l sum_theta F_m(theta) Dt^l_m(theta) with
+// F the sigma-grouped rows before the quadrature.  A batched product over m: the 2B
+// columns (map, re/im) of m against its L - m table rows, with the tiling, double buffering
+// and FP64 16x16x4 products of k_gemm<double>; the table slab [64 l][16 theta] is
+// transposed into the [k][n] LDS layout as it is staged.  Tiles (m, column tile, degree
+// tile) come from eight per-XCD lists.  Output: the internal flm [B][m][l] complex.
+__global__ __launch_bounds__(256) void k_sht_tab(const ShtTab a)
+{
+    constexpr int BM = 128, BN = 64, BK = 16, WN = BN / 32;
+    constexpr int AS = BK + 2, BS = BN + 16;
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    __shared__ __align__(16) double As[2 * BM * AS];
+    __shared__ __align__(16) double Bs[2 * BK * BS];
+    const int xc = blockIdx.x & 7, kx = blockIdx.x >> 3;
+    if (kx >= a.cnt[xc]) return;
+    const int4 tl = a.tiles[a.off[xc] + kx];
+    const int m = tl.x, L = a.L, M = 2 * a.B, N = L - m, K = L;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int row0 = tl.y * BM, col0 = tl.z * BN;
+    const int sig = m & 1, mp = m >> 1;
+    const size_t sigoff = sig == 0 ? 0 : (size_t)a.B * a.M0 * 2;
+    const int Msig = sig == 0 ? a.M0 : a.M1;
+    const double *Bt = a.tab + a.toff[m];
+    // staging: A 128 rows x 16 k as double2 (4 per thread); B 64 rows (l) x 16 k (4 per thread)
+    const double *arow[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int f = tid + 256 * r, am = f >> 3, gr = row0 + am;
+        arow[r] = gr < M ? a.F + (sigoff + ((size_t)(gr >> 1) * Msig + mp) * 2 + (gr & 1)) * L : nullptr;
+    }
+    const int bl = tid >> 2, bq = tid & 3;
+    double2 ra[4], rb[2];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int f = tid + 256 * r, aq = f & 7, gk = k0 + 2 * aq;
+            ra[r] = (arow[r] && gk < K) ? *reinterpret_cast<const double2 *>(arow[r] + gk) : make_double2(0.0, 0.0);
+        }
+        const int gl = col0 + bl, gk = k0 + 4 * bq;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            rb[h] = (gl < N && gk < K) ? *reinterpret_cast<const double2 *>(Bt + (size_t)gl * K + gk + 2 * h)
+                                       : make_double2(0.0, 0.0);
+    };
+    auto sstore = [&](int buf) {
+        double *as = As + buf * BM * AS;
+        double *bs = Bs + buf * BK * BS;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int f = tid + 256 * r, am = f >> 3, aq = f & 7;
+            *reinterpret_cast<double2 *>(as + am * AS + 2 * aq) = ra[r];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            bs[(4 * bq + 2 * h) * BS + bl] = rb[h].x;
+            bs[(4 * bq + 2 * h + 1) * BS + bl] = rb[h].y;
+        }
+    };
+    v4 acc[4][WN];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = v4{0, 0, 0, 0};
+    const int nk = (K + BK - 1) / BK;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int t = 0; t < nk; ++t) {
+        const int cur = t & 1;
+        if (t + 1 < nk) gload((t + 1) * BK);
+        const double *as = As + cur * BM * AS;
+        const double *bs = Bs + cur * BK * BS;
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            double af[4], bf[WN];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) af[i] = as[(wr * 64 + i * 16 + (lane & 15)) * AS + kk + (lane >> 4)];
+#pragma unroll
+            for (int j = 0; j < WN; ++j) bf[j] = bs[(kk + (lane >> 4)) * BS + wc * (BN / 2) + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        if (t + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+    // result register r of lane: column lane % 16, row lane / 16 + 4 r (FP64 layout)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gr = row0 + wr * 64 + i * 16 + (lane >> 4) + 4 * r;
+                const int gc = col0 + wc * (BN / 2) + j * 16 + (lane & 15);
+                if (gr < M && gc < N) {
+                    const int l = m + gc;
+                    a.out[(((size_t)(gr >> 1) * L + m) * L + l) * 2 + (gr & 1)] = acc[i][j][r] * a.w[l];
+                }
+            }
+}
+
+void launch_sht_tab(const ShtTab &a, hipStream_t st)
+{
+    int mx = 0;
+    for (int x = 0; x < 8; ++x) mx = std::max(mx, a.cnt[x]);
+    if (mx == 0) return;
+    hipLaunchKernelGGL(k_sht_tab, dim3(8u * (unsigned)mx), dim3(256), 0, st, a);
+}
+
 template <typename Tp>
 static void launch_gemm_t(const Tp *A, const Tp *Bm, Tp *C, int M, int N, int K, hipStream_t st, bool accum)
 {

@@ -87,9 +87,41 @@ def test_mixed_precompute_synthesis(L, N, J0, B):
         e = elementwise(fpn[b], ref, 0)
         print(f"  map {b}: rel {r:.1e} {fmt(e)}", flush=True)
         assert r < 1e-6 and e["all"] < 2e-5
-    # analysis with the same plan is unchanged by the table (recursion form)
-    f = torch.from_numpy(rng.normal(size=pre.map_shape)).cuda()
+    # analysis (from 8 maps on, its forward SHT runs through the folded FP64 table)
+    flm = np.stack([S.sphere_flm(L, S.stream_key(15, b)) for b in range(B)])
+    f = torch.from_numpy(np.stack([np.real(mw.sht_inverse(flm[b], L)) for b in range(B)])).cuda()
     wa, sa = pre.analysis(f)
-    wa = wa.clone()
+    wa, sa = wa.clone(), sa.clone()
     wb, sb = rec.analysis(f)
-    assert torch.equal(wa, wb)
+    da = (torch.linalg.norm((wa - wb).double()) / torch.linalg.norm(wb.double())).item()
+    print(f"  analysis precompute vs recursion rel diff {da:.1e}", flush=True)
+    assert da < 1e-6
+    va = pre.wav_views(wa)
+    ow, os_ = wavelets.analysis_lm(flm[B - 1], P)
+    es = [_rel(va[k][B - 1].double().cpu().numpy(), w) for k, w in enumerate(ow)]
+    assert max(es) < 1e-6 and _rel(sa[B - 1].cpu().numpy(), os_) < 1e-6, es
+
+
+@pytest.mark.parametrize("L,B", [(64, 8), (256, 8), (1000, 8)])
+def test_fp64_batched_precompute_sht(L, B):
+    """Batched plans in precompute mode: the forward SHT through the folded FP64 table keeps
+    FP64 accuracy (the harmonic coefficients and the analysis against the oracle at 1e-12)."""
+    torch = _torch()
+    import paper_2402_01282_amd as s2w
+    print(f"[fp64 batched precompute sht L={L} B={B}]", flush=True)
+    N = 3
+    pre = s2w.Plan(L, N, 2.0, 0, batch=B, device=0, flags=s2w.S2W_PLAN_PRECOMPUTE)
+    P = wavelets.Plan(L, N, 2.0, 0)
+    flm = np.stack([S.sphere_flm(L, S.stream_key(16, b)) for b in range(B)])
+    f = np.stack([np.real(mw.sht_inverse(flm[b], L)) for b in range(B)])
+    ft = torch.from_numpy(f).cuda()
+    got = pre.sht_forward(ft).cpu().numpy()
+    for b in (0, B - 1):
+        assert _rel(got[b], flm[b]) < 1e-12, (b, _rel(got[b], flm[b]))
+    wav, scal = pre.analysis(ft)
+    views = pre.wav_views(wav)
+    ow, os_ = wavelets.analysis_lm(flm[B - 1], P)
+    es = [_rel(views[k][B - 1].cpu().numpy(), w) for k, w in enumerate(ow)]
+    print("  per-scale rel err " + " ".join(f"{e:.1e}" for e in es), flush=True)
+    assert max(es) < 1e-11
+    assert _rel(pre.synthesis(wav, scal).cpu().numpy(), f) < 1e-11
