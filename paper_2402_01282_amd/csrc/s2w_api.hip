@@ -255,6 +255,10 @@ struct s2w_plan_s {
     int64_t *shtoff = nullptr;
     int4 *shttiles = nullptr;
     int shtcnt[8] = {0}, shtoffx[8] = {0};
+    // ... and the d^l_m0 table of the inverse SHT (same offsets), with its tile lists
+    double *shtitab = nullptr;
+    int4 *shtitiles = nullptr;
+    int shticnt[8] = {0}, shtioffx[8] = {0};
     // persistent l-contraction of the mixed analysis (one launch over the degree groups in
     // lgroups, work items in eight per-XCD lists sorted by cost); used when lsum_list is set
     // and the batch is the one the list was built for
@@ -789,9 +793,11 @@ bool make_shttab(s2w_plan p)
     }
     if (!dalloc(p, p->shttab, (size_t)tot) || !upload(p, p->shtoff, toff)) return false;
     const int NG = (int)p->nglob.size(), ng = nglob_index(p, 0);
-    double *dtmp = nullptr;
+    // the d rows stay as the inverse table
+    if (!dalloc(p, p->shtitab, (size_t)tot)) return false;
+    double *dtmp = p->shtitab;
     int64_t *doffd = nullptr;
-    bool ok = dev_malloc((void **)&dtmp, (size_t)tot * sizeof(double)) == hipSuccess;
+    bool ok = true;
     ok = ok && dev_malloc((void **)&doffd, (size_t)NG * L * sizeof(int64_t)) == hipSuccess;
     if (ok) {
         std::vector<int64_t> doff((size_t)NG * L, 0);
@@ -805,10 +811,22 @@ bool make_shttab(s2w_plan p)
             s2w::launch_gemm(dtmp + toff[m], g.T[m & 1], p->shttab + toff[m], L - m, L, L, nullptr);
         ok = hipDeviceSynchronize() == hipSuccess && hipGetLastError() == hipSuccess;
     }
-    if (dtmp) (void)hipFree(dtmp);
     if (doffd) (void)hipFree(doffd);
     if (!ok) return false;
     const int mt = (2 * p->B + 127) / 128;
+    {
+        std::vector<int4> il[8];
+        for (int m = 0; m < L; ++m)
+            for (int j = 0; j < (L + 63) / 64; ++j)
+                for (int i = 0; i < mt; ++i) il[m % 8].push_back(make_int4(m, i, j, 0));
+        std::vector<int4> iall;
+        for (int x = 0; x < 8; ++x) {
+            p->shtioffx[x] = (int)iall.size();
+            p->shticnt[x] = (int)il[x].size();
+            iall.insert(iall.end(), il[x].begin(), il[x].end());
+        }
+        if (!upload(p, p->shtitiles, iall)) return false;
+    }
     std::vector<int4> lists[8];
     for (int m = 0; m < L; ++m) {   // rows decrease with m: dealt in order
         const int nt = (L - m + 63) / 64;
@@ -919,14 +937,34 @@ void sht_inverse_internal(s2w_plan p, const double *flm_in, double *f, hipStream
     const DevGrid &g = p->grids[p->L];
     const int L = p->L, na = 2 * L - 1;
     std::vector<int> n0{0};
-    LsumArgs la = lsum_args(p, g, L, n0);
-    la.flm = flm_in;
-    la.flm_m = L;
-    la.flm_l = L;
-    la.w[0] = p->wsht;
-    la.wstride = 0;
-    la.out[0] = p->bufA;
-    {
+    if (p->shtitab) {
+        // precompute mode: theta rows from the table of d^l_m0
+        s2w::ShtTab sa{};
+        sa.L = L;
+        sa.B = p->B;
+        sa.F = flm_in;
+        sa.out = p->bufA;
+        sa.w = p->wsht;
+        sa.tab = p->shtitab;
+        sa.toff = p->shtoff;
+        sa.tiles = p->shtitiles;
+        for (int x = 0; x < 8; ++x) {
+            sa.cnt[x] = p->shticnt[x];
+            sa.off[x] = p->shtioffx[x];
+        }
+        Work wk = rec_work_n0(p, p->wsht, L, L, p->B);
+        wk.flop -= wk.flop64;
+        wk.flop64 = 0.0;
+        Prof pr_(p, "shti_tab", wk, st);
+        s2w::launch_shti_tab(sa, st);
+    } else {
+        LsumArgs la = lsum_args(p, g, L, n0);
+        la.flm = flm_in;
+        la.flm_m = L;
+        la.flm_l = L;
+        la.w[0] = p->wsht;
+        la.wstride = 0;
+        la.out[0] = p->bufA;
         Prof pr_(p, "lsum", rec_work_n0(p, p->wsht, la.L, la.mcount, p->B), st);
         s2w::launch_lsum(la, 1, p->B, st);
     }

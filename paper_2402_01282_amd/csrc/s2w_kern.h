@@ -165,6 +165,9 @@ struct ShtTab {
     int cnt[8], off[8];
 };
 void launch_sht_tab(const ShtTab &a, hipStream_t st);
+// the inverse: rows C_m(theta) = sum_l w_l f_lm d^l_m0(theta) ([B][m][theta] complex) from the
+// table of d^l_m0 (per m: [L - m][L]); F is the internal flm, tiles (m, column tile, theta tile)
+void launch_shti_tab(const ShtTab &a, hipStream_t st);
 // three BF16 parts of FP64 values (x0 + x1 + x2 = x to 2^-27 |x|): part p of element i at
 // out[p * count + i]
 void launch_split3_f64(const double *in, uint16_t *out, size_t count, hipStream_t st);

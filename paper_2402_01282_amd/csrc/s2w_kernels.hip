@@ -1983,6 +1983,115 @@ __global__ __launch_bounds__(256) void k_sht_tab(const ShtTab a)
             }
 }
 
+// The inverse SHT's theta rows from the table of d^l_m0(theta) (rows l = m..L-1, theta
+// contiguous): C_m(theta) = sum_l (w_l f_lm) d^l_m0(theta) for the 2B columns (map, re/im) of
+// each m, batched over m as k_sht_tab (the table is the [k][n] operand as it is; the
+// coefficients are staged from the internal flm, times w_l).  Output: rows [B][m][theta]
+// complex, as the l-sum writes them for the gamma and DFT stages.
+__global__ __launch_bounds__(256) void k_shti_tab(const ShtTab a)
+{
+    constexpr int BM = 128, BN = 64, BK = 16, WN = BN / 32;
+    constexpr int AS = BK + 2, BS = BN + 16;
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    __shared__ __align__(16) double As[2 * BM * AS];
+    __shared__ __align__(16) double Bs[2 * BK * BS];
+    const int xc = blockIdx.x & 7, kx = blockIdx.x >> 3;
+    if (kx >= a.cnt[xc]) return;
+    const int4 tl = a.tiles[a.off[xc] + kx];
+    const int m = tl.x, L = a.L, M = 2 * a.B, N = L, K = L - m;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int row0 = tl.y * BM, col0 = tl.z * BN;
+    const double *Bt = a.tab + a.toff[m];
+    const double2 *flm = reinterpret_cast<const double2 *>(a.F);
+    double2 ra[4], rb[2];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int f = tid + 256 * r, bm = f >> 4, kq = f & 15;
+            const int b = (row0 >> 1) + bm, k = k0 + kq;
+            double2 v = make_double2(0.0, 0.0);
+            if (2 * b < M && k < K) {
+                v = flm[((size_t)b * L + m) * L + m + k];
+                const double wl = a.w[m + k];
+                v.x *= wl;
+                v.y *= wl;
+            }
+            ra[r] = v;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int f = tid + 256 * h, bk = f >> 5, bq = f & 31;
+            const int k = k0 + bk, n = col0 + 2 * bq;
+            rb[h] = (k < K && n < N) ? *reinterpret_cast<const double2 *>(Bt + (size_t)k * L + n)
+                                     : make_double2(0.0, 0.0);
+        }
+    };
+    auto sstore = [&](int buf) {
+        double *as = As + buf * BM * AS;
+        double *bs = Bs + buf * BK * BS;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int f = tid + 256 * r, bm = f >> 4, kq = f & 15;
+            as[(2 * bm) * AS + kq] = ra[r].x;
+            as[(2 * bm + 1) * AS + kq] = ra[r].y;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int f = tid + 256 * h, bk = f >> 5, bq = f & 31;
+            *reinterpret_cast<double2 *>(bs + bk * BS + 2 * bq) = rb[h];
+        }
+    };
+    v4 acc[4][WN];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = v4{0, 0, 0, 0};
+    const int nk = (K + BK - 1) / BK;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int t = 0; t < nk; ++t) {
+        const int cur = t & 1;
+        if (t + 1 < nk) gload((t + 1) * BK);
+        const double *as = As + cur * BM * AS;
+        const double *bs = Bs + cur * BK * BS;
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            double af[4], bf[WN];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) af[i] = as[(wr * 64 + i * 16 + (lane & 15)) * AS + kk + (lane >> 4)];
+#pragma unroll
+            for (int j = 0; j < WN; ++j) bf[j] = bs[(kk + (lane >> 4)) * BS + wc * (BN / 2) + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        if (t + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gr = row0 + wr * 64 + i * 16 + (lane >> 4) + 4 * r;
+                const int gc = col0 + wc * (BN / 2) + j * 16 + (lane & 15);
+                if (gr < M && gc < N) a.out[(((size_t)(gr >> 1) * L + m) * L + gc) * 2 + (gr & 1)] = acc[i][j][r];
+            }
+}
+
+void launch_shti_tab(const ShtTab &a, hipStream_t st)
+{
+    int mx = 0;
+    for (int x = 0; x < 8; ++x) mx = std::max(mx, a.cnt[x]);
+    if (mx == 0) return;
+    hipLaunchKernelGGL(k_shti_tab, dim3(8u * (unsigned)mx), dim3(256), 0, st, a);
+}
+
 void launch_sht_tab(const ShtTab &a, hipStream_t st)
 {
     int mx = 0;

@@ -104,8 +104,9 @@ def test_mixed_precompute_synthesis(L, N, J0, B):
 
 @pytest.mark.parametrize("L,B", [(64, 8), (256, 8), (1000, 8)])
 def test_fp64_batched_precompute_sht(L, B):
-    """Batched plans in precompute mode: the forward SHT through the folded FP64 table keeps
-    FP64 accuracy (the harmonic coefficients and the analysis against the oracle at 1e-12)."""
+    """Batched plans in precompute mode: the SHTs through the FP64 tables (forward: d T_sigma
+    folded; inverse: d) keep FP64 accuracy (both transforms and the analysis against the
+    oracle)."""
     torch = _torch()
     import paper_2402_01282_amd as s2w
     print(f"[fp64 batched precompute sht L={L} B={B}]", flush=True)
@@ -116,8 +117,10 @@ def test_fp64_batched_precompute_sht(L, B):
     f = np.stack([np.real(mw.sht_inverse(flm[b], L)) for b in range(B)])
     ft = torch.from_numpy(f).cuda()
     got = pre.sht_forward(ft).cpu().numpy()
+    back = pre.sht_inverse(torch.from_numpy(flm).cuda()).cpu().numpy()
     for b in (0, B - 1):
         assert _rel(got[b], flm[b]) < 1e-12, (b, _rel(got[b], flm[b]))
+        assert _rel(back[b], f[b]) < 1e-12, (b, _rel(back[b], f[b]))
     wav, scal = pre.analysis(ft)
     views = pre.wav_views(wav)
     ow, os_ = wavelets.analysis_lm(flm[B - 1], P)
