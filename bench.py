@@ -66,6 +66,12 @@ def parse():
     ap.add_argument("--ball", action="store_true",
                     help="no headline line: the ball transform at the setting of the paper's ball benchmark "
                          "(N=1, P=L=256 by default; --L sets L=P), FP64 and mixed, one JSON line")
+    ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
+                    help="print a markdown summary of a rocprofv3 --kernel-trace --stats output directory of a "
+                         "bench run (the per-kernel statistics, and the timed steps' launches of --family)")
+    ap.add_argument("--no-gradient", action="store_true", help="skip the gradient loop (for profiled runs)")
+    ap.add_argument("--family", default="lsum_mm", help="bench kernel name whose timed launches are summarised")
+    ap.add_argument("--per-step", type=int, default=6, help="launches of --family per analysis + synthesis step")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="no benchmark: read two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; csv output) "
                          "of 'bench.py --precision mixed --steps 1 --warmup 0 --no-tune --copy-calibration' (one "
@@ -108,6 +114,39 @@ def end_to_end(kern, steps, ms_step, L, B, nwav, scal_shape, esz):
             "work_per_step": {"fp64_flop": fp64, "fp32_mfma_flop": mfma, "hbm_bytes": hbm}}
 
 
+def summarize_trace(d, args):
+    """Markdown summary of a profiled bench run (one form, made with --no-gradient): the kernel
+    statistics of rocprofv3, and the launches of one kernel family (`--family`, matched as in
+    KERNEL_NAMES) inside the timed steps, which are the family's last --steps x --per-step
+    launches of the run."""
+    import csv
+    import glob
+    stats = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)[0]
+    trace = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)[0]
+    rows = list(csv.DictReader(open(stats)))
+    print("| kernel | calls | total (ms) | average (ms) | % |")
+    print("|---|---|---|---|---|")
+    for r in rows[:24]:
+        nm = r["Name"] if len(r["Name"]) <= 90 else r["Name"][:87] + "..."
+        print(f"| `{nm}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+              f"{float(r['AverageNs']) / 1e6:.4f} | {float(r['Percentage']):.2f} |")
+    syms = dict(KERNEL_NAMES).get(args.family, [])
+    disp = []
+    for r in csv.DictReader(open(trace)):
+        nm = r["Kernel_Name"].replace(" ", "")
+        if any(sy.replace(" ", "") in nm for sy in syms):
+            disp.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    disp.sort()
+    k, S = args.per_step, args.steps
+    timed = disp[len(disp) - S * k:] if len(disp) >= S * k else []
+    if timed:
+        tot = sum(e - b for b, e, _ in timed) / 1e6
+        names = sorted({n.split("(")[0] for _, _, n in timed})
+        print(f"\n`{args.family}` in the {S} timed steps: {len(timed)} launches ({k} per step) of "
+              + ", ".join(f"`{n}`" for n in names)
+              + f"; {tot:.3f} ms in total, average {tot / len(timed):.4f} ms per launch, {tot / S:.3f} ms per step.")
+
+
 def record_traffic(fetch_dir, write_dir, args):
     """HBM bytes per launch from FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by
     what the same counter reads for the 1 GiB device copy of --copy-calibration."""
@@ -125,10 +164,22 @@ def record_traffic(fetch_dir, write_dir, args):
 
     fv, fn = load(fetch_dir)
     wv, wn = load(write_dir)
-    gib_kib = float(1 << 20)
-    # the copy is the largest device copy dispatch of the run (1 GiB read, 1 GiB written)
+
+    def step_window(val, name):
+        # a run made with --steps 1 --warmup 0 --no-gradient in precompute mode: its round trip
+        # starts two dispatches (the FP64 DFT and gamma stage of the forward SHT) before the
+        # first k_sht_tab; plan creation, tuning and the input maps come before it
+        ids = [int(k) for k in val if "k_sht_tab" in name[k]]
+        if not ids:
+            return val
+        start = min(ids) - 2
+        return {k: v for k, v in val.items() if int(k) >= start}
+
     cf = max(v for k, v in fv.items() if "copyBuffer" in fn[k])
     cw = max(v for k, v in wv.items() if "copyBuffer" in wn[k])
+    fv, wv = step_window(fv, fn), step_window(wv, wn)
+    gib_kib = float(1 << 20)
+    # the copy is the largest device copy dispatch of the run (1 GiB read, 1 GiB written)
     ff, fw = gib_kib / cf, gib_kib / cw
     kern = {}
     for bname, syms in KERNEL_NAMES:
@@ -149,8 +200,8 @@ def record_traffic(fetch_dir, write_dir, args):
                                 "fetch_scale": ff, "write_scale": fw},
            "command": ("cd /tmp && rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <dir> -o run --output-format csv "
                        "-- python3 bench.py --precision mixed --precompute --steps 1 --warmup 0 --no-cpu-baseline "
-                       "--no-kernel-timing --copy-calibration; per kernel the average over every dispatch of the "
-                       "run (plan tuning, the round trip and the gradient step: same shapes)"),
+                       "--no-kernel-timing --no-gradient --copy-calibration; per kernel the average over the "
+                       "dispatches of the round trip (from the forward SHT's first stage on)"),
            "kernels": kern}
     with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
         json.dump(rec, fh, indent=1)
@@ -284,13 +335,15 @@ def run_form(args, precision, B, precompute=None):
         plan.analysis(f, wav, scal)
         plan.analysis_adjoint(wav, gscal, gf)
 
-    grad_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
+    dtg = None
+    if not args.no_gradient:
         grad_step()
-    torch.cuda.synchronize()
-    dtg = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            grad_step()
+        torch.cuda.synchronize()
+        dtg = time.perf_counter() - t0
     workload = (f"sphere directional wavelets analysis+synthesis, "
                 f"{'mixed FP32/FP64 batched' if mixed else 'FP64'}, L={L}, N={N}, lambda={lam:g}, J0={J0}, batch={B}"
                 + (", precompute mode" if precompute else ""))
@@ -298,8 +351,9 @@ def run_form(args, precision, B, precompute=None):
            "dtype": "f32+f64" if mixed else "f64", "workload": workload, "batch": B,
            "coefficients_per_s": maps_per_s * (plan.wav_offset[-1] // B), "round_trip_rel_err": err,
            "plan_create_s": t_plan, "plan_device_gib": plan_bytes / 2 ** 30, "precompute": bool(precompute),
-           "gradient": {"maps_per_s": B * args.steps / dtg, "ms_per_step": 1e3 * dtg / args.steps,
-                        "what": "analysis + transpose of the analysis (gradient of sum_j sum (W^j)^2)"}}
+           "gradient": None if dtg is None else
+           {"maps_per_s": B * args.steps / dtg, "ms_per_step": 1e3 * dtg / args.steps,
+            "what": "analysis + transpose of the analysis (gradient of sum_j sum (W^j)^2)"}}
     if kern:
         tot = sum(v[0] for v in kern.values())
         name, (ms, cnt, flop, flop64, dense) = max(kern.items(), key=lambda kv: kv[1][0])
@@ -406,6 +460,9 @@ def main():
         return
     if args.record_traffic:
         record_traffic(args.record_traffic[0], args.record_traffic[1], args)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args)
         return
     if args.sweep:
         if args.gpus != 1:

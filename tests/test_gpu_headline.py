@@ -1,8 +1,8 @@
 """Parity at the headline configuration L=1024, N=8, lambda=2, J0=0 (eleven wavelet
 scales, L_j = 2, 4, ..., 512, 1024, 1024), element by element against the oracle.
 
-* Mixed form, batch 64 (the measured workload) of independently seeded Gaussian
-  fields: every scale and the scaling coefficients of maps 0 and 63 against the
+* Mixed form, batch 64 (the measured workload, tuned, with and without precompute
+  mode) of independently seeded Gaussian fields: every scale and the scaling coefficients of maps 0 and 63 against the
   oracle's analysis; the synthesis of the oracle's coefficients of maps 0 and 63 (the
   other 62 maps zero, so every column group of the theta contraction is full) against
   the input maps, which the exact transform reconstructs; round trip of every map.
@@ -82,18 +82,22 @@ def _check_synthesis(plan, wr_by_map, sr_by_map, f, tol_l2, tol_el):
         assert torch.count_nonzero(g[others]).item() == 0
 
 
-def test_mixed_headline_B64_all_scales(oracle_plan):
+@pytest.mark.parametrize("precompute", [False, True])
+def test_mixed_headline_B64_all_scales(oracle_plan, precompute):
+    """The measured plans: tuned, with and without precompute mode (folded SHT and
+    synthesis tables)."""
     torch = _torch()
     import paper_2402_01282_amd as s2w
     B = 64
-    print("[headline mixed L=1024 N=8 B=64]", flush=True)
+    print(f"[headline mixed L=1024 N=8 B=64 precompute={precompute}]", flush=True)
     flm = [S.sphere_flm(L, S.stream_key(4, b)) for b in range(B)]
     p1 = s2w.Plan(L, N, LAM, J0, batch=1, device=0)
     f = torch.empty((B, L, 2 * L - 1), dtype=torch.float64, device="cuda")
     for b in range(B):
         f[b].copy_(p1.sht_inverse(torch.from_numpy(flm[b][None].copy()).cuda())[0])
     del p1
-    plan = s2w.Plan(L, N, LAM, J0, batch=B, precision=s2w.S2W_MIXED, device=0)
+    flags = s2w.S2W_PLAN_TUNE | (s2w.S2W_PLAN_PRECOMPUTE if precompute else 0)
+    plan = s2w.Plan(L, N, LAM, J0, batch=B, precision=s2w.S2W_MIXED, device=0, flags=flags)
     wav, scal = plan.analysis(f)
     f2 = plan.synthesis(wav, scal)
     errs = [(torch.linalg.norm(f2[b] - f[b]) / torch.linalg.norm(f[b])).item() for b in range(B)]
