@@ -141,3 +141,33 @@ def test_spin_wavelets_mixed_L512():
     P = wavelets.Plan(L, N, 2.0, 0)
     _, fs = _maps(L, s, B, 93)
     _check_wavelets(plan, P, fs, s, B, 1e-6, 2e-5, "mixed L=512")
+
+
+@pytest.mark.parametrize("L,N,s,B,flags", [(64, 3, 1, 8, "precompute"), (128, 4, -2, 4, "precompute+tune"),
+                                           (96, 2, 2, 8, "tune+persistent")])
+def test_spin_plan_flags(L, N, s, B, flags):
+    """Spin plans with precompute tables, tuning and the persistent list: the same results
+    as the plain spin plan to the mixed bar, and against the oracle for the last map."""
+    torch = _torch()
+    import paper_2402_01282_amd as s2w
+    print(f"[spin flags {flags} L={L} N={N} s={s} B={B}]", flush=True)
+    fl = 0
+    if "precompute" in flags:
+        fl |= s2w.S2W_PLAN_PRECOMPUTE
+    if "tune" in flags:
+        fl |= s2w.S2W_PLAN_TUNE
+    if "persistent" in flags:
+        fl |= s2w.S2W_PLAN_PERSISTENT
+    plan = s2w.SpinPlan(L, N, s, 2.0, 0, batch=B, precision=s2w.S2W_MIXED, device=0, flags=fl)
+    ref = s2w.SpinPlan(L, N, s, 2.0, 0, batch=B, precision=s2w.S2W_MIXED, device=0)
+    _, fs = _maps(L, s, B, 94)
+    f = torch.from_numpy(_planar(fs)).cuda()
+    w1, s1 = plan.analysis(f)
+    w1, s1 = w1.clone(), s1.clone()
+    w2, s2 = ref.analysis(f)
+    assert rel(w1.double().cpu().numpy(), w2.double().cpu().numpy()) < 1e-6
+    g1 = plan.synthesis(w1, s1).clone()
+    g2 = ref.synthesis(w1, s1)
+    assert rel(g1.cpu().numpy(), g2.cpu().numpy()) < 1e-6
+    P = wavelets.Plan(L, N, 2.0, 0)
+    _check_wavelets(plan, P, fs, s, B, 1e-6, 2e-5, f"mixed {flags}")
