@@ -1897,6 +1897,7 @@ static void synthesis_to_fhat(s2w_plan p, const void *wav_, const double *scal, 
     const int B = p->B;
     const int npar = (p->N - 1) & 1;
     const bool mixed = p->prec == S2W_MIXED;
+    std::vector<int> p32(p->S.s.size(), 0);   // scales whose P the folded-table product wrote in FP32
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
         if (!mixed) continue;
         const auto &grp = p->groups[gi];
@@ -1953,8 +1954,9 @@ static void synthesis_to_fhat(s2w_plan p, const void *wav_, const double *scal, 
             for (int i = 0; i < nn; ++i) tb.nval[i] = si.n[i];
             for (int s = 0; s < NS; ++s) {
                 tb.h[s] = A32 + s * cstride;
-                tb.out[s] = p->P[grp.scales[s]];
+                tb.out[s] = reinterpret_cast<float *>(p->P[grp.scales[s]]);
                 tb.w[s] = p->wpsi[grp.scales[s]];
+                p32[grp.scales[s]] = 1;
             }
             tb.wstride = Lk;
             tb.tab = tt.tab;
@@ -2033,6 +2035,7 @@ static void synthesis_to_fhat(s2w_plan p, const void *wav_, const double *scal, 
     for (size_t k = 0; k < p->S.s.size(); ++k) {
         auto &t = ca.t[ca.nterms++];
         t.P = p->P[k];
+        t.f32 = p32[k];
         t.L = p->S.s[k].L;
         t.nn = (int)p->S.s[k].n.size();
         t.phr = p->F.xi_imag ? 0.0 : 1.0;

@@ -99,8 +99,9 @@ struct GammaArgs {
 };
 
 struct CombineTerm {
-    const double *P;             // [B][L][nn][L] complex, read at l >= m only
+    const void *P;               // [B][L][nn][L] complex, read at l >= m only
     int L, nn;
+    int f32;                     // P holds FP32 values (else FP64)
     double phr, phi;
 };
 
@@ -143,7 +144,7 @@ struct TsumTab {
     int L, mcount, nn, B, NS, npar, M0, M1;
     int nval[MAX_NN];
     const float *h[MAX_NS];      // sigma-grouped rows before the theta quadrature, FP32
-    double *out[MAX_NS];         // [B][mcount][nn][L] complex FP64
+    float *out[MAX_NS];          // [B][mcount][nn][L] complex FP32 (the products accumulate in FP32)
     const double *w[MAX_NS];     // filter weights [nn][wstride]
     int wstride;
     const uint16_t *tab;         // per (n index, m): three BF16 parts, each [L - l0][L]

@@ -1504,7 +1504,8 @@ __global__ __launch_bounds__(256) void k_gamma_r2c(const GammaArgs a)
 }
 
 // -------------------------------------------------------------- combine ----
-// fhat[b][m][l] = sum_terms ph_t * sum_ni P_t[b][m][ni][l]   (FP64, fixed order)
+// fhat[b][m][l] = sum_terms ph_t * sum_ni P_t[b][m][ni][l]   (FP64, fixed order; a term's P
+// may hold FP32 values, widened as they are read)
 __global__ __launch_bounds__(256) void k_combine(const CombineArgs a)
 {
     const int l = blockIdx.x * 256 + threadIdx.x;
@@ -1517,9 +1518,16 @@ __global__ __launch_bounds__(256) void k_combine(const CombineArgs a)
             if (m >= c.L || l >= c.L) continue;
             double sr = 0.0, si = 0.0;
             for (int ni = 0; ni < c.nn; ++ni) {
-                const double *p = c.P + ((((size_t)b * c.L + m) * c.nn + ni) * c.L + l) * 2;
-                sr += p[0];
-                si += p[1];
+                const size_t e = ((((size_t)b * c.L + m) * c.nn + ni) * c.L + l) * 2;
+                if (c.f32) {
+                    const float *p = static_cast<const float *>(c.P) + e;
+                    sr += (double)p[0];
+                    si += (double)p[1];
+                } else {
+                    const double *p = static_cast<const double *>(c.P) + e;
+                    sr += p[0];
+                    si += p[1];
+                }
             }
             re += c.phr * sr - c.phi * si;
             im += c.phr * si + c.phi * sr;

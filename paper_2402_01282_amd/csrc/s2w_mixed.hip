@@ -1703,8 +1703,8 @@ __global__ __launch_bounds__(256, 2) void k_tsum_tab(const TsumTab a)
                 if (cg >= ncols) continue;
                 const int s = cg / (2 * B), b = (cg - s * 2 * B) >> 1;
                 const double wt = a.w[s][(size_t)ni * a.wstride + l];
-                double2 *o = reinterpret_cast<double2 *>(a.out[s]) + (((size_t)b * a.mcount + m) * a.nn + ni) * L + l;
-                *o = make_double2((double)acc[i][j][2 * h] * wt, (double)acc[i][j][2 * h + 1] * wt);
+                float2 *o = reinterpret_cast<float2 *>(a.out[s]) + (((size_t)b * a.mcount + m) * a.nn + ni) * L + l;
+                *o = make_float2((float)((double)acc[i][j][2 * h] * wt), (float)((double)acc[i][j][2 * h + 1] * wt));
             }
         }
     // m <= l < l0: zero (d^l_mn vanishes below max(|m|, |n|)); the first degree tile's blocks
@@ -1714,7 +1714,7 @@ __global__ __launch_bounds__(256, 2) void k_tsum_tab(const TsumTab a)
             const int cg = row0 + 2 * pr;
             if (cg >= ncols) continue;
             const int s = cg / (2 * B), b = (cg - s * 2 * B) >> 1;
-            reinterpret_cast<double2 *>(a.out[s])[(((size_t)b * a.mcount + m) * a.nn + ni) * L + l] = make_double2(0.0, 0.0);
+            reinterpret_cast<float2 *>(a.out[s])[(((size_t)b * a.mcount + m) * a.nn + ni) * L + l] = make_float2(0.f, 0.f);
         }
     }
 }
