@@ -2218,9 +2218,10 @@ void launch_gamma_r2c(const GammaArgs &a, hipStream_t st, bool f32)
 {
     const bool one = a.nn == 1 && a.ng == 1;
     if (f32) {
-        dim3 grid((a.M + 15) / 16, (a.L + 31) / 32, a.B);
-        if (one) hipLaunchKernelGGL((k_gamma_r2c<float, 16, 32, 1, 1>), grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((k_gamma_r2c<float, 16, 32, GAMMA_MAXN, GAMMA_MAXG>), grid, dim3(256), 0, st, a);
+        // 32 x 32 tiles: 256-byte reads of the rows over m (218 VGPRs, two blocks per CU)
+        dim3 grid((a.M + 31) / 32, (a.L + 31) / 32, a.B);
+        if (one) hipLaunchKernelGGL((k_gamma_r2c<float, 32, 32, 1, 1>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_gamma_r2c<float, 32, 32, GAMMA_MAXN, GAMMA_MAXG>), grid, dim3(256), 0, st, a);
     } else {
         dim3 grid((a.M + 15) / 16, (a.L + 15) / 16, a.B);
         if (one) hipLaunchKernelGGL((k_gamma_r2c<double, 16, 16, 1, 1>), grid, dim3(256), 0, st, a);
