@@ -72,6 +72,11 @@ def parse():
     ap.add_argument("--no-gradient", action="store_true", help="skip the gradient loop (for profiled runs)")
     ap.add_argument("--family", default="lsum_mm", help="bench kernel name whose timed launches are summarised")
     ap.add_argument("--per-step", type=int, default=6, help="launches of --family per analysis + synthesis step")
+    ap.add_argument("--summarize-counters", metavar="PMC_DIR",
+                    help="print a markdown table of a rocprofv3 --pmc output directory of a one-step precompute "
+                         "run with the SQ counters SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_INST_ANY "
+                         "SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_MFMA SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT, "
+                         "summed per bench kernel name over the round trip's dispatches")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="no benchmark: read two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; csv output) "
                          "of 'bench.py --precision mixed --steps 1 --warmup 0 --no-tune --copy-calibration' (one "
@@ -145,6 +150,44 @@ def summarize_trace(d, args):
         print(f"\n`{args.family}` in the {S} timed steps: {len(timed)} launches ({k} per step) of "
               + ", ".join(f"`{n}`" for n in names)
               + f"; {tot:.3f} ms in total, average {tot / len(timed):.4f} ms per launch, {tot / S:.3f} ms per step.")
+
+
+def summarize_counters(d):
+    """Markdown table of shader counters per bench kernel name, summed over the dispatches from
+    the round trip's first stage on (two dispatches before the first k_sht_tab)."""
+    import collections
+    import csv
+    import glob
+    path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+    val = collections.defaultdict(lambda: collections.defaultdict(float))
+    name = {}
+    for r in csv.DictReader(open(path)):
+        i = int(r["Dispatch_Id"])
+        val[i][r["Counter_Name"]] += float(r["Counter_Value"])
+        name[i] = r["Kernel_Name"].replace(" ", "")
+    ids = [i for i in name if "k_sht_tab" in name[i]]
+    start = min(ids) - 2 if ids else 0
+    fams = KERNEL_NAMES + [("sht_tab", ["k_sht_tab("]), ("shti_tab", ["k_shti_tab("])]
+    fam = collections.defaultdict(lambda: collections.defaultdict(float))
+    cnt = collections.Counter()
+    for i, v in val.items():
+        if i < start:
+            continue
+        for bname, syms in fams:
+            if any(sy.replace(" ", "") in name[i] for sy in syms):
+                for k, x in v.items():
+                    fam[bname][k] += x
+                cnt[bname] += 1
+                break
+    print("| kernel | dispatches | matrix cores busy | waves waiting on a counter | VALU per MFMA instruction "
+          "| LDS bank-conflict cycles per LDS instruction |")
+    print("|---|---|---|---|---|---|")
+    for b, v in sorted(fam.items(), key=lambda kv: -kv[1]["SQ_BUSY_CYCLES"]):
+        busy = v["SQ_VALU_MFMA_BUSY_CYCLES"] / (v["SQ_BUSY_CYCLES"] * 32) if v["SQ_BUSY_CYCLES"] else 0.0
+        wait = v["SQ_WAIT_INST_ANY"] / v["SQ_WAVE_CYCLES"] if v["SQ_WAVE_CYCLES"] else 0.0
+        vpm = v["SQ_INSTS_VALU"] / v["SQ_INSTS_MFMA"] if v["SQ_INSTS_MFMA"] else float("nan")
+        lds = v["SQ_LDS_BANK_CONFLICT"] / v["SQ_INSTS_LDS"] if v["SQ_INSTS_LDS"] else float("nan")
+        print(f"| {b} | {cnt[b]} | {busy:.3f} | {wait:.3f} | {vpm:.1f} | {lds:.2f} |")
 
 
 def record_traffic(fetch_dir, write_dir, args):
@@ -463,6 +506,9 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters)
         return
     if args.sweep:
         if args.gpus != 1:
